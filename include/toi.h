@@ -1,0 +1,164 @@
+/*
+ * toi.h - C ABI of the MI355X (gfx950) TOI snapshot imager and FITrig stage.
+ *
+ * Method: FIP-TOI, "Transient-Oriented Radio Astronomical Imager" (arXiv
+ * 2512.06254).  Each call below names the passage of the paper whose
+ * operation it computes.  All arrays are caller-owned DEVICE pointers
+ * (HIP/PyTorch allocations on the context's device) unless stated otherwise;
+ * the context owns only its workspace.  Every call is asynchronous on the
+ * context's HIP stream, except toi_plan_info (which synchronises) and
+ * toi_create/toi_destroy.  No exception crosses this boundary: failures are
+ * returned as toi_status and described by toi_last_error().
+ *
+ * Data-dependent conditions never abort a call: they produce a defined output
+ * (an all-zero image) and set bits of a device status word that
+ * toi_plan_info() returns (TOI_STATUS_* below).
+ *
+ * Layouts follow the Measurement Set columns the paper reads (Section 3.5):
+ *   uvw    f64  [n_row][3]               baseline (ant2 - ant1) in metres
+ *   vis    c64  [n_row][n_chan][n_corr]  interleaved (re, im) float pairs
+ *   flag   u8   [n_row][n_chan][n_corr]  nonzero = flagged        (nullable)
+ *   weight f32  [n_row][n_chan][n_corr]  WEIGHT_SPECTRUM           (nullable)
+ *   freq   f64  [n_chan]                 CHAN_FREQ in Hz
+ * Images are f32 [N][N], row j2 (m / t2 axis) major, column j1 (l / t1 axis)
+ * fastest; pixel (j1, j2) has l = -cell (j1 - N/2), m = cell (j2 - N/2)
+ * (Section 3.3 with 0-based indices).
+ */
+#ifndef TOI_H
+#define TOI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct toi_ctx toi_ctx;
+
+typedef enum {
+    TOI_OK = 0,
+    TOI_EINVAL = 1,        /* bad argument: NULL pointer, size out of range */
+    TOI_ENOMEM = 2,        /* workspace allocation failed (toi_create only) */
+    TOI_EDEVICE = 3,       /* a HIP runtime call failed */
+    TOI_EUNSUPPORTED = 4   /* a parameter combination this build does not implement */
+} toi_status;
+
+/* device status word bits (toi_plan_info) */
+#define TOI_STATUS_NO_SAMPLES 1u   /* every sample flagged or zero-weight: zero image      */
+#define TOI_STATUS_DEGENERATE 2u   /* |V33| < 1e-6: transformed plane edge-on, zero image   */
+#define TOI_STATUS_PLANES     4u   /* automatic N_slab * K exceeds max_planes: zero image   */
+
+typedef struct {
+    int32_t  n_pix;        /* N, image side: power of two, 32 .. 8192                       */
+    double   cell_deg;     /* cell size (degrees)                                           */
+    int32_t  mode;         /* 2: coplanar imaging (Section 3.2); 3: near-coplanar (3.4)      */
+    int32_t  n_slab;       /* N_slab; 0 = eq. (27) with alpha_target                         */
+    int32_t  cheb_k;       /* K; 0 = smallest of {8,16,24,32} meeting cheb_gamma (3.4)       */
+    double   alpha_target; /* eq. (27), default 10                                           */
+    double   cheb_gamma;   /* Chebyshev sampled-error threshold, default 1e-2                */
+    int32_t  max_planes;   /* workspace capacity for N_slab*K (0 = n_slab*cheb_k, or 32)     */
+    int32_t  support;      /* gridding kernel support W: 8 only                              */
+    uint32_t corr_mask;    /* correlations averaged (bit k = corr k); 0 = parallel hands     */
+    int32_t  tile;         /* FITrig tile side in pixels, default 32                         */
+    int32_t  n_row_max;    /* largest n_row of any snapshot passed to this context           */
+    int32_t  n_chan;
+    int32_t  n_corr;       /* 1, 2 or 4                                                      */
+    int32_t  n_ant;        /* antennas (gains length), may be 0 when no gains are used       */
+} toi_params;
+
+typedef struct {
+    const double*  uvw;
+    const void*    vis;
+    const uint8_t* flag;    /* NULL: nothing flagged                                       */
+    const float*   weight;  /* NULL: unit weights                                          */
+    const double*  freq;
+    const int32_t* ant1;    /* i32[n_row]; required when gains != NULL                     */
+    const int32_t* ant2;
+    const void*    gains;   /* c64[n_ant] per-antenna factors g; each row's samples are     */
+                            /* multiplied by g[ant1] conj(g[ant2]); NULL = no gains         */
+    int32_t        n_row;   /* 0 <= n_row <= n_row_max                                      */
+} toi_snapshot;
+
+/* Fill *p with defaults for an N x N image of cell_deg cells (host only). */
+toi_status toi_params_default(toi_params* p, int32_t n_pix, double cell_deg,
+                              int32_t n_row_max, int32_t n_chan, int32_t n_corr);
+
+/* Allocate the context and its whole workspace on the current HIP device
+ * (the only allocating call; Section 4.2's rule of no allocation in the loop).
+ * hip_stream: a hipStream_t (NULL = the null stream).  On failure *out = NULL. */
+toi_status toi_create(const toi_params* p, void* hip_stream, toi_ctx** out);
+
+/* Free the workspace; ctx may be NULL.  Synchronises the context's stream. */
+toi_status toi_destroy(toi_ctx* ctx);
+
+/* Change the stream subsequent calls are ordered on. */
+toi_status toi_set_stream(toi_ctx* ctx, void* hip_stream);
+
+/* Sections 3.1, 3.4, 3.5: select and weight samples (flags -> zero weight,
+ * weighted average of the parallel hands, each baseline-channel pair one
+ * sample, uvw scaled to wavelengths per channel), estimate the snapshot basis
+ * V by PCA of the centred baselines (omega of eq. 11, xi/eta of Section 3.3),
+ * choose N_slab and K (eqs. 26-27) unless forced, and grid every Chebyshev
+ * moment M_{p,k} of Section 3.4 (one plane in 2-D mode) with an ES kernel of
+ * support 8 on a 2N x 2N grid.  The snapshot's arrays must stay valid until
+ * the stream reaches the end of this call's work.  The planes are kept in the
+ * context for toi_image / toi_degrid. */
+toi_status toi_grid(toi_ctx* ctx, const toi_snapshot* snap);
+
+/* Sections 3.2-3.4: inverse 2-D FFT of every plane, grid correction, the
+ * Chebyshev/slab combination sum_p e^{i2pi r3p t3} sum_k c_k(2pi dr3 t3) M_{p,k}
+ * scaled by 1/(omega W) (W = sum of sample weights = N_vis for unit weights),
+ * real part, then the re-projection of Section 3.3 (the reduced SIN mapping
+ * composed with the in-plane 2x2 block of V) with bilinear interpolation onto
+ * the standard grid.  image_out: f32[N][N] (required); tplane_out: f32[N][N]
+ * transformed-plane image before re-projection (nullable). */
+toi_status toi_image(toi_ctx* ctx, float* image_out, float* tplane_out);
+
+/* Adjoint of toi_grid + toi_image for the snapshot last passed to toi_grid
+ * (same arrays): given grad_image = dL/dI (f32[N][N]) returns
+ * grad_vis = dL/dRe(vis) + i dL/dIm(vis) (c64 like vis; nullable) and
+ * grad_gains (c64[n_ant]; nullable, requires gains).  Reads the snapshot's
+ * flags/weights/gains again; overwrites both outputs. */
+toi_status toi_degrid(toi_ctx* ctx, const float* grad_image, const toi_snapshot* snap,
+                      void* grad_vis, void* grad_gains);
+
+/* FITrig tLISI (Sections 2, 4.5): from the three youngest images, the
+ * difference images D_{t-1} = I_{t-1} - I_{t-2} and D_t = I_t - I_{t-1} are
+ * compared tile by tile; one value in [0, 1] per tile (1 = identical).
+ * tlisi_out: f32[N/tile][N/tile].  The index used is the SSIM-form stand-in
+ * documented with the implementation (the FITrig formula is not in the
+ * paper). */
+toi_status fitrig_tlisi(toi_ctx* ctx, const float* img_tm2, const float* img_tm1,
+                        const float* img_t, float* tlisi_out);
+
+/* FITrig detection (Section 2) over a sliding window of the 16 newest tLISI
+ * maps: per tile, the harmonic-summed DFT power of the window and the
+ * non-periodic score sum(1 - tLISI), z-scores over tiles, thresholds 5 and 4,
+ * 8-connected components -> boxes (t, x0, y0, x1, y1) in pixels, sorted by
+ * (y0, x0, y1, x1).  window: f32[16][N/tile][N/tile], oldest first.
+ * boxes_out: i32[max_boxes][5]; n_boxes_out: device i32 (the number found,
+ * possibly > max_boxes, in which case only max_boxes are written). */
+toi_status fitrig_detect(toi_ctx* ctx, const float* window, int32_t t,
+                         int32_t* boxes_out, int32_t max_boxes, int32_t* n_boxes_out);
+
+/* Several snapshots in one call (uneven sample counts allowed): for each i,
+ * toi_grid(snaps[i]) + toi_image(images_out + i*N*N), and for i >= 2 the
+ * tLISI map of (i-2, i-1, i) into tlisi_out + (i-2)*(N/tile)^2 (nullable).
+ * snaps is a HOST array of n descriptors.  Executed as a captured HIP graph
+ * replayed per snapshot. */
+toi_status toi_image_batch(toi_ctx* ctx, const toi_snapshot* snaps, int32_t n,
+                           float* images_out, float* tlisi_out);
+
+/* Synchronise and report the last gridded snapshot's plan (host outputs, each
+ * nullable): V row-major, omega, W (sum of weights), N_slab, K, and the status
+ * word.  Diagnostics only: the imaging loop never calls it. */
+toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* wsum,
+                         int32_t* n_slab, int32_t* cheb_k, uint32_t* status);
+
+/* Message for the last failing call on ctx (or a global one if ctx is NULL). */
+const char* toi_last_error(const toi_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOI_H */

@@ -1,0 +1,309 @@
+// Host runtime of libtoi: context creation (the only allocating call), argument
+// validation, the host-built tables and the C ABI entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "toi_internal.h"
+
+namespace {
+std::mutex g_err_mu;
+std::string g_err;   // message of the last failure without a context
+
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+}  // namespace
+
+namespace toi {
+
+toi_status fail(toi_ctx* ctx, toi_status st, const std::string& msg) {
+    if (ctx) {
+        ctx->err = msg;
+    } else {
+        std::lock_guard<std::mutex> lk(g_err_mu);
+        g_err = msg;
+    }
+    return st;
+}
+
+toi_status hip_check(toi_ctx* ctx, hipError_t e, const char* what) {
+    if (e == hipSuccess) return TOI_OK;
+    return fail(ctx, TOI_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                x[i] = z;
+                w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+                break;
+            }
+            x[i] = z;
+            w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        }
+    }
+}
+
+// Grid correction of the ES kernel: psi(a) = (W/2) int_{-1}^{1} phi(z) cos(pi W z a / M) dz,
+// a = j - N/2; stored as (-1)^a / psi(a) so that one real factor per axis also
+// undoes the half-grid shift of the FFT origin.
+void es_correction_table(int N, int M, double* out) {
+    std::vector<double> z, w;
+    gauss_legendre(128, z, w);
+    const double beta = kEsBetaPerW * kSupport;
+    for (int j = 0; j < N; ++j) {
+        const double a = j - N / 2;
+        double s = 0.0;
+        for (size_t q = 0; q < z.size(); ++q) {
+            const double phi = std::exp(beta * (std::sqrt(1.0 - z[q] * z[q]) - 1.0));
+            s += w[q] * phi * std::cos(kPi * kSupport * z[q] * a / M);
+        }
+        const double psi = 0.5 * kSupport * s;
+        const double sign = ((j - N / 2) % 2 == 0) ? 1.0 : -1.0;
+        out[j] = sign / psi;
+    }
+}
+
+}  // namespace toi
+
+using namespace toi;
+
+extern "C" {
+
+toi_status toi_params_default(toi_params* p, int32_t n_pix, double cell_deg, int32_t n_row_max,
+                              int32_t n_chan, int32_t n_corr) {
+    if (!p) return fail(nullptr, TOI_EINVAL, "toi_params_default: p is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->n_pix = n_pix;
+    p->cell_deg = cell_deg;
+    p->mode = 3;
+    p->n_slab = 0;
+    p->cheb_k = 0;
+    p->alpha_target = 10.0;
+    p->cheb_gamma = 1e-2;
+    p->max_planes = 0;
+    p->support = kSupport;
+    p->corr_mask = 0;
+    p->tile = 32;
+    p->n_row_max = n_row_max;
+    p->n_chan = n_chan;
+    p->n_corr = n_corr;
+    p->n_ant = 0;
+    return TOI_OK;
+}
+
+static uint32_t default_mask(int n_corr) {
+    return n_corr == 4 ? 0x9u : (n_corr == 2 ? 0x3u : 0x1u);
+}
+
+toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
+    if (!out) return fail(nullptr, TOI_EINVAL, "toi_create: out is NULL");
+    *out = nullptr;
+    if (!pin) return fail(nullptr, TOI_EINVAL, "toi_create: params is NULL");
+    toi_params p = *pin;
+    if (!is_pow2(p.n_pix) || p.n_pix < 32 || p.n_pix > 8192)
+        return fail(nullptr, TOI_EINVAL, "toi_create: n_pix must be a power of two in [32, 8192]");
+    if (!(p.cell_deg > 0.0) || p.cell_deg * p.n_pix >= 180.0)
+        return fail(nullptr, TOI_EINVAL, "toi_create: cell_deg must be > 0 and the field < 180 deg");
+    if (p.mode != 2 && p.mode != 3) return fail(nullptr, TOI_EINVAL, "toi_create: mode must be 2 or 3");
+    if (p.support != kSupport)
+        return fail(nullptr, TOI_EUNSUPPORTED, "toi_create: only gridding support 8 is implemented");
+    if (p.n_corr != 1 && p.n_corr != 2 && p.n_corr != 4)
+        return fail(nullptr, TOI_EINVAL, "toi_create: n_corr must be 1, 2 or 4");
+    if (p.n_chan <= 0 || p.n_row_max < 0 || p.n_ant < 0)
+        return fail(nullptr, TOI_EINVAL, "toi_create: n_chan must be > 0, n_row_max and n_ant >= 0");
+    if (p.corr_mask == 0) p.corr_mask = default_mask(p.n_corr);
+    if (p.corr_mask >> p.n_corr)
+        return fail(nullptr, TOI_EINVAL, "toi_create: corr_mask selects a correlation >= n_corr");
+    if (p.tile <= 0 || p.tile > p.n_pix || (p.n_pix % p.tile))
+        return fail(nullptr, TOI_EINVAL, "toi_create: tile must divide n_pix");
+    if (p.n_slab < 0 || p.cheb_k < 0 || p.cheb_k > 32 || p.max_planes < 0)
+        return fail(nullptr, TOI_EINVAL, "toi_create: n_slab, cheb_k in [0, 32], max_planes must be >= 0");
+    if (!(p.alpha_target > 0.0) || !(p.cheb_gamma > 0.0))
+        return fail(nullptr, TOI_EINVAL, "toi_create: alpha_target and cheb_gamma must be > 0");
+
+    toi_ctx* c = new toi_ctx();
+    c->p = p;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->N = p.n_pix;
+    c->M = 2 * p.n_pix;
+    c->T = p.n_pix / p.tile;
+    if (p.mode == 2) {
+        c->P_cap = 1;
+        c->forced_K = 1;
+    } else {
+        const int fk = p.cheb_k;
+        c->forced_K = fk;
+        int cap = p.max_planes;
+        if (cap == 0) cap = (p.n_slab > 0 && fk > 0) ? p.n_slab * fk : 32;
+        if (p.n_slab > 0 && fk > 0 && p.n_slab * fk > cap)
+            return delete c, fail(nullptr, TOI_EINVAL, "toi_create: n_slab * cheb_k exceeds max_planes");
+        c->P_cap = cap;
+    }
+    const int k = c->forced_K;
+    c->kmax = (k == 1) ? 1 : (k > 0 && k <= 4) ? 4 : (k > 0 && k <= 8) ? 8 : (k > 0 && k <= 16) ? 16 : 32;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, TOI_EDEVICE, "toi_create: no HIP device");
+    }
+
+    const size_t N = c->N, M = c->M, P = c->P_cap, T = c->T;
+    struct Alloc { void** ptr; size_t bytes; };
+    Alloc allocs[] = {
+        {(void**)&c->grid, P * M * M * sizeof(float2)},
+        {(void**)&c->hbuf, P * N * M * sizeof(float2)},
+        {(void**)&c->tplane_t, N * N * sizeof(float)},
+        {(void**)&c->plan, sizeof(DevPlan)},
+        {(void**)&c->rows, std::max<size_t>(1, p.n_row_max) * sizeof(RowStat)},
+        {(void**)&c->corr, N * sizeof(float)},
+        {(void**)&c->twiddle, M * sizeof(float2)},
+        {(void**)&c->tiles, T * T * sizeof(TileStat)},
+        {(void**)&c->scratch_d, 64 * sizeof(double)},
+        {(void**)&c->scratch_i, 64 * sizeof(int32_t)},
+        {(void**)&c->det_scores, 2 * T * T * sizeof(float)},
+        {(void**)&c->det_labels, T * T * sizeof(int32_t)},
+    };
+    for (auto& a : allocs) {
+        if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
+            for (auto& b : allocs)
+                if (*b.ptr) (void)hipFree(*b.ptr);
+            delete c;
+            return fail(nullptr, TOI_ENOMEM, "toi_create: workspace allocation failed");
+        }
+    }
+    // host-built tables: ES grid correction and FFT twiddles, computed in FP64
+    std::vector<double> corr_d(N);
+    es_correction_table((int)N, (int)M, corr_d.data());
+    std::vector<float> corr_f(N);
+    for (size_t j = 0; j < N; ++j) corr_f[j] = (float)corr_d[j];
+    std::vector<float2> tw(M);
+    for (size_t n = 0; n < M; ++n) {
+        const double a = 2.0 * kPi * (double)n / (double)M;
+        tw[n] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    DevPlan zero{};
+    hipError_t e = hipMemcpy(c->corr, corr_f.data(), N * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->twiddle, tw.data(), M * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->plan, &zero, sizeof(DevPlan), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        toi_destroy(c);
+        return fail(nullptr, TOI_EDEVICE, std::string("toi_create: table upload: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return TOI_OK;
+}
+
+toi_status toi_destroy(toi_ctx* c) {
+    if (!c) return TOI_OK;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
+    if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
+    void* ptrs[] = {c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
+                    c->scratch_d, c->scratch_i, c->det_scores, c->det_labels, c->batch_desc};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete c;
+    return TOI_OK;
+}
+
+toi_status toi_set_stream(toi_ctx* c, void* s) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_set_stream: ctx is NULL");
+    c->stream = reinterpret_cast<hipStream_t>(s);
+    return TOI_OK;
+}
+
+static toi_status check_snapshot(toi_ctx* c, const toi_snapshot* s, const char* who) {
+    if (!s) return fail(c, TOI_EINVAL, std::string(who) + ": snapshot is NULL");
+    if (s->n_row < 0 || s->n_row > c->p.n_row_max)
+        return fail(c, TOI_EINVAL, std::string(who) + ": n_row outside [0, n_row_max]");
+    if (s->n_row > 0 && (!s->uvw || !s->vis || !s->freq))
+        return fail(c, TOI_EINVAL, std::string(who) + ": uvw, vis and freq are required");
+    if (s->gains && (!s->ant1 || !s->ant2))
+        return fail(c, TOI_EINVAL, std::string(who) + ": gains need ant1 and ant2");
+    if (s->gains && c->p.n_ant <= 0)
+        return fail(c, TOI_EINVAL, std::string(who) + ": gains given but n_ant is 0");
+    return TOI_OK;
+}
+
+toi_status toi_grid(toi_ctx* c, const toi_snapshot* s) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_grid: ctx is NULL");
+    toi_status st = check_snapshot(c, s, "toi_grid");
+    if (st != TOI_OK) return st;
+    st = hip_check(c, launch_prep(c, *s), "toi_grid: prep");
+    if (st != TOI_OK) return st;
+    return hip_check(c, launch_grid(c, *s), "toi_grid: gridding");
+}
+
+toi_status toi_image(toi_ctx* c, float* image_out, float* tplane_out) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_image: ctx is NULL");
+    if (!image_out) return fail(c, TOI_EINVAL, "toi_image: image_out is NULL");
+    return hip_check(c, launch_image(c, image_out, tplane_out), "toi_image");
+}
+
+toi_status toi_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot* s, void* grad_vis,
+                      void* grad_gains) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_degrid: ctx is NULL");
+    if (!grad_image) return fail(c, TOI_EINVAL, "toi_degrid: grad_image is NULL");
+    toi_status st = check_snapshot(c, s, "toi_degrid");
+    if (st != TOI_OK) return st;
+    if (grad_gains && !s->gains) return fail(c, TOI_EINVAL, "toi_degrid: grad_gains needs gains");
+    return hip_check(c, launch_degrid(c, grad_image, *s, (float2*)grad_vis, (float2*)grad_gains),
+                     "toi_degrid");
+}
+
+toi_status fitrig_tlisi(toi_ctx* c, const float* a, const float* b, const float* d, float* out) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "fitrig_tlisi: ctx is NULL");
+    if (!a || !b || !d || !out) return fail(c, TOI_EINVAL, "fitrig_tlisi: NULL image or output");
+    return hip_check(c, launch_tlisi(c, a, b, d, out), "fitrig_tlisi");
+}
+
+toi_status fitrig_detect(toi_ctx* c, const float* window, int32_t t, int32_t* boxes, int32_t max_boxes,
+                         int32_t* n_boxes) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "fitrig_detect: ctx is NULL");
+    if (!window || !n_boxes || (max_boxes > 0 && !boxes) || max_boxes < 0)
+        return fail(c, TOI_EINVAL, "fitrig_detect: NULL window/boxes/count or max_boxes < 0");
+    return hip_check(c, launch_detect(c, window, t, boxes, max_boxes, n_boxes), "fitrig_detect");
+}
+
+toi_status toi_plan_info(toi_ctx* c, double V_out[9], double* omega, double* wsum, int32_t* n_slab,
+                         int32_t* cheb_k, uint32_t* status) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_plan_info: ctx is NULL");
+    DevPlan h{};
+    hipError_t e = hipMemcpyAsync(&h, c->plan, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "toi_plan_info");
+    if (V_out) std::memcpy(V_out, h.V, sizeof(h.V));
+    if (omega) *omega = h.omega;
+    if (wsum) *wsum = h.wsum;
+    if (n_slab) *n_slab = h.n_slab;
+    if (cheb_k) *cheb_k = h.K;
+    if (status) *status = h.status;
+    return TOI_OK;
+}
+
+const char* toi_last_error(const toi_ctx* c) {
+    if (c) return c->err.c_str();
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    return g_err.c_str();
+}
+
+}  // extern "C"

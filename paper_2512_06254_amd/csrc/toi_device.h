@@ -1,0 +1,81 @@
+// Device helpers shared by the kernels: deterministic block reductions and
+// small numeric routines.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace toi {
+
+// Sum over a 64-lane wavefront with a fixed butterfly order (deterministic).
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename T>
+__device__ inline T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+template <typename T>
+__device__ inline T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block reductions for blockDim.x a multiple of 64 (<= 1024); `red` holds one
+// slot per wavefront.  Every thread receives the result.
+template <typename T>
+__device__ inline T block_sum(T v, T* red) {
+    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    T s = 0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    __syncthreads();
+    return s;
+}
+template <typename T>
+__device__ inline T block_max(T v, T* red) {
+    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+    v = wave_max(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    T s = red[0];
+    for (int i = 1; i < nw; ++i) s = fmax(s, red[i]);
+    __syncthreads();
+    return s;
+}
+template <typename T>
+__device__ inline T block_min(T v, T* red) {
+    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+    v = wave_min(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    T s = red[0];
+    for (int i = 1; i < nw; ++i) s = fmin(s, red[i]);
+    __syncthreads();
+    return s;
+}
+
+__device__ inline float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// Exponential-of-semicircle gridding kernel on |z| <= 1 (beta = 2.30 * 8).
+__device__ inline float es_kernel(float z) {
+    constexpr float beta = 18.4f;
+    const float a = fmaxf(1.0f - z * z, 0.0f);
+    return __expf(beta * (__fsqrt_rn(a) - 1.0f));
+}
+
+}  // namespace toi

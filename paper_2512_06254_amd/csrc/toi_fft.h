@@ -1,0 +1,154 @@
+// Block-wide inverse FFT of length M held in LDS (Stockham auto-sort).
+//
+// T = M / E threads each hold E complex values in registers.  The length is
+// split as M = R1 * E * ... * E (R1 <= E, all powers of two); each stage does
+// E / R radix-R butterflies per thread in registers, with one LDS round trip
+// between stages.  Before the first stage thread t holds elements
+// t + b T + r (M / R1) (b < E / R1, r < R1) in v[b R1 + r]; after the last
+// stage it holds outputs t + r T (r < E) in v[r], in natural order.  The sign
+// is +i (inverse transform, un-normalised).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "toi_device.h"
+
+namespace toi {
+
+// e^{+2 pi i m / 32} for m < 16
+__device__ constexpr float kTwCos32[16] = {
+    1.0f, 9.807852804e-01f, 9.238795325e-01f, 8.314696123e-01f, 7.071067812e-01f, 5.555702330e-01f,
+    3.826834324e-01f, 1.950903220e-01f, 0.0f, -1.950903220e-01f, -3.826834324e-01f, -5.555702330e-01f,
+    -7.071067812e-01f, -8.314696123e-01f, -9.238795325e-01f, -9.807852804e-01f};
+__device__ constexpr float kTwSin32[16] = {
+    0.0f, 1.950903220e-01f, 3.826834324e-01f, 5.555702330e-01f, 7.071067812e-01f, 8.314696123e-01f,
+    9.238795325e-01f, 9.807852804e-01f, 1.0f, 9.807852804e-01f, 9.238795325e-01f, 8.314696123e-01f,
+    7.071067812e-01f, 5.555702330e-01f, 3.826834324e-01f, 1.950903220e-01f};
+
+// R-point inverse DFT in registers, natural order in and out (radix-2 DIT).
+template <int R>
+struct Dft {
+    __device__ static inline void run(float2* v) {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        Dft<R / 2>::run(e);
+        Dft<R / 2>::run(o);
+#pragma unroll
+        for (int m = 0; m < R / 2; ++m) {
+            float2 t;
+            if (m == 0) {
+                t = o[m];
+            } else if (4 * m == R) {                         // w = i
+                t = make_float2(-o[m].y, o[m].x);
+            } else {
+                const float2 w = make_float2(kTwCos32[m * (32 / R)], kTwSin32[m * (32 / R)]);
+                t = cmul(w, o[m]);
+            }
+            v[m] = cadd(e[m], t);
+            v[m + R / 2] = csub(e[m], t);
+        }
+    }
+};
+template <>
+struct Dft<1> {
+    __device__ static inline void run(float2*) {}
+};
+template <>
+struct Dft<2> {
+    __device__ static inline void run(float2* v) {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+__host__ __device__ constexpr int fft_first_radix(int M, int E) {
+    int r = M;
+    while (r > E) r /= E;
+    return r;
+}
+__host__ __device__ constexpr int fft_radix_at(int M, int E, int NS) {
+    return NS == 1 ? fft_first_radix(M, E) : E;
+}
+
+template <int M, int E, int R, int NS>
+__device__ inline void fft_stage_regs(float2* v, const float2* __restrict__ tw) {
+    constexpr int T = M / E;
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        if (NS > 1) {
+            const int j = threadIdx.x + b * T;
+            const int k = j & (NS - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], tw[(r * k * (M / (NS * R))) & (M - 1)]);
+        }
+        Dft<R>::run(v + b * R);
+    }
+}
+
+template <int M, int E, int NS>
+__device__ inline void fft_stages(float2* v, float2* lds, const float2* __restrict__ tw) {
+    constexpr int T = M / E;
+    constexpr int R = fft_radix_at(M, E, NS);
+    fft_stage_regs<M, E, R, NS>(v, tw);
+    if constexpr (NS * R < M) {
+        constexpr int R2 = fft_radix_at(M, E, NS * R);
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < E / R; ++b) {
+            const int j = threadIdx.x + b * T;
+            const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[base + r * NS] = v[b * R + r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < E / R2; ++b) {
+            const int j = threadIdx.x + b * T;
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[j + r * (M / R2)];
+        }
+        fft_stages<M, E, NS * R>(v, lds, tw);
+    }
+}
+
+// Load the stage-1 pattern of one length-M row starting at src.
+template <int M, int E>
+__device__ inline void fft_load(float2* v, const float2* __restrict__ src) {
+    constexpr int T = M / E;
+    constexpr int R1 = fft_first_radix(M, E);
+#pragma unroll
+    for (int b = 0; b < E / R1; ++b)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) v[b * R1 + r] = src[threadIdx.x + b * T + r * (M / R1)];
+}
+
+// Output slot r (0 <= r < E) of thread t is bin k = t + r T.  With M = 2N the
+// kept bins are a = k (k < N/2) and a = k - M (k >= M - N/2), a in [-N/2, N/2),
+// i.e. the slots r < E/4 and r >= 3E/4.
+template <int E>
+__device__ constexpr int fft_kept_slot(int q) {  // q < E/2 -> slot r
+    return q < E / 4 ? q : q + E / 2;
+}
+
+// Image index j = a + N/2 of kept slot q for thread t.
+template <int M, int E>
+__device__ inline int fft_kept_index(int q) {
+    constexpr int T = M / E;
+    const int r = fft_kept_slot<E>(q);
+    const int k = threadIdx.x + r * T;
+    return (k < M / 4) ? k + M / 4 : k - M + M / 4;
+}
+
+// Hardware dispatches workgroup i to XCD i mod 8.  Remap so that each XCD
+// receives a contiguous range of logical ids (neighbouring tiles share its L2).
+__device__ inline int xcd_block_id(int bid, int nblk) {
+    if (nblk % 8) return bid;
+    return (bid & 7) * (nblk >> 3) + (bid >> 3);
+}
+
+}  // namespace toi

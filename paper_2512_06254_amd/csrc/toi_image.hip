@@ -1,0 +1,263 @@
+// S5-S7: inverse FFT of every moment plane, grid correction, the Chebyshev /
+// slab combination of Section 3.4 (or the single plane of Section 3.2), and
+// the re-projection of Section 3.3.
+//
+// Row pass (per plane, bands of B grid rows): FFT along x, keep the N central
+// bins and write them column-major per plane, hbuf[plane][j1][y], so that the
+// column pass reads each column as one contiguous 8M-byte run.
+// Column pass (one image column j1 per workgroup): for every plane, FFT along
+// y, keep the N central bins, and fold the plane into the pixel's combination
+// in registers; only the real t-plane image leaves the workgroup.
+#include "toi_fft.h"
+#include "toi_internal.h"
+
+namespace toi {
+
+template <int M, int E, int B>
+__global__ __launch_bounds__(M / E) void k_fft_rows(const float2* __restrict__ grid, float2* __restrict__ hbuf,
+                                                    const float2* __restrict__ tw,
+                                                    const DevPlan* __restrict__ plan, int nbands) {
+    constexpr int N = M / 2;
+    constexpr int KEEP = E / 2;
+    __shared__ float2 lds[M];
+    const int id = xcd_block_id(blockIdx.x, gridDim.x);
+    const int plane = id / nbands, band = id % nbands;
+    if (plan->status || plane >= plan->planes) return;
+    float2 keep[B][KEEP];
+#pragma unroll
+    for (int rb = 0; rb < B; ++rb) {
+        const int y = band * B + rb;
+        float2 v[E];
+        fft_load<M, E>(v, grid + ((size_t)plane * M + y) * M);
+        fft_stages<M, E, 1>(v, lds, tw);
+#pragma unroll
+        for (int q = 0; q < KEEP; ++q) keep[rb][q] = v[fft_kept_slot<E>(q)];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < KEEP; ++q) {
+        const int j1 = fft_kept_index<M, E>(q);
+        float2* dst = hbuf + ((size_t)plane * N + j1) * M + band * B;
+        if constexpr (B % 2 == 0) {
+#pragma unroll
+            for (int rb = 0; rb < B; rb += 2)
+                *reinterpret_cast<float4*>(dst + rb) =
+                    make_float4(keep[rb][q].x, keep[rb][q].y, keep[rb + 1][q].x, keep[rb + 1][q].y);
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < B; ++rb) dst[rb] = keep[rb][q];
+        }
+    }
+}
+
+// Per-pixel state of the Chebyshev combination.  The Bessel values J_k(alpha)
+// come from Miller's backward recurrence (DLMF 10.74(iii)) run from order L
+// down to 0 alongside the planes k = K-1 .. 0, with the normalisation
+// J_0 + 2 sum_m J_{2m} = 1 applied once at the end; small |alpha| uses the
+// power series.
+template <int M, int E>
+__global__ __launch_bounds__(M / E) void k_fft_cols(const float2* __restrict__ hbuf, float* __restrict__ tplane_t,
+                                                    const float2* __restrict__ tw, const float* __restrict__ corr,
+                                                    const DevPlan* __restrict__ plan, float cell_rad, int mode) {
+    constexpr int N = M / 2;
+    constexpr int KEEP = E / 2;
+    __shared__ float2 lds[M];
+    const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
+    int j2[KEEP];
+#pragma unroll
+    for (int q = 0; q < KEEP; ++q) j2[q] = fft_kept_index<M, E>(q);
+    float* out = tplane_t + (size_t)j1 * N;
+    if (plan->status) {
+#pragma unroll
+        for (int q = 0; q < KEEP; ++q) out[j2[q]] = 0.f;
+        return;
+    }
+    const int K = plan->K, ns = plan->n_slab;
+    const float c1 = corr[j1];
+    float tr[KEEP], ti[KEEP];
+#pragma unroll
+    for (int q = 0; q < KEEP; ++q) { tr[q] = 0.f; ti[q] = 0.f; }
+
+    if (mode == 2) {
+        float2 v[E];
+        fft_load<M, E>(v, hbuf + (size_t)j1 * M);
+        fft_stages<M, E, 1>(v, lds, tw);
+#pragma unroll
+        for (int q = 0; q < KEEP; ++q) tr[q] = v[fft_kept_slot<E>(q)].x;
+    } else {
+        // transformed-plane geometry of this thread's pixels
+        const float V13 = (float)plan->V[2], V23 = (float)plan->V[5], V33 = (float)plan->V[8];
+        const float sg = V33 >= 0.f ? 1.f : -1.f;
+        const float t1 = -cell_rad * (float)(j1 - N / 2);
+        const float dr3 = (float)plan->dr3;
+        float t3[KEEP], alpha[KEEP], ialpha[KEEP];
+        bool small[KEEP], valid[KEEP];
+#pragma unroll
+        for (int q = 0; q < KEEP; ++q) {
+            const float t2 = cell_rad * (float)(j2[q] - N / 2);
+            const float a1 = t1 + V13, a2 = t2 + V23;
+            const float arg = 1.f - a1 * a1 - a2 * a2;
+            valid[q] = arg >= 0.f;
+            // eq. (t3) in a cancellation-free form: 1 - V33^2 = V13^2 + V23^2
+            const float num = t1 * t1 + t2 * t2 + 2.f * t1 * V13 + 2.f * t2 * V23;
+            t3[q] = valid[q] ? -sg * num / (sqrtf(fmaxf(arg, 0.f)) + fabsf(V33)) : 0.f;
+            alpha[q] = 2.f * 3.14159265358979f * dr3 * t3[q];
+            small[q] = fabsf(alpha[q]) < 1e-3f;
+            ialpha[q] = small[q] ? 0.f : 1.f / alpha[q];
+        }
+        const int L = max(plan->miller_top, K + 2);
+        for (int p = 0; p < ns; ++p) {
+            float jp1[KEEP], jc[KEEP], nrm[KEEP], ar[KEEP], ai[KEEP];
+#pragma unroll
+            for (int q = 0; q < KEEP; ++q) { jp1[q] = 0.f; jc[q] = 1.f; nrm[q] = 0.f; ar[q] = 0.f; ai[q] = 0.f; }
+            // orders L .. K: recurrence only
+            for (int n = L; n >= K; --n) {
+#pragma unroll
+                for (int q = 0; q < KEEP; ++q) {
+                    if ((n & 1) == 0) nrm[q] += 2.f * jc[q];
+                    const float jm1 = (2.f * n) * ialpha[q] * jc[q] - jp1[q];
+                    jp1[q] = jc[q];
+                    jc[q] = jm1;
+                    if (fabsf(jc[q]) > 1e15f) {
+                        jc[q] *= 1e-15f; jp1[q] *= 1e-15f; nrm[q] *= 1e-15f;
+                        ar[q] *= 1e-15f; ai[q] *= 1e-15f;
+                    }
+                }
+            }
+            // orders K-1 .. 0 with their planes
+            for (int k = K - 1; k >= 0; --k) {
+                float2 v[E];
+                fft_load<M, E>(v, hbuf + ((size_t)(p * K + k) * N + j1) * M);
+                fft_stages<M, E, 1>(v, lds, tw);
+#pragma unroll
+                for (int q = 0; q < KEEP; ++q) {
+                    float jk;
+                    if (small[q]) {
+                        const float a = alpha[q];
+                        jk = k == 0 ? 1.f - 0.25f * a * a
+                           : k == 1 ? 0.5f * a * (1.f - 0.125f * a * a)
+                           : k == 2 ? 0.125f * a * a
+                           : k == 3 ? a * a * a * (1.f / 48.f) : 0.f;
+                    } else {
+                        jk = jc[q];
+                        if ((k & 1) == 0) nrm[q] += (k == 0 ? 1.f : 2.f) * jk;
+                    }
+                    const float f = (k == 0 ? 1.f : 2.f) * jk;
+                    const float2 F = v[fft_kept_slot<E>(q)];
+                    switch (k & 3) {   // c_k = 2 i^k J_k (c_0 = J_0)
+                        case 0: ar[q] += f * F.x; ai[q] += f * F.y; break;
+                        case 1: ar[q] -= f * F.y; ai[q] += f * F.x; break;
+                        case 2: ar[q] -= f * F.x; ai[q] -= f * F.y; break;
+                        default: ar[q] += f * F.y; ai[q] -= f * F.x; break;
+                    }
+                    if (!small[q] && k > 0) {
+                        const float jm1 = (2.f * k) * ialpha[q] * jc[q] - jp1[q];
+                        jp1[q] = jc[q];
+                        jc[q] = jm1;
+                        if (fabsf(jc[q]) > 1e15f) {
+                            jc[q] *= 1e-15f; jp1[q] *= 1e-15f; nrm[q] *= 1e-15f;
+                            ar[q] *= 1e-15f; ai[q] *= 1e-15f;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            const float r3p = (float)(plan->r3min + (2 * p + 1) * plan->dr3);
+#pragma unroll
+            for (int q = 0; q < KEEP; ++q) {
+                const float inv = small[q] ? 1.f : 1.f / nrm[q];
+                float sn, cs;
+                sincosf(2.f * 3.14159265358979f * r3p * t3[q], &sn, &cs);
+                const float xr = ar[q] * inv, xi = ai[q] * inv;
+                tr[q] += cs * xr - sn * xi;
+                ti[q] += cs * xi + sn * xr;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KEEP; ++q)
+            if (!valid[q]) tr[q] = 0.f;
+    }
+    const float norm = (float)plan->norm;
+#pragma unroll
+    for (int q = 0; q < KEEP; ++q) out[j2[q]] = tr[q] * c1 * corr[j2[q]] * norm;
+}
+
+// Re-projection (Section 3.3): output pixel -> reduced SIN map to the tilted
+// plane (x' = x + r0 z xi, y' = y + r0 z eta, z = 1 - n) -> in-plane 2x2 block
+// of V -> transformed-plane coordinates -> bilinear gather.  FP64 coordinates.
+__global__ __launch_bounds__(256) void k_reproject(const float* __restrict__ tplane_t, float* __restrict__ img,
+                                                   const DevPlan* __restrict__ plan, int N, double cell_rad) {
+    const int j1 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j2 = blockIdx.y;
+    if (j1 >= N) return;
+    float val = 0.f;
+    if (!plan->status) {
+        const double l = -cell_rad * (j1 - N / 2), m = cell_rad * (j2 - N / 2);
+        const double rho2 = l * l + m * m;
+        if (rho2 < 1.0) {
+            const double z = rho2 / (1.0 + sqrt(1.0 - rho2));       // 1 - n, stable near the centre
+            const double a = l + plan->xi * z, b = m + plan->eta * z;
+            const double t1 = plan->V[0] * a + plan->V[1] * b;
+            const double t2 = plan->V[3] * a + plan->V[4] * b;
+            const double u1 = 0.5 * N - t1 / cell_rad, u2 = 0.5 * N + t2 / cell_rad;
+            const double f1d = floor(u1), f2d = floor(u2);
+            if (f1d >= 0.0 && f1d <= N - 2 && f2d >= 0.0 && f2d <= N - 2) {
+                const int i1 = (int)f1d, i2 = (int)f2d;
+                const float f1 = (float)(u1 - f1d), f2 = (float)(u2 - f2d);
+                const float* c0 = tplane_t + (size_t)i1 * N + i2;      // j1-major t-plane
+                const float* c1 = c0 + N;
+                val = (1.f - f1) * (1.f - f2) * c0[0] + f1 * (1.f - f2) * c1[0] + (1.f - f1) * f2 * c0[1] +
+                      f1 * f2 * c1[1];
+            }
+        }
+    }
+    img[(size_t)j2 * N + j1] = val;
+}
+
+__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src, float* __restrict__ dst, int N) {
+    __shared__ float tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int i = ty; i < 32; i += 8) tile[i][tx] = src[(size_t)(by + i) * N + bx + tx];
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) dst[(size_t)(bx + i) * N + by + tx] = tile[tx][i];
+}
+
+template <int M, int E>
+static hipError_t launch_fft_passes(toi_ctx* c) {
+    constexpr int B = (M >= 8192) ? 2 : 4;
+    const int nbands = M / B;
+    const int P = c->P_cap;
+    hipLaunchKernelGGL((k_fft_rows<M, E, B>), dim3(nbands * P), dim3(M / E), 0, c->stream, c->grid, c->hbuf,
+                       c->twiddle, c->plan, nbands);
+    const float cell = (float)(c->p.cell_deg * kPi / 180.0);
+    hipLaunchKernelGGL((k_fft_cols<M, E>), dim3(M / 2), dim3(M / E), 0, c->stream, c->hbuf, c->tplane_t,
+                       c->twiddle, c->corr, c->plan, cell, c->p.mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_image(toi_ctx* c, float* image_out, float* tplane_out) {
+    hipError_t e;
+    switch (c->M) {
+        case 64: e = launch_fft_passes<64, 8>(c); break;
+        case 128: e = launch_fft_passes<128, 8>(c); break;
+        case 256: e = launch_fft_passes<256, 16>(c); break;
+        case 512: e = launch_fft_passes<512, 16>(c); break;
+        case 1024: e = launch_fft_passes<1024, 16>(c); break;
+        case 2048: e = launch_fft_passes<2048, 16>(c); break;
+        case 4096: e = launch_fft_passes<4096, 16>(c); break;
+        case 8192: e = launch_fft_passes<8192, 32>(c); break;
+        case 16384: e = launch_fft_passes<16384, 32>(c); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    const int N = c->N;
+    const double cell = c->p.cell_deg * kPi / 180.0;
+    hipLaunchKernelGGL(k_reproject, dim3((N + 255) / 256, N), dim3(256), 0, c->stream, c->tplane_t, image_out,
+                       c->plan, N, cell);
+    if (tplane_out)
+        hipLaunchKernelGGL(k_transpose, dim3(N / 32, N / 32), dim3(256), 0, c->stream, c->tplane_t, tplane_out, N);
+    return hipGetLastError();
+}
+
+}  // namespace toi

@@ -1,0 +1,102 @@
+// Internal declarations shared by the HIP translation units of libtoi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/toi.h"
+
+namespace toi {
+
+constexpr double kCLight = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kSupport = 8;                 // ES kernel support W (cells)
+constexpr double kEsBetaPerW = 2.30;        // beta = 2.30 W for a 2x oversampled grid
+constexpr int kWindow = 16;                 // FITrig sliding window (tLISI maps)
+
+// Plan of the current snapshot, written and read on the device only.
+struct DevPlan {
+    double V[9];          // rows: e1, e2, e3
+    double omega, xi, eta;
+    double wsum;          // W = sum of sample weights
+    double nvis;          // kept samples
+    double r3min, r3max;
+    double t3max;         // written through its bit pattern by an atomic max
+    double phimax, dr3, alpha_slab;
+    double norm;          // 1 / (omega W)
+    double sum_b[3];
+    double sum_bb[6];
+    int32_t n_slab, K, planes;
+    uint32_t status;
+    int32_t miller_top;   // starting order of the Bessel backward recurrence
+    int32_t pad_[3];
+};
+
+// Per-row partial sums of the kept samples (sample prep).
+struct RowStat {
+    double cnt;           // kept channels
+    double s1;            // sum nu / c
+    double s2;            // sum (nu / c)^2
+    double wsum;          // sum of sample weights
+    double numin, numax;  // extreme kept frequencies (Hz)
+    double pad_[2];
+};
+
+struct TileStat {         // FITrig per-tile sums (FP64)
+    double sx, sy, sxx, syy, sxy, mn, mx, pad_;
+};
+
+}  // namespace toi
+
+struct toi_ctx {
+    toi_params p;
+    hipStream_t stream;
+    int device;
+    int N, M, T;          // image side, grid side, tLISI tiles per axis
+    int P_cap;            // plane capacity
+    int forced_K;         // 0 when chosen on the device
+    int kmax;             // accumulator width of the gridder (>= K)
+    std::string err;
+
+    // workspace (device)
+    float2* grid;         // [P_cap][M][M]
+    float2* hbuf;         // [P_cap][N][M]   row-pass output, column major per plane
+    float* tplane_t;      // [N][N]          transformed-plane image, j1 major
+    toi::DevPlan* plan;
+    toi::RowStat* rows;   // [n_row_max]
+    float* corr;          // [N]  (-1)^a / psi(a), a = j - N/2
+    float2* twiddle;      // [M]  e^{+2 pi i n / M}
+    toi::TileStat* tiles; // [T*T]
+    double* scratch_d;    // small FP64 scratch (reductions)
+    int32_t* scratch_i;   // small integer scratch (detection)
+    float* det_scores;    // [2][T*T] detection z-scores
+    int32_t* det_labels;  // [T*T]
+
+    // batched execution
+    hipGraph_t batch_graph;
+    hipGraphExec_t batch_exec;
+    void* batch_desc;     // device copy of the current snapshot descriptor
+};
+
+namespace toi {
+
+// error helpers (toi_ctx.cpp)
+toi_status fail(toi_ctx* ctx, toi_status st, const std::string& msg);
+toi_status hip_check(toi_ctx* ctx, hipError_t e, const char* what);
+
+// launchers, one per translation unit
+hipError_t launch_prep(toi_ctx* ctx, const toi_snapshot& s);
+hipError_t launch_grid(toi_ctx* ctx, const toi_snapshot& s);
+hipError_t launch_image(toi_ctx* ctx, float* image_out, float* tplane_out);
+hipError_t launch_degrid(toi_ctx* ctx, const float* grad_image, const toi_snapshot& s,
+                         float2* grad_vis, float2* grad_gains);
+hipError_t launch_tlisi(toi_ctx* ctx, const float* a, const float* b, const float* c, float* out);
+hipError_t launch_detect(toi_ctx* ctx, const float* window, int t, int32_t* boxes, int max_boxes,
+                         int32_t* n_boxes);
+
+// host-side tables (toi_tables.cpp)
+void es_correction_table(int N, int M, double* out);   // (-1)^a / psi(a)
+
+}  // namespace toi
