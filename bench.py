@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the TOI snapshot-imaging hot path on one MI355X.
+
+One step = one snapshot through the whole path: sample statistics, basis and
+plan, gridding of the moment planes, inverse FFT with grid correction and
+Chebyshev/slab combination, re-projection, and the tLISI map of the three
+youngest images.  Inputs are resident in HBM before the timed region starts
+(a pool of distinct synthetic snapshots generated on the device by the seeded
+generator and cycled through).  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload meerkat] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms/snapshot imaged (2016 bl×4096 ch→2048²), batched vs plain; adjoint ms"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_pool(wl, n_pool, device):
+    """n_pool distinct snapshots of the workload, generated on the device."""
+    import numpy as np
+    import torch
+
+    import synth_inputs as S
+    enu, sky = S.antenna_enu(wl), S.make_sky(wl)
+    freq = torch.from_numpy(S.channel_freqs(wl)).to(device)
+    a1, a2 = S.baseline_pairs(wl.n_ant)
+    ant1, ant2 = torch.from_numpy(a1).to(device), torch.from_numpy(a2).to(device)
+    g = S.gains(wl)
+    gains = None if g is None else torch.from_numpy(g).to(device)
+    pool = []
+    for t in range(n_pool):
+        uvw = S.snapshot_uvw(wl, t, enu)
+        l, m, s = S.sources_at(sky, t)
+        vis = S.predict(uvw, S.channel_freqs(wl), l, m, s, wl.n_corr, device=device, chunk_rows=32)
+        gen = torch.Generator(device=device).manual_seed(1000003 * wl.seed + t)
+        nz = torch.randn(vis.shape + (2,), generator=gen, device=device, dtype=torch.float32) * wl.noise_sigma
+        vis += torch.view_as_complex(nz)
+        flag = None
+        if wl.flag_frac_max > 0:
+            frac = float(np.random.default_rng([wl.seed, 3, t]).uniform(0, wl.flag_frac_max))
+            f2 = (torch.rand((wl.n_row, wl.n_chan), generator=gen, device=device) < frac).to(torch.uint8)
+            flag = f2[:, :, None].expand(-1, -1, wl.n_corr).contiguous()
+        pool.append(dict(uvw=torch.from_numpy(uvw).to(device), vis=vis.contiguous(), flag=flag, weight=None,
+                         freq=freq, ant1=ant1, ant2=ant2, gains=gains))
+    torch.cuda.synchronize()
+    return pool
+
+
+def stage_bytes(wl, P, with_flags):
+    """Algorithmic HBM bytes per launch of each stage (each array read or written once)."""
+    N, M = wl.n_pix, 2 * wl.n_pix
+    vis = wl.n_row * wl.n_chan * wl.n_corr * 8
+    flags = wl.n_row * wl.n_chan * wl.n_corr if with_flags else 0
+    grid = P * M * M * 8
+    h = P * N * M * 8
+    img = N * N * 4
+    return {
+        "prep": flags + wl.n_chan * 8 + wl.n_row * 24,
+        "clear": grid,
+        "grid": vis + flags + grid,
+        "fft_rows": grid + h,
+        "fft_cols": h + img,
+        "reproject": 2 * img,
+        "tlisi": 3 * img,
+    }
+
+
+def cpu_baseline(wl, snap_dev, n_slab, K, n_pixels=6):
+    """The FP64 oracle on a bounded sample of one snapshot, extrapolated to ms/snapshot."""
+    import numpy as np
+
+    from oracle import fitrig as F
+    from oracle import toi as O
+    host = {k: (None if v is None else v.cpu().numpy()) for k, v in snap_dev.items()}
+    t0 = time.perf_counter()
+    smp = O.select_samples(host)
+    bas = O.snapshot_basis(smp.b)
+    r = O.rotate(bas.V, smp.b)
+    plan = O.make_plan(r[:, 2], bas.V, wl.n_pix, wl.cell_deg, n_slab=n_slab, K=K)
+    t_fixed = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    j1 = rng.integers(0, wl.n_pix, n_pixels)
+    j2 = rng.integers(0, wl.n_pix, n_pixels)
+    t1 = time.perf_counter()
+    O.image_cheb_at(r, smp.x, smp.W, bas.omega, bas.V, plan, j1, j2, wl.n_pix, wl.cell_deg)
+    t_pix = (time.perf_counter() - t1) / n_pixels
+    tp = np.zeros((wl.n_pix, wl.n_pix))
+    t2 = time.perf_counter()
+    O.reproject(tp, bas.V, wl.n_pix, wl.cell_deg)
+    F.tlisi(tp, tp + 1.0, tp, tile=32)
+    t_post = time.perf_counter() - t2
+    total_s = t_fixed + t_pix * wl.n_pix ** 2 + t_post
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": round(total_s * 1e3, 1), "unit": "ms/snapshot", "cores": cores, "kind": "oracle",
+        "sample": (f"FP64 oracle: sample selection, SVD basis and plan on all {smp.n} samples "
+                   f"({t_fixed:.1f} s), the Chebyshev t-plane sum at {n_pixels} random pixels "
+                   f"({t_pix:.2f} s/pixel, extrapolated to {wl.n_pix}^2 pixels), re-projection and tLISI "
+                   f"on full {wl.n_pix}^2 arrays ({t_post:.1f} s); wall time of the sample "
+                   f"{time.perf_counter() - t0:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="meerkat")
+    ap.add_argument("--pool", type=int, default=4, help="distinct resident snapshots cycled through")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this path has no multi-GPU mode (asked for --gpus {args.gpus}). "
+              "Snapshots are independent, so N GPUs would each take a contiguous time block.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth_inputs as S
+    from paper_2512_06254_amd import toi as T
+
+    wl = S.WORKLOADS[args.workload]
+    device = torch.device("cuda", 0)
+    torch.cuda.set_device(device)
+    n_slab, K = wl.forced_planes
+    P = n_slab * K
+    log(f"[bench] generating {args.pool} snapshots of '{wl.name}' on the GPU")
+    pool = make_pool(wl, args.pool, device)
+    im = T.Imager(wl.n_pix, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, mode=3, n_slab=n_slab, cheb_k=K,
+                  n_ant=wl.n_ant, tile=32)
+    N = wl.n_pix
+    ring = [torch.zeros((N, N), dtype=torch.float32, device=device) for _ in range(3)]
+    tl = torch.zeros((N // 32, N // 32), dtype=torch.float32, device=device)
+
+    def step(i):
+        im.grid(pool[i % len(pool)])
+        im.image(out=ring[i % 3])
+        if i >= 2:
+            im.tlisi(ring[(i - 2) % 3], ring[(i - 1) % 3], ring[i % 3], out=tl)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps); timing {args.steps} steps")
+    im.profile(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(args.warmup, args.warmup + args.steps):
+        step(i)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    prof = im.profile_read()
+    im.profile(False)
+    info = im.plan_info()
+    log(f"[bench] {ms:.3f} ms/snapshot; plan n_slab={info['n_slab']} K={info['K']} status={info['status']}")
+
+    sb = stage_bytes(wl, P, wl.flag_frac_max > 0)
+    stages = {}
+    for name, (tot, n) in prof.items():
+        if n:
+            avg = tot / n
+            stages[name] = {"avg_ms": round(avg, 4), "launches": n,
+                            "GBps": round(sb.get(name, 0) / (avg * 1e-3) / 1e9, 1) if name in sb else None}
+    dom = max((s for s in stages if s in sb), key=lambda s: stages[s]["avg_ms"] * stages[s]["launches"])
+    ach = sb[dom] / (stages[dom]["avg_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": dom,
+                "algorithmic_bytes": sb[dom]}
+    step_bytes = sum(sb.values()) - sb["clear"]
+    out = {
+        "metric": METRIC, "value": round(ms, 4), "unit": "ms/snapshot", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "baselines": wl.n_row, "channels": wl.n_chan, "correlations": wl.n_corr,
+                   "image": f"{N}x{N}", "cell_arcsec": wl.cell_arcsec, "planes": f"{n_slab} slab x K={K}",
+                   "grid": f"{2 * N}x{2 * N} ES support 8", "tlisi_tile": 32, "path": "plain per-snapshot",
+                   "pool": args.pool},
+        "roofline": roofline,
+        "stages": stages,
+        "step_effective_GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a bounded sample (cpu_baseline)")
+        out["cpu_baseline"] = cpu_baseline(wl, pool[0], n_slab, K)
+    im.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

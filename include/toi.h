@@ -155,6 +155,27 @@ toi_status toi_image_batch(toi_ctx* ctx, const toi_snapshot* snaps, int32_t n,
 toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* wsum,
                          int32_t* n_slab, int32_t* cheb_k, uint32_t* status);
 
+/* Measurement support.  Stages timed with HIP events on the context's stream:
+ * TOI_STAGE_PREP (sample statistics, basis, plan), TOI_STAGE_CLEAR (grid
+ * clear), TOI_STAGE_GRID (gridding), TOI_STAGE_FFT_ROWS, TOI_STAGE_FFT_COLS
+ * (column FFT + correction + combination), TOI_STAGE_REPROJECT,
+ * TOI_STAGE_TLISI, TOI_STAGE_DEGRID (adjoint).  toi_profile_enable(ctx, 1)
+ * creates the events and clears the totals (0 disables recording);
+ * toi_profile_read synchronises the stream and writes, per stage, the summed
+ * duration in milliseconds and the number of timed launches (host arrays of
+ * TOI_NSTAGE entries, each nullable). */
+#define TOI_STAGE_PREP 0
+#define TOI_STAGE_CLEAR 1
+#define TOI_STAGE_GRID 2
+#define TOI_STAGE_FFT_ROWS 3
+#define TOI_STAGE_FFT_COLS 4
+#define TOI_STAGE_REPROJECT 5
+#define TOI_STAGE_TLISI 6
+#define TOI_STAGE_DEGRID 7
+#define TOI_NSTAGE 8
+toi_status toi_profile_enable(toi_ctx* ctx, int32_t enable);
+toi_status toi_profile_read(toi_ctx* ctx, double* total_ms, int32_t* launches);
+
 /* Message for the last failing call on ctx (or a global one if ctx is NULL). */
 const char* toi_last_error(const toi_ctx* ctx);
 

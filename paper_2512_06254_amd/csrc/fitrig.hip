@@ -74,6 +74,7 @@ __global__ __launch_bounds__(256) void k_tlisi_final(const TileStat* __restrict_
 
 hipError_t launch_tlisi(toi_ctx* c, const float* a, const float* b, const float* d, float* out) {
     const int T = c->T;
+    StageTimer timer(c, TOI_STAGE_TLISI);
     hipLaunchKernelGGL(k_tlisi_tiles, dim3(T * T), dim3(256), 0, c->stream, a, b, d, c->N, c->p.tile, c->tiles);
     hipLaunchKernelGGL(k_tlisi_final, dim3(1), dim3(256), 0, c->stream, c->tiles, T * T, c->p.tile, out);
     return hipGetLastError();

@@ -83,6 +83,17 @@ void es_correction_table(int N, int M, double* out) {
     }
 }
 
+StageTimer::StageTimer(toi_ctx* ctx, int stage) : c(ctx), slot(-1) {
+    if (!c->prof_on || c->prof_n >= c->prof_stage.size()) return;
+    slot = (int)c->prof_n++;
+    c->prof_stage[slot] = stage;
+    (void)hipEventRecord(c->prof_ev[2 * slot], c->stream);
+}
+
+StageTimer::~StageTimer() {
+    if (slot >= 0) (void)hipEventRecord(c->prof_ev[2 * slot + 1], c->stream);
+}
+
 }  // namespace toi
 
 using namespace toi;
@@ -215,6 +226,8 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
 toi_status toi_destroy(toi_ctx* c) {
     if (!c) return TOI_OK;
     (void)hipStreamSynchronize(c->stream);
+    for (auto& e : c->prof_ev)
+        if (e) (void)hipEventDestroy(e);
     if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
     if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
     void* ptrs[] = {c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
@@ -297,6 +310,42 @@ toi_status toi_plan_info(toi_ctx* c, double V_out[9], double* omega, double* wsu
     if (n_slab) *n_slab = h.n_slab;
     if (cheb_k) *cheb_k = h.K;
     if (status) *status = h.status;
+    return TOI_OK;
+}
+
+toi_status toi_profile_enable(toi_ctx* c, int32_t enable) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_profile_enable: ctx is NULL");
+    c->prof_on = enable != 0;
+    c->prof_n = 0;
+    if (c->prof_on && c->prof_ev.empty()) {
+        const size_t cap = 8192;
+        c->prof_ev.resize(2 * cap);
+        c->prof_stage.assign(cap, 0);
+        for (auto& e : c->prof_ev) {
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return hip_check(c, err, "toi_profile_enable");
+        }
+    }
+    return TOI_OK;
+}
+
+toi_status toi_profile_read(toi_ctx* c, double* total_ms, int32_t* launches) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_profile_read: ctx is NULL");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "toi_profile_read");
+    double tot[TOI_NSTAGE] = {0};
+    int32_t cnt[TOI_NSTAGE] = {0};
+    for (size_t i = 0; i < c->prof_n; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_check(c, e, "toi_profile_read");
+        tot[c->prof_stage[i]] += ms;
+        cnt[c->prof_stage[i]] += 1;
+    }
+    for (int s = 0; s < TOI_NSTAGE; ++s) {
+        if (total_ms) total_ms[s] = tot[s];
+        if (launches) launches[s] = cnt[s];
+    }
     return TOI_OK;
 }
 

@@ -136,8 +136,12 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
     const toi_params& p = c->p;
     const size_t M = c->M;
     const size_t n4 = (size_t)c->P_cap * M * M * sizeof(float2) / sizeof(float4);
-    hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, c->stream, (float4*)c->grid, n4);
+    {
+        StageTimer timer(c, TOI_STAGE_CLEAR);
+        hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, c->stream, (float4*)c->grid, n4);
+    }
     if (s.n_row == 0) return hipGetLastError();
+    StageTimer timer(c, TOI_STAGE_GRID);
     const int chunk = 64;
     const int n_chunks = (p.n_chan + chunk - 1) / chunk;
     const long items = (long)s.n_row * n_chunks;

@@ -228,9 +228,13 @@ static hipError_t launch_fft_passes(toi_ctx* c) {
     constexpr int B = (M >= 8192) ? 2 : 4;
     const int nbands = M / B;
     const int P = c->P_cap;
-    hipLaunchKernelGGL((k_fft_rows<M, E, B>), dim3(nbands * P), dim3(M / E), 0, c->stream, c->grid, c->hbuf,
-                       c->twiddle, c->plan, nbands);
+    {
+        StageTimer timer(c, TOI_STAGE_FFT_ROWS);
+        hipLaunchKernelGGL((k_fft_rows<M, E, B>), dim3(nbands * P), dim3(M / E), 0, c->stream, c->grid,
+                           c->hbuf, c->twiddle, c->plan, nbands);
+    }
     const float cell = (float)(c->p.cell_deg * kPi / 180.0);
+    StageTimer timer(c, TOI_STAGE_FFT_COLS);
     hipLaunchKernelGGL((k_fft_cols<M, E>), dim3(M / 2), dim3(M / E), 0, c->stream, c->hbuf, c->tplane_t,
                        c->twiddle, c->corr, c->plan, cell, c->p.mode);
     return hipGetLastError();
@@ -253,6 +257,7 @@ hipError_t launch_image(toi_ctx* c, float* image_out, float* tplane_out) {
     if (e != hipSuccess) return e;
     const int N = c->N;
     const double cell = c->p.cell_deg * kPi / 180.0;
+    StageTimer timer(c, TOI_STAGE_REPROJECT);
     hipLaunchKernelGGL(k_reproject, dim3((N + 255) / 256, N), dim3(256), 0, c->stream, c->tplane_t, image_out,
                        c->plan, N, cell);
     if (tplane_out)

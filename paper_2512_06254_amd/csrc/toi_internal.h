@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/toi.h"
 
@@ -74,6 +75,12 @@ struct toi_ctx {
     float* det_scores;    // [2][T*T] detection z-scores
     int32_t* det_labels;  // [T*T]
 
+    // per-stage timing (measurement only)
+    bool prof_on;
+    std::vector<hipEvent_t> prof_ev;      // pairs (start, stop)
+    std::vector<int> prof_stage;          // stage of each recorded pair
+    size_t prof_n;
+
     // batched execution
     hipGraph_t batch_graph;
     hipGraphExec_t batch_exec;
@@ -96,7 +103,16 @@ hipError_t launch_tlisi(toi_ctx* ctx, const float* a, const float* b, const floa
 hipError_t launch_detect(toi_ctx* ctx, const float* window, int t, int32_t* boxes, int max_boxes,
                          int32_t* n_boxes);
 
-// host-side tables (toi_tables.cpp)
+// RAII stage timer: records a start/stop event pair on the context's stream
+// when profiling is enabled (toi_ctx.cpp).
+struct StageTimer {
+    toi_ctx* c;
+    int slot;
+    StageTimer(toi_ctx* ctx, int stage);
+    ~StageTimer();
+};
+
+// host-side tables (toi_ctx.cpp)
 void es_correction_table(int N, int M, double* out);   // (-1)^a / psi(a)
 
 }  // namespace toi

@@ -18,20 +18,20 @@ __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ wei
     double mn = 1e300, mx = -1e300;
     for (int c = threadIdx.x; c < n_chan; c += blockDim.x) {
         const size_t base = ((size_t)r * n_chan + c) * n_corr;
-        float w = 0.f;
+        double w = 0.0;
         for (int k = 0; k < n_corr; ++k) {
             if (!((mask >> k) & 1u)) continue;
-            float wk = weight ? weight[base + k] : 1.f;
-            if (flag && flag[base + k]) wk = 0.f;
+            double wk = weight ? (double)weight[base + k] : 1.0;
+            if (flag && flag[base + k]) wk = 0.0;
             w += wk;
         }
-        if (w > 0.f) {
+        if (w > 0.0) {
             const double nu = freq[c];
             const double kk = nu / kCLight;
             cnt += 1.0;
             s1 += kk;
             s2 += kk * kk;
-            ws += (double)w;
+            ws += w;
             mn = fmin(mn, nu);
             mx = fmax(mx, nu);
         }
@@ -297,6 +297,7 @@ __global__ __launch_bounds__(256) void k_plan(double alpha_target, double gamma,
 }
 
 hipError_t launch_prep(toi_ctx* c, const toi_snapshot& s) {
+    StageTimer timer(c, TOI_STAGE_PREP);
     const toi_params& p = c->p;
     if (s.n_row > 0)
         hipLaunchKernelGGL(k_row_stats, dim3(s.n_row), dim3(256), 0, c->stream, s.weight, s.flag, s.freq,

@@ -65,8 +65,13 @@ _SIGS = {
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_uint32)]),
+    "toi_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "toi_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "toi_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
+
+STAGES = ("prep", "clear", "grid", "fft_rows", "fft_cols", "reproject", "tlisi", "degrid")
 
 
 def lib():
@@ -200,6 +205,18 @@ class Imager:
         self._sync_stream()
         _check(lib().toi_image_batch(self.ctx, arr, len(snaps), _ptr(images_out), _ptr(tlisi_out)),
                self.ctx)
+
+    def profile(self, enable: bool = True):
+        """Start (clearing the totals) or stop per-stage HIP-event timing."""
+        _check(lib().toi_profile_enable(self.ctx, 1 if enable else 0), self.ctx)
+
+    def profile_read(self) -> dict:
+        """Synchronise; {stage: (total ms, launches)} of the timed stages."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = (ctypes.c_int32 * len(STAGES))()
+        self._sync_stream()
+        _check(lib().toi_profile_read(self.ctx, ms, n), self.ctx)
+        return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
 
     def plan_info(self) -> dict:
         V = (ctypes.c_double * 9)()
