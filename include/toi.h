@@ -47,6 +47,7 @@ typedef enum {
 #define TOI_STATUS_NO_SAMPLES 1u   /* every sample flagged or zero-weight: zero image      */
 #define TOI_STATUS_DEGENERATE 2u   /* |V33| < 1e-6: transformed plane edge-on, zero image   */
 #define TOI_STATUS_PLANES     4u   /* automatic N_slab * K exceeds max_planes: zero image   */
+#define TOI_STATUS_OVERFLOW   8u   /* gridding bin lists overflowed: image incomplete       */
 
 typedef struct {
     int32_t  n_pix;        /* N, image side: power of two, 32 .. 8192                       */

@@ -178,8 +178,21 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
     }
 
     const size_t N = c->N, M = c->M, P = c->P_cap, T = c->T;
+    c->NT = c->M / kTile;
+    c->NG_max = std::max(1, (c->P_cap + 7) / 8);
+    c->n_items_max = std::max(1, p.n_row_max * ((p.n_chan + kItemChans - 1) / kItemChans));
+    c->bin_cap = c->n_items_max * 8 + 1024;
+    const size_t NT = c->NT, NG = c->NG_max, words = (NT + 31) / 32;
     struct Alloc { void** ptr; size_t bytes; };
     Alloc allocs[] = {
+        {(void**)&c->items, (size_t)c->n_items_max * sizeof(ItemBox)},
+        {(void**)&c->bin_count, NG * NT * NT * sizeof(int32_t)},
+        {(void**)&c->bin_off, (NG * NT * NT + 1) * sizeof(int32_t)},
+        {(void**)&c->bin_cursor, NG * NT * NT * sizeof(int32_t)},
+        {(void**)&c->bin_list, (size_t)c->bin_cap * sizeof(int32_t)},
+        {(void**)&c->bin_order, NG * NT * NT * sizeof(int32_t)},
+        {(void**)&c->tile_bits, NG * NT * words * sizeof(uint32_t)},
+        {(void**)&c->row_bits, NG * words * sizeof(uint32_t)},
         {(void**)&c->grid, P * M * M * sizeof(float2)},
         {(void**)&c->hbuf, P * N * M * sizeof(float2)},
         {(void**)&c->tplane_t, N * N * sizeof(float)},
@@ -230,7 +243,8 @@ toi_status toi_destroy(toi_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
     if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
-    void* ptrs[] = {c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
+    void* ptrs[] = {c->items, c->bin_order, c->bin_count, c->bin_off, c->bin_cursor, c->bin_list, c->tile_bits, c->row_bits,
+                    c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
                     c->scratch_d, c->scratch_i, c->det_scores, c->det_labels, c->batch_desc};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);

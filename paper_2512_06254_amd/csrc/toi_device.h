@@ -71,11 +71,20 @@ __device__ inline float2 cmul(float2 a, float2 b) {
 __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-// Exponential-of-semicircle gridding kernel on |z| <= 1 (beta = 2.30 * 8).
+// Hardware dispatches workgroup i to XCD i mod 8.  Remap so that each XCD
+// receives a contiguous range of logical ids (neighbouring tiles share its L2).
+__device__ inline int xcd_block_id(int bid, int nblk) {
+    if (nblk % 8) return bid;
+    return (bid & 7) * (nblk >> 3) + (bid >> 3);
+}
+
+// Exponential-of-semicircle gridding kernel on |z| <= 1 (beta = 2.30 * 8):
+// exp(beta (sqrt(1 - z^2) - 1)) = 2^(beta log2(e) (sqrt(1 - z^2) - 1)), with the
+// hardware square root and base-2 exponential (about 1 ulp each).
 __device__ inline float es_kernel(float z) {
-    constexpr float beta = 18.4f;
+    constexpr float beta_log2e = 18.4f * 1.4426950408889634f;
     const float a = fmaxf(1.0f - z * z, 0.0f);
-    return __expf(beta * (__fsqrt_rn(a) - 1.0f));
+    return __builtin_amdgcn_exp2f(beta_log2e * (__builtin_amdgcn_sqrtf(a) - 1.0f));
 }
 
 }  // namespace toi

@@ -127,6 +127,20 @@ __device__ inline void fft_load(float2* v, const float2* __restrict__ src) {
         for (int r = 0; r < R1; ++r) v[b * R1 + r] = src[threadIdx.x + b * T + r * (M / R1)];
 }
 
+// As fft_load, with elements whose index fails pred(i) read as zero (not loaded).
+template <int M, int E, typename Pred>
+__device__ inline void fft_load_masked(float2* v, const float2* __restrict__ src, Pred pred) {
+    constexpr int T = M / E;
+    constexpr int R1 = fft_first_radix(M, E);
+#pragma unroll
+    for (int b = 0; b < E / R1; ++b)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int i = threadIdx.x + b * T + r * (M / R1);
+            v[b * R1 + r] = pred(i) ? src[i] : make_float2(0.f, 0.f);
+        }
+}
+
 // Output slot r (0 <= r < E) of thread t is bin k = t + r T.  With M = 2N the
 // kept bins are a = k (k < N/2) and a = k - M (k >= M - N/2), a in [-N/2, N/2),
 // i.e. the slots r < E/4 and r >= 3E/4.
@@ -142,13 +156,6 @@ __device__ inline int fft_kept_index(int q) {
     const int r = fft_kept_slot<E>(q);
     const int k = threadIdx.x + r * T;
     return (k < M / 4) ? k + M / 4 : k - M + M / 4;
-}
-
-// Hardware dispatches workgroup i to XCD i mod 8.  Remap so that each XCD
-// receives a contiguous range of logical ids (neighbouring tiles share its L2).
-__device__ inline int xcd_block_id(int bid, int nblk) {
-    if (nblk % 8) return bid;
-    return (bid & 7) * (nblk >> 3) + (bid >> 3);
 }
 
 }  // namespace toi

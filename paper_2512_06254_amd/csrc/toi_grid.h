@@ -1,0 +1,119 @@
+// Device helpers shared by the gridder and the degridder: sample selection,
+// per-row track coefficients, slab / plane-group mapping and the Chebyshev
+// recurrence start.
+#pragma once
+
+#include "toi_device.h"
+#include "toi_internal.h"
+
+namespace toi {
+
+constexpr uint32_t kStatusFatal = TOI_STATUS_NO_SAMPLES | TOI_STATUS_DEGENERATE | TOI_STATUS_PLANES;
+
+// Weighted sum of the selected correlations of one (row, channel) sample with
+// flags as zero weight (Section 3.5).  Returns the sample weight w.
+__device__ inline float sample_value(const float2* __restrict__ vis, const float* __restrict__ weight,
+                                     const uint8_t* __restrict__ flag, size_t base, int n_corr, uint32_t mask,
+                                     float& xr, float& xi) {
+    float w = 0.f;
+    xr = 0.f;
+    xi = 0.f;
+    for (int k = 0; k < n_corr; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        float wk = weight ? weight[base + k] : 1.f;
+        if (flag && flag[base + k]) wk = 0.f;
+        const float2 v = vis[base + k];
+        w += wk;
+        xr += wk * v.x;
+        xi += wk * v.y;
+    }
+    return w;
+}
+
+__device__ inline bool sample_kept(const float* __restrict__ weight, const uint8_t* __restrict__ flag, size_t base,
+                                   int n_corr, uint32_t mask) {
+    float w = 0.f;
+    for (int k = 0; k < n_corr; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        float wk = weight ? weight[base + k] : 1.f;
+        if (flag && flag[base + k]) wk = 0.f;
+        w += wk;
+    }
+    return w > 0.f;
+}
+
+// Per-row track: grid coordinates X = M/2 + ax nu, Y = M/2 + ay nu and the
+// residual coordinate r3 = a3 nu (r = V b with b = uvw nu / c).
+struct Track {
+    double ax, ay, a3;
+};
+__device__ inline Track row_track(const double* __restrict__ uvw, int r, const DevPlan* __restrict__ P, int M,
+                                  double cell_rad) {
+    const double u0 = uvw[3 * r], u1 = uvw[3 * r + 1], u2 = uvw[3 * r + 2];
+    const double* V = P->V;
+    const double sc = (double)M * cell_rad / kCLight;
+    Track t;
+    t.ax = -(V[0] * u0 + V[1] * u1 + V[2] * u2) * sc;
+    t.ay = (V[3] * u0 + V[4] * u1 + V[5] * u2) * sc;
+    t.a3 = (V[6] * u0 + V[7] * u1 + V[8] * u2) / kCLight;
+    return t;
+}
+
+// g[ant1] conj(g[ant2]) of a row; an antenna index outside [0, n_ant) gives 0.
+__device__ inline float2 row_gain(const float2* __restrict__ gains, const int32_t* __restrict__ ant1,
+                                  const int32_t* __restrict__ ant2, int n_ant, int r) {
+    if (!gains) return make_float2(1.f, 0.f);
+    const int a1 = ant1[r], a2 = ant2[r];
+    if (a1 < 0 || a1 >= n_ant || a2 < 0 || a2 >= n_ant) return make_float2(0.f, 0.f);
+    const float2 g1 = gains[a1], g2 = gains[a2];
+    return cmul(g1, make_float2(g2.x, -g2.y));
+}
+
+// Slab of a residual coordinate: p = min(N_slab - 1, floor((r3 - r3min) / (2 dr3))).
+__device__ inline int slab_index(double r3, const DevPlan* __restrict__ P) {
+    if (!(P->dr3 > 0.0)) return 0;
+    int p = (int)floor((r3 - P->r3min) / (2.0 * P->dr3));
+    return max(0, min(P->n_slab - 1, p));
+}
+
+// Plane groups: whole slabs (sg of them) when K <= kGroupPlanes, otherwise
+// two groups per slab holding orders [0, kp) and [kp, K).
+__device__ inline int group_of_slab(int p, const DevPlan* __restrict__ P) {
+    return P->K <= kGroupPlanes ? p / P->sg : 2 * p;
+}
+__device__ inline int group_of_plane(int plane, const DevPlan* __restrict__ P) {
+    const int p = plane / P->K, k = plane % P->K;
+    return P->K <= kGroupPlanes ? p / P->sg : 2 * p + (k >= P->kp ? 1 : 0);
+}
+__device__ inline void group_range(int g, const DevPlan* __restrict__ P, int& s0, int& s1, int& k0, int& k1) {
+    if (P->K <= kGroupPlanes) {
+        s0 = g * P->sg;
+        s1 = min(P->n_slab, s0 + P->sg);
+        k0 = 0;
+        k1 = P->K;
+    } else {
+        s0 = g / 2;
+        s1 = s0 + 1;
+        k0 = (g & 1) ? P->kp : 0;
+        k1 = (g & 1) ? P->K : P->kp;
+    }
+}
+
+// Chebyshev recurrence T_{k+1} = 2 s T_k - T_{k-1} started at order k0:
+// returns t = T_{k0}(s) and tm1 = T_{k0-1}(s) (T_{-1} = T_1).
+__device__ inline void cheb_start(float s, int k0, float& t, float& tm1) {
+    if (k0 == 0) {
+        t = 1.f;
+        tm1 = s;
+        return;
+    }
+    tm1 = 1.f;
+    t = s;
+    for (int k = 1; k < k0; ++k) {
+        const float tn = 2.f * s * t - tm1;
+        tm1 = t;
+        t = tn;
+    }
+}
+
+}  // namespace toi

@@ -1,126 +1,304 @@
 // S4: gridding of the Chebyshev moment planes M_{p,k} (Section 3.4) with an
 // exponential-of-semicircle kernel of support 8 on a periodic 2N x 2N grid.
 //
-// Work distribution: one wavefront per (row, channel chunk).  A row's samples
-// lie on a radial track (b = uvw nu / c), so consecutive channels land on
-// nearby grid cells.  Lane (i, j) of the wavefront owns the cells with
-// x = i and y = j modulo 8; for every sample exactly one cell of each lane's
-// residue class lies inside the 8 x 8 footprint.  Each lane accumulates its
-// current cell's K plane values in registers and adds them to the grid only
-// when the track moves its cell (or slab), so one global atomic replaces many
-// (Romein, ICS 2012, "An efficient work-distribution strategy for gridding
-// radio-telescope data on GPUs").
+// Tile-owner design, no global float atomics:
+//  1. Work items are runs of kItemChans channels of one row.  A row's samples
+//     lie on a radial track (b = uvw nu / c), so an item's 8 x 8 footprints
+//     cover a small box; k_items computes the box and the slabs it touches and
+//     counts the item into every (plane group, 32 x 32 tile) bin it overlaps.
+//  2. k_bin_scan turns the counts into list offsets and occupancy bit masks;
+//     k_bin_fill writes the item lists.
+//  3. k_grid_tiles: one workgroup per (group, tile) accumulates the tile's
+//     planes in LDS and writes it to HBM once.  Inside a workgroup each
+//     wavefront walks one item at a time: lane (i, j) owns the cells with
+//     x = i, y = j (mod 8), exactly one of which lies in every footprint, and
+//     keeps that cell's plane values in registers until the track moves it
+//     (Romein, ICS 2012), then adds them to LDS.
+// Tiles without samples are never written; the FFT passes read the
+// occupancy masks and treat them as zero.
 //
 // Coordinates are formed in FP64 (X = M/2 - r1 M Delta, Y = M/2 + r2 M Delta)
 // and split into an integer cell and an FP32 offset before the kernel is
 // evaluated; values and accumulation are FP32.
-#include "toi_internal.h"
 #include "toi_device.h"
+#include "toi_grid.h"
+#include "toi_internal.h"
 
 namespace toi {
 
-__global__ __launch_bounds__(256) void k_fill_zero(float4* __restrict__ p, size_t n4) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+__global__ __launch_bounds__(256) void k_fill_zero_i32(int32_t* __restrict__ p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-template <int KMAX>
-__global__ __launch_bounds__(256) void k_grid_tracks(
+// ---------------------------------------------------------------- 1. items
+__global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, const float* __restrict__ weight,
+                                               const uint8_t* __restrict__ flag, const double* __restrict__ freq,
+                                               int n_chan, int n_corr, uint32_t mask, int mode,
+                                               const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
+                                               int n_items, ItemBox* __restrict__ items,
+                                               int32_t* __restrict__ bin_count) {
+    const int lane = threadIdx.x & 63;
+    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= n_items) return;
+    const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
+    const int r = item / n_chunks;
+    const int c = (item % n_chunks) * kItemChans + lane;
+    ItemBox box;
+    box.tx0 = 1; box.tx1 = 0; box.ty0 = 1; box.ty1 = 0; box.g0 = 1; box.g1 = 0;
+    box.pad_[0] = box.pad_[1] = 0;
+    if (P->status) {
+        if (lane == 0) items[item] = box;
+        return;
+    }
+    const Track tr = row_track(uvw, r, P, M, cell_rad);
+    double xlo = 1e300, xhi = -1e300, ylo = 1e300, yhi = -1e300, rlo = 1e300, rhi = -1e300;
+    if (c < n_chan && sample_kept(weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask)) {
+        const double nu = freq[c];
+        xlo = xhi = 0.5 * M + tr.ax * nu;
+        ylo = yhi = 0.5 * M + tr.ay * nu;
+        rlo = rhi = tr.a3 * nu;
+    }
+    xlo = wave_min(xlo); xhi = wave_max(xhi);
+    ylo = wave_min(ylo); yhi = wave_max(yhi);
+    rlo = wave_min(rlo); rhi = wave_max(rhi);
+    if (xlo > xhi) {   // no kept sample
+        if (lane == 0) items[item] = box;
+        return;
+    }
+    // footprint cells [ceil(X - 4), ceil(X - 4) + 7] -> tiles (floor division)
+    box.tx0 = ((int)ceil(xlo - 4.0)) >> 5;
+    box.tx1 = ((int)ceil(xhi - 4.0) + 7) >> 5;
+    box.ty0 = ((int)ceil(ylo - 4.0)) >> 5;
+    box.ty1 = ((int)ceil(yhi - 4.0) + 7) >> 5;
+    const int p0 = mode == 3 ? slab_index(rlo, P) : 0, p1 = mode == 3 ? slab_index(rhi, P) : 0;
+    box.g0 = group_of_slab(min(p0, p1), P);
+    box.g1 = group_of_slab(max(p0, p1), P) + ((P->K > kGroupPlanes) ? 1 : 0);
+    if (lane == 0) items[item] = box;
+    // count into bins, lanes spread over the (group, tile) combinations
+    const int nx = box.tx1 - box.tx0 + 1, ny = box.ty1 - box.ty0 + 1, ng = box.g1 - box.g0 + 1;
+    const int tiles = NT * NT;
+    for (int e = lane; e < nx * ny * ng; e += 64) {
+        const int tx = (box.tx0 + e % nx) & (NT - 1);
+        const int ty = (box.ty0 + (e / nx) % ny) & (NT - 1);
+        const int g = box.g0 + e / (nx * ny);
+        atomicAdd(&bin_count[(size_t)g * tiles + ty * NT + tx], 1);
+    }
+}
+
+// ---------------------------------------------------------------- 2. scan
+// One workgroup of 1024 threads: exclusive scan of the counts, bin cursors and
+// occupancy masks (tile_bits[g][ty][tx/32], row_bits[g][ty/32]).
+__global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* __restrict__ count, int n_bins, int NT,
+                                                   int bin_cap, DevPlan* __restrict__ P, int32_t* __restrict__ off,
+                                                   int32_t* __restrict__ cursor, uint32_t* __restrict__ tile_bits,
+                                                   uint32_t* __restrict__ row_bits, int32_t* __restrict__ order,
+                                                   int32_t* __restrict__ n_active) {
+    __shared__ int32_t part[1024];
+    __shared__ int32_t hist[32];
+    const int per = (n_bins + 1023) / 1024;
+    const int b0 = min(n_bins, (int)threadIdx.x * per), b1 = min(n_bins, b0 + per);
+    int s = 0;
+    for (int i = b0; i < b1; ++i) s += count[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive Hillis-Steele scan of the partial sums
+        const int v = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = part[threadIdx.x] - s;
+    for (int i = b0; i < b1; ++i) {
+        off[i] = run;
+        cursor[i] = run;
+        run += count[i];
+    }
+    if (threadIdx.x == 1023) {
+        off[n_bins] = part[1023];
+        if (part[1023] > bin_cap) atomicOr(&P->status, (uint32_t)TOI_STATUS_OVERFLOW);
+    }
+    // launch order of the non-empty bins: heaviest first, bucketed by floor(log2(count))
+    if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = b0; i < b1; ++i)
+        if (count[i] > 0) atomicAdd(&hist[31 - __clz(count[i])], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int b = 31; b >= 0; --b) {
+            const int h = hist[b];
+            hist[b] = acc;
+            acc += h;
+        }
+        *n_active = acc;
+    }
+    __syncthreads();
+    for (int i = b0; i < b1; ++i)
+        if (count[i] > 0) order[atomicAdd(&hist[31 - __clz(count[i])], 1)] = i;
+    // occupancy masks
+    const int words = (NT + 31) / 32;
+    const int n_groups = n_bins / (NT * NT);
+    for (int w = threadIdx.x; w < n_groups * NT * words; w += blockDim.x) {
+        const int g = w / (NT * words), ty = (w / words) % NT, wd = w % words;
+        uint32_t bits = 0;
+        for (int b = 0; b < 32 && wd * 32 + b < NT; ++b)
+            if (count[(size_t)g * NT * NT + ty * NT + wd * 32 + b] > 0) bits |= 1u << b;
+        tile_bits[w] = bits;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < n_groups * words; w += blockDim.x) {
+        const int g = w / words, wd = w % words;
+        uint32_t bits = 0;
+        for (int b = 0; b < 32 && wd * 32 + b < NT; ++b) {
+            const int ty = wd * 32 + b;
+            uint32_t any = 0;
+            for (int x = 0; x < words; ++x) any |= tile_bits[((size_t)g * NT + ty) * words + x];
+            if (any) bits |= 1u << b;
+        }
+        row_bits[w] = bits;
+    }
+}
+
+// ---------------------------------------------------------------- 2b. fill
+__global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ items, int n_items, int NT,
+                                                  int bin_cap, int32_t* __restrict__ cursor,
+                                                  int32_t* __restrict__ list) {
+    const int lane = threadIdx.x & 63;
+    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= n_items) return;
+    const ItemBox box = items[item];
+    if (box.tx0 > box.tx1) return;
+    const int nx = box.tx1 - box.tx0 + 1, ny = box.ty1 - box.ty0 + 1, ng = box.g1 - box.g0 + 1;
+    const int tiles = NT * NT;
+    for (int e = lane; e < nx * ny * ng; e += 64) {
+        const int tx = (box.tx0 + e % nx) & (NT - 1);
+        const int ty = (box.ty0 + (e / nx) % ny) & (NT - 1);
+        const int g = box.g0 + e / (nx * ny);
+        const int pos = atomicAdd(&cursor[(size_t)g * tiles + ty * NT + tx], 1);
+        if (pos < bin_cap) list[pos] = item;
+    }
+}
+
+// ---------------------------------------------------------------- 3. tiles
+template <int KACC>
+__global__ __launch_bounds__(512) void k_grid_tiles(
     const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
     const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
-    const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_row, int n_chan, int n_corr,
-    uint32_t mask, int chunk, int mode, const DevPlan* __restrict__ plan, float2* __restrict__ grid, int M,
-    double cell_rad) {
-    const int lane = threadIdx.x & 63;
-    const int n_chunks = (n_chan + chunk - 1) / chunk;
-    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int r = item / n_chunks;
-    if (r >= n_row) return;
-    if (plan->status) return;                 // nothing to grid: the planes stay zero
-    const int c0 = (item % n_chunks) * chunk;
-    const int c1 = min(n_chan, c0 + chunk);
-    const int K = plan->K, ns = plan->n_slab;
-    const double dr3 = plan->dr3, r3min = plan->r3min;
-    const double u0 = uvw[3 * r], u1 = uvw[3 * r + 1], u2 = uvw[3 * r + 2];
-    const double* V = plan->V;
-    const double sc = (double)M * cell_rad / kCLight;
-    const double ax = -(V[0] * u0 + V[1] * u1 + V[2] * u2) * sc;     // X = M/2 + ax nu
-    const double ay = (V[3] * u0 + V[4] * u1 + V[5] * u2) * sc;      // Y = M/2 + ay nu
-    const double a3 = (V[6] * u0 + V[7] * u1 + V[8] * u2) / kCLight; // r3 = a3 nu
-    float2 g = make_float2(1.f, 0.f);
-    if (gains) {   // an antenna index outside [0, n_ant) gives the row a zero gain
-        const int a1 = ant1[r], a2 = ant2[r];
-        if (a1 >= 0 && a1 < n_ant && a2 >= 0 && a2 < n_ant) {
-            const float2 g1 = gains[a1], g2 = gains[a2];
-            g = cmul(g1, make_float2(g2.x, -g2.y));
-        } else {
-            g = make_float2(0.f, 0.f);
-        }
-    }
+    const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_chan, int n_corr,
+    uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
+    const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ n_active, float2* __restrict__ grid) {
+    extern __shared__ float lds[];                      // [planes][kTile][kTile] x (re, im)
+    const int tiles = NT * NT;
+    // Non-empty bins in decreasing order of work, dealt round-robin over the
+    // XCDs by the dispatcher (tiles with samples cluster around the uv centre,
+    // so contiguous ranges per XCD would leave most XCDs idle).
+    if ((int)blockIdx.x >= *n_active) return;
+    const int bid = order[blockIdx.x];
+    const int g = bid / tiles, tile = bid % tiles;
+    if (P->status & kStatusFatal) return;
+    if (g >= P->ng) return;
+    const int b0 = bin_off[(size_t)g * tiles + tile];
+    const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
+    if (b1 <= b0) return;                               // empty tile: never written
+    int s0, s1, k0, k1;
+    group_range(g, P, s0, s1, k0, k1);
+    const int nk = k1 - k0;
+    const int n_planes = (s1 - s0) * nk;
+    for (int i = threadIdx.x; i < n_planes * kTile * kTile * 2; i += blockDim.x) lds[i] = 0.f;
+    __syncthreads();
+
+    const int tx = tile % NT, ty = tile / NT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
     const int li = lane & 7, lj = lane >> 3;
     const double half = 0.5 * M;
-    const bool cheb = (mode == 3) && (dr3 > 0.0);
+    const bool cheb = (mode == 3) && (P->dr3 > 0.0);
+    const double dr3 = P->dr3, r3min = P->r3min;
+    const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
 
-    int cur_x = 0, cur_y = 0, cur_p = -1;
-    float ar[KMAX], ai[KMAX];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
-
-    auto flush = [&]() {
-        const size_t cell = (size_t)(cur_y & (M - 1)) * M + (cur_x & (M - 1));
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            if (k < K) {
-                float* dst = reinterpret_cast<float*>(grid + (size_t)(cur_p * K + k) * M * M + cell);
-                unsafeAtomicAdd(dst, ar[k]);
-                unsafeAtomicAdd(dst + 1, ai[k]);
+    for (int it = b0 + wave; it < b1; it += n_waves) {
+        const int item = list[it];
+        const int r = item / n_chunks;
+        const int c0 = (item % n_chunks) * kItemChans, c1 = min(n_chan, c0 + kItemChans);
+        const Track trk = row_track(uvw, r, P, M, cell_rad);
+        const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
+        // lane-parallel prefetch: lane l prepares channel c0 + l (FP64 coordinates once per sample)
+        int ix = 0, iy = 0, sp = 0;
+        float ox = 0.f, oy = 0.f, vr0 = 0.f, vi0 = 0.f, ss = 0.f;
+        bool act = false;
+        {
+            const int c = c0 + lane;
+            if (c < c1) {
+                float xr, xi;
+                const float w =
+                    sample_value(vis, weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask, xr, xi);
+                if (w > 0.f) {
+                    const double nu = freq[c];
+                    if (cheb) {
+                        const double r3 = trk.a3 * nu;
+                        sp = slab_index(r3, P);
+                        ss = (float)((r3 - (r3min + (2 * sp + 1) * dr3)) / dr3);
+                    }
+                    const double X = half + trk.ax * nu, Y = half + trk.ay * nu;
+                    const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
+                    ix = (int)fx0;
+                    iy = (int)fy0;
+                    ox = (float)(X - fx0);                 // in (3, 4]
+                    oy = (float)(Y - fy0);
+                    // does the 8 x 8 footprint touch this tile (periodic grid)?
+                    const int ddx = (ix - tx * kTile) & (M - 1), ddy = (iy - ty * kTile) & (M - 1);
+                    act = (sp >= s0 && sp < s1) && (ddx < kTile || ddx >= M - 7) && (ddy < kTile || ddy >= M - 7);
+                    vr0 = xr * gr.x - xi * gr.y;
+                    vi0 = xr * gr.y + xi * gr.x;
+                }
             }
         }
-    };
+        uint64_t pending = __ballot(act);
+        int cur_x = 0, cur_y = 0, cur_p = -1;
+        bool cur_in = false;
+        float ar[KACC], ai[KACC];
+#pragma unroll
+        for (int k = 0; k < KACC; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
 
-    for (int c = c0; c < c1; ++c) {
-        const size_t base = ((size_t)r * n_chan + c) * n_corr;
-        float w = 0.f, xr = 0.f, xi = 0.f;
-        for (int k = 0; k < n_corr; ++k) {
-            if (!((mask >> k) & 1u)) continue;
-            float wk = weight ? weight[base + k] : 1.f;
-            if (flag && flag[base + k]) wk = 0.f;
-            const float2 v = vis[base + k];
-            w += wk;
-            xr += wk * v.x;
-            xi += wk * v.y;
-        }
-        if (!(w > 0.f)) continue;
-        const float vr0 = xr * g.x - xi * g.y, vi0 = xr * g.y + xi * g.x;
-        const double nu = freq[c];
-        const double X = half + ax * nu, Y = half + ay * nu;
-        const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
-        const int ix0 = (int)fx0, iy0 = (int)fy0;
-        const float ox = (float)(X - fx0), oy = (float)(Y - fy0);    // in (3, 4]
-        const int dx = (li - ix0) & 7, dy = (lj - iy0) & 7;
-        const int cx = ix0 + dx, cy = iy0 + dy;
-        const float wgt = es_kernel(((float)dx - ox) * 0.25f) * es_kernel(((float)dy - oy) * 0.25f);
-        int p = 0;
-        float s = 0.f;
-        if (cheb) {
-            const double r3 = a3 * nu;
-            p = (int)floor((r3 - r3min) / (2.0 * dr3));
-            p = max(0, min(ns - 1, p));
-            s = (float)((r3 - (r3min + (2 * p + 1) * dr3)) / dr3);
-        }
-        if (cx != cur_x || cy != cur_y || p != cur_p) {
-            if (cur_p >= 0) flush();
-            cur_x = cx; cur_y = cy; cur_p = p;
+        auto flush = [&]() {
+            if (!cur_in) return;
+            const int lx = cur_x & (kTile - 1), ly = cur_y & (kTile - 1);
+            float* base = lds + 2 * ((size_t)((cur_p - s0) * nk) * kTile * kTile + ly * kTile + lx);
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
-        }
-        const float vr = wgt * vr0, vi = wgt * vi0;
-        ar[0] += vr;
-        ai[0] += vi;
-        if (KMAX > 1) {
-            float tm1 = 1.f, t = s;
+            for (int k = 0; k < KACC; ++k) {
+                if (k < nk) {
+                    atomicAdd(base + 2 * (size_t)k * kTile * kTile, ar[k]);
+                    atomicAdd(base + 2 * (size_t)k * kTile * kTile + 1, ai[k]);
+                }
+            }
+        };
+
+        while (pending) {                               // wave-uniform walk over the active samples
+            const int q = __ffsll((unsigned long long)pending) - 1;
+            pending &= pending - 1;
+            const int qx = __builtin_amdgcn_readlane(ix, q), qy = __builtin_amdgcn_readlane(iy, q);
+            const int p = __builtin_amdgcn_readlane(sp, q);
+            const float qox = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ox), q));
+            const float qoy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(oy), q));
+            const float qvr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vr0), q));
+            const float qvi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vi0), q));
+            const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ss), q));
+            const int dx = (li - qx) & 7, dy = (lj - qy) & 7;
+            const int cx = qx + dx, cy = qy + dy;
+            if (cx != cur_x || cy != cur_y || p != cur_p) {
+                flush();
+                cur_x = cx; cur_y = cy; cur_p = p;
+                cur_in = (((cx & (M - 1)) >> 5) == tx) && (((cy & (M - 1)) >> 5) == ty);
 #pragma unroll
-            for (int k = 1; k < KMAX; ++k) {
+                for (int k = 0; k < KACC; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
+            }
+            if (!cur_in) continue;
+            const float wgt = es_kernel(((float)dx - qox) * 0.25f) * es_kernel(((float)dy - qoy) * 0.25f);
+            const float vr = wgt * qvr, vi = wgt * qvi;
+            float t, tm1;
+            cheb_start(s, k0, t, tm1);                  // t = T_{k0}(s), tm1 = T_{k0 - 1}(s)
+#pragma unroll
+            for (int k = 0; k < KACC; ++k) {
                 ar[k] += t * vr;
                 ai[k] += t * vi;
                 const float tn = 2.f * s * t - tm1;
@@ -128,37 +306,56 @@ __global__ __launch_bounds__(256) void k_grid_tracks(
                 t = tn;
             }
         }
+        flush();
     }
-    if (cur_p >= 0) flush();
+    __syncthreads();
+    // write the tile's planes (only the planes of this group)
+    for (int i = threadIdx.x; i < n_planes * kTile * kTile; i += blockDim.x) {
+        const int pl = i / (kTile * kTile), cell = i % (kTile * kTile);
+        const int pg = (s0 + pl / nk) * P->K + k0 + pl % nk;   // global plane index
+        const int y = ty * kTile + cell / kTile, x = tx * kTile + cell % kTile;
+        grid[((size_t)pg * M + y) * M + x] = make_float2(lds[2 * i], lds[2 * i + 1]);
+    }
 }
 
 hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
     const toi_params& p = c->p;
-    const size_t M = c->M;
-    const size_t n4 = (size_t)c->P_cap * M * M * sizeof(float2) / sizeof(float4);
-    {
-        StageTimer timer(c, TOI_STAGE_CLEAR);
-        hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, c->stream, (float4*)c->grid, n4);
-    }
-    if (s.n_row == 0) return hipGetLastError();
-    StageTimer timer(c, TOI_STAGE_GRID);
-    const int chunk = 64;
-    const int n_chunks = (p.n_chan + chunk - 1) / chunk;
-    const long items = (long)s.n_row * n_chunks;
-    const int blocks = (int)((items + 3) / 4);
+    const int M = c->M, NT = c->NT;
     const double cell = p.cell_deg * kPi / 180.0;
-#define TOI_GRID_ARGS                                                                                  \
-    dim3(blocks), dim3(256), 0, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, \
-        s.ant2, (const float2*)s.gains, p.n_ant, s.n_row, p.n_chan, p.n_corr, p.corr_mask, chunk, p.mode, c->plan,  \
-        c->grid, (int)M, cell
-    switch (c->kmax) {
-        case 1: hipLaunchKernelGGL(k_grid_tracks<1>, TOI_GRID_ARGS); break;
-        case 4: hipLaunchKernelGGL(k_grid_tracks<4>, TOI_GRID_ARGS); break;
-        case 8: hipLaunchKernelGGL(k_grid_tracks<8>, TOI_GRID_ARGS); break;
-        case 16: hipLaunchKernelGGL(k_grid_tracks<16>, TOI_GRID_ARGS); break;
-        default: hipLaunchKernelGGL(k_grid_tracks<32>, TOI_GRID_ARGS); break;
+    const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;
+    const int n_items = s.n_row * n_chunks;
+    const int n_bins = c->NG_max * NT * NT;
+    {
+        StageTimer timer(c, TOI_STAGE_CLEAR);   // binning
+        hipLaunchKernelGGL(k_fill_zero_i32, dim3(256), dim3(256), 0, c->stream, c->bin_count, n_bins);
+        if (n_items > 0)
+            hipLaunchKernelGGL(k_items, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw, s.weight, s.flag,
+                               s.freq, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, NT, cell, n_items,
+                               c->items, c->bin_count);
+        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, c->bin_count, n_bins, NT, c->bin_cap,
+                           c->plan, c->bin_off, c->bin_cursor, c->tile_bits, c->row_bits, c->bin_order,
+                           c->scratch_i);
+        if (n_items > 0)
+            hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, c->items, n_items, NT,
+                               c->bin_cap, c->bin_cursor, c->bin_list);
     }
-#undef TOI_GRID_ARGS
+    if (n_items == 0) return hipGetLastError();
+    StageTimer timer(c, TOI_STAGE_GRID);
+    const size_t lds_bytes = (size_t)kGroupPlanes * kTile * kTile * 2 * sizeof(float);
+    const int blocks = n_bins;
+#define TOI_TILE_ARGS                                                                                         \
+    dim3(blocks), dim3(512), lds_bytes, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag, s.freq,      \
+        s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, NT, \
+        cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
+    if (c->kmax <= 1)
+        hipLaunchKernelGGL(k_grid_tiles<1>, TOI_TILE_ARGS);
+    else if (c->kmax <= 4)
+        hipLaunchKernelGGL(k_grid_tiles<4>, TOI_TILE_ARGS);
+    else if (c->kmax <= 8)
+        hipLaunchKernelGGL(k_grid_tiles<8>, TOI_TILE_ARGS);
+    else
+        hipLaunchKernelGGL(k_grid_tiles<16>, TOI_TILE_ARGS);
+#undef TOI_TILE_ARGS
     return hipGetLastError();
 }
 

@@ -4,11 +4,14 @@
 //
 // Row pass (per plane, bands of B grid rows): FFT along x, keep the N central
 // bins and write them column-major per plane, hbuf[plane][j1][y], so that the
-// column pass reads each column as one contiguous 8M-byte run.
+// column pass reads each column as one contiguous 8M-byte run.  Grid tiles the
+// gridder did not write (no samples) are read as zero, bands of empty tile
+// rows are skipped and their hbuf rows read as zero by the column pass.
 // Column pass (one image column j1 per workgroup): for every plane, FFT along
 // y, keep the N central bins, and fold the plane into the pixel's combination
 // in registers; only the real t-plane image leaves the workgroup.
 #include "toi_fft.h"
+#include "toi_grid.h"
 #include "toi_internal.h"
 
 namespace toi {
@@ -16,19 +19,29 @@ namespace toi {
 template <int M, int E, int B>
 __global__ __launch_bounds__(M / E) void k_fft_rows(const float2* __restrict__ grid, float2* __restrict__ hbuf,
                                                     const float2* __restrict__ tw,
-                                                    const DevPlan* __restrict__ plan, int nbands) {
+                                                    const DevPlan* __restrict__ plan, int nbands,
+                                                    const uint32_t* __restrict__ tile_bits,
+                                                    const uint32_t* __restrict__ row_bits) {
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
+    constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[M];
+    __shared__ uint32_t tb[WORDS];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
     const int plane = id / nbands, band = id % nbands;
-    if (plan->status || plane >= plan->planes) return;
+    if ((plan->status & kStatusFatal) || plane >= plan->planes) return;
+    const int g = group_of_plane(plane, plan);
+    const int ty = (band * B) / kTile;
+    if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) return;   // empty tile row
+    if (threadIdx.x < WORDS) tb[threadIdx.x] = tile_bits[((size_t)g * NT + ty) * WORDS + threadIdx.x];
+    __syncthreads();
+    auto occupied = [&](int x) { return (tb[x >> 10] >> ((x >> 5) & 31)) & 1u; };
     float2 keep[B][KEEP];
 #pragma unroll
     for (int rb = 0; rb < B; ++rb) {
         const int y = band * B + rb;
         float2 v[E];
-        fft_load<M, E>(v, grid + ((size_t)plane * M + y) * M);
+        fft_load_masked<M, E>(v, grid + ((size_t)plane * M + y) * M, occupied);
         fft_stages<M, E, 1>(v, lds, tw);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) keep[rb][q] = v[fft_kept_slot<E>(q)];
@@ -58,16 +71,21 @@ __global__ __launch_bounds__(M / E) void k_fft_rows(const float2* __restrict__ g
 template <int M, int E>
 __global__ __launch_bounds__(M / E) void k_fft_cols(const float2* __restrict__ hbuf, float* __restrict__ tplane_t,
                                                     const float2* __restrict__ tw, const float* __restrict__ corr,
-                                                    const DevPlan* __restrict__ plan, float cell_rad, int mode) {
+                                                    const DevPlan* __restrict__ plan, float cell_rad, int mode,
+                                                    const uint32_t* __restrict__ row_bits, int ng_cap) {
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
+    constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[M];
+    extern __shared__ uint32_t rb_s[];                 // [ng][WORDS] nonempty tile rows per group
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
     int j2[KEEP];
 #pragma unroll
     for (int q = 0; q < KEEP; ++q) j2[q] = fft_kept_index<M, E>(q);
     float* out = tplane_t + (size_t)j1 * N;
-    if (plan->status) {
+    for (int i = threadIdx.x; i < ng_cap * WORDS; i += blockDim.x) rb_s[i] = row_bits[i];
+    __syncthreads();
+    if (plan->status & kStatusFatal) {
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) out[j2[q]] = 0.f;
         return;
@@ -80,7 +98,7 @@ __global__ __launch_bounds__(M / E) void k_fft_cols(const float2* __restrict__ h
 
     if (mode == 2) {
         float2 v[E];
-        fft_load<M, E>(v, hbuf + (size_t)j1 * M);
+        fft_load_masked<M, E>(v, hbuf + (size_t)j1 * M, [&](int y) { return (rb_s[y >> 10] >> ((y >> 5) & 31)) & 1u; });
         fft_stages<M, E, 1>(v, lds, tw);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) tr[q] = v[fft_kept_slot<E>(q)].x;
@@ -127,7 +145,9 @@ __global__ __launch_bounds__(M / E) void k_fft_cols(const float2* __restrict__ h
             // orders K-1 .. 0 with their planes
             for (int k = K - 1; k >= 0; --k) {
                 float2 v[E];
-                fft_load<M, E>(v, hbuf + ((size_t)(p * K + k) * N + j1) * M);
+                const uint32_t* rbg = rb_s + group_of_plane(p * K + k, plan) * WORDS;
+                fft_load_masked<M, E>(v, hbuf + ((size_t)(p * K + k) * N + j1) * M,
+                                      [&](int y) { return (rbg[y >> 10] >> ((y >> 5) & 31)) & 1u; });
                 fft_stages<M, E, 1>(v, lds, tw);
 #pragma unroll
                 for (int q = 0; q < KEEP; ++q) {
@@ -191,7 +211,7 @@ __global__ __launch_bounds__(256) void k_reproject(const float* __restrict__ tpl
     const int j2 = blockIdx.y;
     if (j1 >= N) return;
     float val = 0.f;
-    if (!plan->status) {
+    if (!(plan->status & kStatusFatal)) {
         const double l = -cell_rad * (j1 - N / 2), m = cell_rad * (j2 - N / 2);
         const double rho2 = l * l + m * m;
         if (rho2 < 1.0) {
@@ -231,12 +251,14 @@ static hipError_t launch_fft_passes(toi_ctx* c) {
     {
         StageTimer timer(c, TOI_STAGE_FFT_ROWS);
         hipLaunchKernelGGL((k_fft_rows<M, E, B>), dim3(nbands * P), dim3(M / E), 0, c->stream, c->grid,
-                           c->hbuf, c->twiddle, c->plan, nbands);
+                           c->hbuf, c->twiddle, c->plan, nbands, c->tile_bits, c->row_bits);
     }
     const float cell = (float)(c->p.cell_deg * kPi / 180.0);
     StageTimer timer(c, TOI_STAGE_FFT_COLS);
-    hipLaunchKernelGGL((k_fft_cols<M, E>), dim3(M / 2), dim3(M / E), 0, c->stream, c->hbuf, c->tplane_t,
-                       c->twiddle, c->corr, c->plan, cell, c->p.mode);
+    const int words = (c->NT + 31) / 32;
+    hipLaunchKernelGGL((k_fft_cols<M, E>), dim3(M / 2), dim3(M / E), c->NG_max * words * sizeof(uint32_t),
+                       c->stream, c->hbuf, c->tplane_t, c->twiddle, c->corr, c->plan, cell, c->p.mode, c->row_bits,
+                       c->NG_max);
     return hipGetLastError();
 }
 

@@ -32,7 +32,21 @@ struct DevPlan {
     int32_t n_slab, K, planes;
     uint32_t status;
     int32_t miller_top;   // starting order of the Bessel backward recurrence
-    int32_t pad_[3];
+    int32_t ng;           // plane groups gridded together (<= kGroupPlanes planes each)
+    int32_t sg;           // slabs per group when K <= kGroupPlanes
+    int32_t kp;           // Chebyshev orders per group when K > kGroupPlanes
+};
+
+// Binned gridding: grid tiles of kTile x kTile cells, work items of kItemChans
+// channels of one row, up to kGroupPlanes planes accumulated per tile pass.
+constexpr int kTile = 32;
+constexpr int kItemChans = 64;
+constexpr int kGroupPlanes = 16;
+
+// Bin of one work item: tile and group ranges it touches (unwrapped tile
+// indices; wrapped modulo the tiles per axis when used).
+struct ItemBox {
+    int32_t tx0, tx1, ty0, ty1, g0, g1, pad_[2];
 };
 
 // Per-row partial sums of the kept samples (sample prep).
@@ -62,7 +76,19 @@ struct toi_ctx {
     std::string err;
 
     // workspace (device)
-    float2* grid;         // [P_cap][M][M]
+    float2* grid;         // [P_cap][M][M]   only tiles with samples are written
+    int NT;               // grid tiles per axis (M / kTile)
+    int NG_max;           // plane-group capacity
+    int n_items_max;      // work items capacity (n_row_max * chunks)
+    toi::ItemBox* items;  // [n_items_max]
+    int32_t* bin_count;   // [NG_max][NT*NT]
+    int32_t* bin_off;     // [NG_max][NT*NT + 1]
+    int32_t* bin_cursor;  // [NG_max][NT*NT]
+    int32_t* bin_list;    // [bin capacity]
+    int32_t* bin_order;   // [NG_max][NT*NT] non-empty bins, heaviest first (count in scratch_i[0])
+    int bin_cap;
+    uint32_t* tile_bits;  // [NG_max][NT][NT/32]  nonempty tiles of each tile row
+    uint32_t* row_bits;   // [NG_max][NT/32]      nonempty tile rows
     float2* hbuf;         // [P_cap][N][M]   row-pass output, column major per plane
     float* tplane_t;      // [N][N]          transformed-plane image, j1 major
     toi::DevPlan* plan;

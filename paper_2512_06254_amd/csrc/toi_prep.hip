@@ -159,6 +159,9 @@ __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, c
         P.n_slab = 1;
         P.K = 1;
         P.planes = 1;
+        P.ng = 1;
+        P.sg = kGroupPlanes;
+        P.kp = 1;
         P.status = st;
         *plan = P;
         for (int i = 0; i < 9; ++i) V_s[i] = P.V[i];
@@ -262,7 +265,7 @@ __device__ double cheb_sampled_error(double alpha_slab, int K, double* red) {
 }
 
 __global__ __launch_bounds__(256) void k_plan(double alpha_target, double gamma, int forced_slab,
-                                              int forced_k, int p_cap, DevPlan* __restrict__ plan) {
+                                              int forced_k, int p_cap, int ng_cap, DevPlan* __restrict__ plan) {
     __shared__ double red[4];
     __shared__ double a_slab;
     if (plan->status & TOI_STATUS_NO_SAMPLES) return;
@@ -292,7 +295,16 @@ __global__ __launch_bounds__(256) void k_plan(double alpha_target, double gamma,
         plan->K = K;
         plan->planes = plan->n_slab * K;
         plan->miller_top = 2 * ((K + 16 + (int)ceil(1.5 * fabs(a_slab))) / 2);
-        if (plan->planes > p_cap) plan->status |= TOI_STATUS_PLANES;
+        if (K <= kGroupPlanes) {
+            plan->sg = kGroupPlanes / K;
+            plan->kp = K;
+            plan->ng = (plan->n_slab + plan->sg - 1) / plan->sg;
+        } else {
+            plan->sg = 1;
+            plan->kp = (K + 1) / 2;
+            plan->ng = 2 * plan->n_slab;
+        }
+        if (plan->planes > p_cap || plan->ng > ng_cap) plan->status |= TOI_STATUS_PLANES;
     }
 }
 
@@ -309,7 +321,7 @@ hipError_t launch_prep(toi_ctx* c, const toi_snapshot& s) {
         const int blocks = (int)std::min<long>(1024, (total + 255) / 256);
         hipLaunchKernelGGL(k_t3max, dim3(blocks), dim3(256), 0, c->stream, c->N, cell, c->plan);
         hipLaunchKernelGGL(k_plan, dim3(1), dim3(256), 0, c->stream, p.alpha_target, p.cheb_gamma, p.n_slab,
-                           p.cheb_k, c->P_cap, c->plan);
+                           p.cheb_k, c->P_cap, c->NG_max, c->plan);
     }
     return hipGetLastError();
 }
