@@ -61,6 +61,15 @@ def make_pool(wl, n_pool, device):
     return pool
 
 
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def grid_flops(wl, P):
+    """Useful gridding arithmetic per snapshot: each sample adds a complex value times a
+    real kernel weight (4 flops) to 8 x 8 cells of each of the P planes."""
+    return wl.n_vis * 64 * P * 4
+
+
 def stage_bytes(wl, P, with_flags):
     """Algorithmic HBM bytes per launch of each stage (each array read or written once)."""
     N, M = wl.n_pix, 2 * wl.n_pix
@@ -78,6 +87,25 @@ def stage_bytes(wl, P, with_flags):
         "reproject": 2 * img,
         "tlisi": 3 * img,
     }
+
+
+def recorded_traffic(kernel="k_grid_tiles", source="toi_grid.hip", workload="meerkat"):
+    """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (profiles/), or None
+    when the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith(("traffic_bytes ", "source_sha256 ")):
+            key, val = line.split(":", 1)
+            rec[key.strip()] = val.strip()
+    src = os.path.join(ROOT, "paper_2512_06254_amd", "csrc", source)
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get(f"source_sha256 {source}") != digest or f"traffic_bytes {kernel}" not in rec:
+        return None
+    return int(rec[f"traffic_bytes {kernel}"])
 
 
 def cpu_baseline(wl, snap_dev, n_slab, K, n_pixels=6):
@@ -124,7 +152,19 @@ def main():
     ap.add_argument("--workload", default="meerkat")
     ap.add_argument("--pool", type=int, default=4, help="distinct resident snapshots cycled through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this path has no multi-GPU mode (asked for --gpus {args.gpus}). "
               "Snapshots are independent, so N GPUs would each take a contiguous time block.",
@@ -179,11 +219,21 @@ def main():
             avg = tot / n
             stages[name] = {"avg_ms": round(avg, 4), "launches": n,
                             "GBps": round(sb.get(name, 0) / (avg * 1e-3) / 1e9, 1) if name in sb else None}
+    if "grid" in stages:
+        stages["grid"]["TFLOPs"] = round(grid_flops(wl, P) / (stages["grid"]["avg_ms"] * 1e-3) / 1e12, 2)
+        stages["grid"]["GBps"] = None
     dom = max((s for s in stages if s in sb), key=lambda s: stages[s]["avg_ms"] * stages[s]["launches"])
-    ach = sb[dom] / (stages[dom]["avg_ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": dom,
-                "algorithmic_bytes": sb[dom]}
+    if dom == "grid":   # the gridder is bound by FP32 vector arithmetic, not by HBM
+        ach = grid_flops(wl, P) / (stages[dom]["avg_ms"] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    "traffic": recorded_traffic() if wl.name == "meerkat" else None,
+                    "kernel": "k_grid_tiles", "algorithmic_flops": grid_flops(wl, P)}
+    else:
+        ach = sb[dom] / (stages[dom]["avg_ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": dom,
+                    "algorithmic_bytes": sb[dom]}
     step_bytes = sum(sb.values()) - sb["clear"]
     out = {
         "metric": METRIC, "value": round(ms, 4), "unit": "ms/snapshot", "n_gpus": 1, "steps": args.steps,

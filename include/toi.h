@@ -50,7 +50,7 @@ typedef enum {
 #define TOI_STATUS_OVERFLOW   8u   /* gridding bin lists overflowed: image incomplete       */
 
 typedef struct {
-    int32_t  n_pix;        /* N, image side: power of two, 32 .. 8192                       */
+    int32_t  n_pix;        /* N, image side: power of two, 32 .. 4096                       */
     double   cell_deg;     /* cell size (degrees)                                           */
     int32_t  mode;         /* 2: coplanar imaging (Section 3.2); 3: near-coplanar (3.4)      */
     int32_t  n_slab;       /* N_slab; 0 = eq. (27) with alpha_target                         */

@@ -131,8 +131,8 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
     *out = nullptr;
     if (!pin) return fail(nullptr, TOI_EINVAL, "toi_create: params is NULL");
     toi_params p = *pin;
-    if (!is_pow2(p.n_pix) || p.n_pix < 32 || p.n_pix > 8192)
-        return fail(nullptr, TOI_EINVAL, "toi_create: n_pix must be a power of two in [32, 8192]");
+    if (!is_pow2(p.n_pix) || p.n_pix < 32 || p.n_pix > 4096)
+        return fail(nullptr, TOI_EINVAL, "toi_create: n_pix must be a power of two in [32, 4096]");
     if (!(p.cell_deg > 0.0) || p.cell_deg * p.n_pix >= 180.0)
         return fail(nullptr, TOI_EINVAL, "toi_create: cell_deg must be > 0 and the field < 180 deg");
     if (p.mode != 2 && p.mode != 3) return fail(nullptr, TOI_EINVAL, "toi_create: mode must be 2 or 3");

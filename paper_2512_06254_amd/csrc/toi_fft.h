@@ -75,8 +75,24 @@ __host__ __device__ constexpr int fft_radix_at(int M, int E, int NS) {
     return NS == 1 ? fft_first_radix(M, E) : E;
 }
 
+// e^{+2 pi i n / M} from a half-period table tw[n] (n < M/2), which the
+// kernels keep in LDS: e^{i pi} = -1 supplies the second half.
+template <int M>
+__device__ inline float2 twiddle(const float2* tw, int n) {
+    n &= M - 1;
+    const float2 w = tw[n & (M / 2 - 1)];
+    return n < M / 2 ? w : make_float2(-w.x, -w.y);
+}
+
+// Copy the half-period twiddle table into LDS (all threads; ends with a barrier).
+template <int M>
+__device__ inline void load_twiddles(float2* tw_s, const float2* __restrict__ tw) {
+    for (int i = threadIdx.x; i < M / 2; i += blockDim.x) tw_s[i] = tw[i];
+    __syncthreads();
+}
+
 template <int M, int E, int R, int NS>
-__device__ inline void fft_stage_regs(float2* v, const float2* __restrict__ tw) {
+__device__ inline void fft_stage_regs(float2* v, const float2* tw) {
     constexpr int T = M / E;
 #pragma unroll
     for (int b = 0; b < E / R; ++b) {
@@ -84,14 +100,14 @@ __device__ inline void fft_stage_regs(float2* v, const float2* __restrict__ tw) 
             const int j = threadIdx.x + b * T;
             const int k = j & (NS - 1);
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], tw[(r * k * (M / (NS * R))) & (M - 1)]);
+            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], twiddle<M>(tw, r * k * (M / (NS * R))));
         }
         Dft<R>::run(v + b * R);
     }
 }
 
 template <int M, int E, int NS>
-__device__ inline void fft_stages(float2* v, float2* lds, const float2* __restrict__ tw) {
+__device__ inline void fft_stages(float2* v, float2* lds, const float2* tw) {
     constexpr int T = M / E;
     constexpr int R = fft_radix_at(M, E, NS);
     fft_stage_regs<M, E, R, NS>(v, tw);

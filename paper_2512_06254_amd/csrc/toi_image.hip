@@ -17,7 +17,7 @@
 namespace toi {
 
 template <int M, int E, int B>
-__global__ __launch_bounds__(M / E) void k_fft_rows(const float2* __restrict__ grid, float2* __restrict__ hbuf,
+__global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict__ grid, float2* __restrict__ hbuf,
                                                     const float2* __restrict__ tw,
                                                     const DevPlan* __restrict__ plan, int nbands,
                                                     const uint32_t* __restrict__ tile_bits,
@@ -26,6 +26,7 @@ __global__ __launch_bounds__(M / E) void k_fft_rows(const float2* __restrict__ g
     constexpr int KEEP = E / 2;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[M];
+    __shared__ float2 tw_s[M / 2];
     __shared__ uint32_t tb[WORDS];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
     const int plane = id / nbands, band = id % nbands;
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(M / E) void k_fft_rows(const float2* __restrict__ g
     const int ty = (band * B) / kTile;
     if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) return;   // empty tile row
     if (threadIdx.x < WORDS) tb[threadIdx.x] = tile_bits[((size_t)g * NT + ty) * WORDS + threadIdx.x];
-    __syncthreads();
+    load_twiddles<M>(tw_s, tw);
     auto occupied = [&](int x) { return (tb[x >> 10] >> ((x >> 5) & 31)) & 1u; };
     float2 keep[B][KEEP];
 #pragma unroll
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(M / E) void k_fft_rows(const float2* __restrict__ g
         const int y = band * B + rb;
         float2 v[E];
         fft_load_masked<M, E>(v, grid + ((size_t)plane * M + y) * M, occupied);
-        fft_stages<M, E, 1>(v, lds, tw);
+        fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) keep[rb][q] = v[fft_kept_slot<E>(q)];
         __syncthreads();
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(M / E) void k_fft_rows(const float2* __restrict__ g
 // J_0 + 2 sum_m J_{2m} = 1 applied once at the end; small |alpha| uses the
 // power series.
 template <int M, int E>
-__global__ __launch_bounds__(M / E) void k_fft_cols(const float2* __restrict__ hbuf, float* __restrict__ tplane_t,
+__global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict__ hbuf, float* __restrict__ tplane_t,
                                                     const float2* __restrict__ tw, const float* __restrict__ corr,
                                                     const DevPlan* __restrict__ plan, float cell_rad, int mode,
                                                     const uint32_t* __restrict__ row_bits, int ng_cap) {
@@ -77,6 +78,7 @@ __global__ __launch_bounds__(M / E) void k_fft_cols(const float2* __restrict__ h
     constexpr int KEEP = E / 2;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[M];
+    __shared__ float2 tw_s[M / 2];
     extern __shared__ uint32_t rb_s[];                 // [ng][WORDS] nonempty tile rows per group
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
     int j2[KEEP];
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(M / E) void k_fft_cols(const float2* __restrict__ h
     for (int q = 0; q < KEEP; ++q) j2[q] = fft_kept_index<M, E>(q);
     float* out = tplane_t + (size_t)j1 * N;
     for (int i = threadIdx.x; i < ng_cap * WORDS; i += blockDim.x) rb_s[i] = row_bits[i];
-    __syncthreads();
+    load_twiddles<M>(tw_s, tw);
     if (plan->status & kStatusFatal) {
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) out[j2[q]] = 0.f;
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(M / E) void k_fft_cols(const float2* __restrict__ h
     if (mode == 2) {
         float2 v[E];
         fft_load_masked<M, E>(v, hbuf + (size_t)j1 * M, [&](int y) { return (rb_s[y >> 10] >> ((y >> 5) & 31)) & 1u; });
-        fft_stages<M, E, 1>(v, lds, tw);
+        fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) tr[q] = v[fft_kept_slot<E>(q)].x;
     } else {
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(M / E) void k_fft_cols(const float2* __restrict__ h
                 const uint32_t* rbg = rb_s + group_of_plane(p * K + k, plan) * WORDS;
                 fft_load_masked<M, E>(v, hbuf + ((size_t)(p * K + k) * N + j1) * M,
                                       [&](int y) { return (rbg[y >> 10] >> ((y >> 5) & 31)) & 1u; });
-                fft_stages<M, E, 1>(v, lds, tw);
+                fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
                 for (int q = 0; q < KEEP; ++q) {
                     float jk;
@@ -273,7 +275,6 @@ hipError_t launch_image(toi_ctx* c, float* image_out, float* tplane_out) {
         case 2048: e = launch_fft_passes<2048, 16>(c); break;
         case 4096: e = launch_fft_passes<4096, 16>(c); break;
         case 8192: e = launch_fft_passes<8192, 32>(c); break;
-        case 16384: e = launch_fft_passes<16384, 32>(c); break;
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
