@@ -196,6 +196,8 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
         {(void**)&c->grid, P * M * M * sizeof(float2)},
         {(void**)&c->hbuf, P * N * M * sizeof(float2)},
         {(void**)&c->tplane_t, N * N * sizeof(float)},
+        {(void**)&c->adj_tp, N * N * sizeof(float)},
+        {(void**)&c->item_gain, (size_t)c->n_items_max * sizeof(double2)},
         {(void**)&c->plan, sizeof(DevPlan)},
         {(void**)&c->rows, std::max<size_t>(1, p.n_row_max) * sizeof(RowStat)},
         {(void**)&c->corr, N * sizeof(float)},
@@ -244,7 +246,7 @@ toi_status toi_destroy(toi_ctx* c) {
     if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
     if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
     void* ptrs[] = {c->items, c->bin_order, c->bin_count, c->bin_off, c->bin_cursor, c->bin_list, c->tile_bits, c->row_bits,
-                    c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
+                    c->adj_tp, c->item_gain, c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
                     c->scratch_d, c->scratch_i, c->det_scores, c->det_labels, c->batch_desc};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);

@@ -1,0 +1,394 @@
+// S10: adjoint of toi_grid + toi_image for the snapshot last gridded.
+//
+// The imaging map x -> I is real-linear; under <I, y> = sum I y and
+// <x, z> = Re sum conj(z) x its adjoint is applied step by step in reverse:
+//   1. re-projection transpose: each output pixel's gradient is scattered with
+//      its bilinear weights onto the transformed plane;
+//   2. column pass: per image column and plane, the pixel gradients times
+//      conj(c_k(alpha) e^{i 2 pi r3p t3}) times the grid correction and
+//      1/(omega W) are placed at their FFT bins and transformed with e^{-i}
+//      (as conj(F^{-1}(conj(.))) with the inverse FFT);
+//   3. row pass: the same along x, giving the gradient of every grid plane in
+//      the rows that hold samples;
+//   4. degridding: each sample gathers the kernel-weighted plane gradients of
+//      its 8 x 8 footprint and sums them with T_k(s);
+//   5. visibilities: grad V_k = conj(g_a1 conj(g_a2)) W_k (1 - F_k) grad x;
+//      gains: per work item sum_c conj(y_c) grad x_c (y = pre-gain weighted
+//      sum), reduced per antenna in FP64 in a fixed order.
+// The grid and row-pass workspaces are reused, so toi_grid must run again
+// before the next toi_image.
+#include "toi_fft.h"
+#include "toi_grid.h"
+#include "toi_internal.h"
+
+namespace toi {
+
+__global__ __launch_bounds__(256) void k_zero_f32(float* __restrict__ p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+// 1. transpose of the bilinear re-projection (t-plane gradient, j1-major)
+__global__ __launch_bounds__(256) void k_reproject_adj(const float* __restrict__ gimg, float* __restrict__ gtp,
+                                                       const DevPlan* __restrict__ plan, int N, double cell_rad) {
+    const int j1 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j2 = blockIdx.y;
+    if (j1 >= N || (plan->status & kStatusFatal)) return;
+    int i1, i2;
+    float f1, f2;
+    if (!reproject_source(plan, N, cell_rad, j1, j2, i1, i2, f1, f2)) return;
+    const float y = gimg[(size_t)j2 * N + j1];
+    if (y == 0.f) return;
+    float* c0 = gtp + (size_t)i1 * N + i2;
+    float* c1 = c0 + N;
+    unsafeAtomicAdd(c0, (1.f - f1) * (1.f - f2) * y);
+    unsafeAtomicAdd(c1, f1 * (1.f - f2) * y);
+    unsafeAtomicAdd(c0 + 1, (1.f - f1) * f2 * y);
+    unsafeAtomicAdd(c1 + 1, f1 * f2 * y);
+}
+
+// Miller backward recurrence for J_n(alpha) in FP64 from a per-pixel start
+// order (no rescaling needed for |alpha| >= 1e-3 and start <= 76).
+__device__ inline int miller_start(int K, double alpha) { return 2 * ((K + 14 + (int)ceil(1.5 * fabs(alpha))) / 2); }
+
+__device__ inline double miller_norm(double alpha, int L) {
+    double jp1 = 0.0, j = 1e-100, nrm = 0.0;
+    const double ia = 1.0 / alpha;
+    for (int n = L; n >= 0; --n) {
+        if ((n & 1) == 0) nrm += (n == 0 ? 1.0 : 2.0) * j;
+        const double jm1 = 2.0 * n * ia * j - jp1;
+        jp1 = j;
+        j = jm1;
+    }
+    return nrm;
+}
+
+// 2. column pass of the adjoint
+template <int M, int E>
+__global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__ gtp, float2* __restrict__ gh,
+                                                       const float2* __restrict__ tw, const float* __restrict__ corr,
+                                                       const DevPlan* __restrict__ plan, float cell_rad, int mode) {
+    constexpr int N = M / 2;
+    constexpr int KEEP = E / 2;
+    constexpr int T = M / E;
+    __shared__ float2 lds[M];
+    __shared__ float2 tw_s[M / 2];
+    const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
+    if (plan->status & kStatusFatal) return;
+    load_twiddles<M>(tw_s, tw);
+    const int K = plan->K, ns = plan->n_slab;
+    int j2[KEEP];
+    float y[KEEP];
+    const float c1 = corr[j1] * (float)plan->norm;
+#pragma unroll
+    for (int q = 0; q < KEEP; ++q) {
+        j2[q] = fft_kept_index<M, E>(q);
+        y[q] = gtp[(size_t)j1 * N + j2[q]] * c1 * corr[j2[q]];
+    }
+    // per-pixel geometry (FP64 here: the adjoint runs once per backward pass)
+    double t3[KEEP], alpha[KEEP], nrm[KEEP], jp1[KEEP], jc[KEEP];
+    int Lq[KEEP];
+    if (mode == 3) {
+        const double V13 = plan->V[2], V23 = plan->V[5], V33 = plan->V[8];
+        const double sg = V33 >= 0 ? 1.0 : -1.0;
+        const double t1 = -(double)cell_rad * (j1 - N / 2);
+#pragma unroll
+        for (int q = 0; q < KEEP; ++q) {
+            const double t2 = (double)cell_rad * (j2[q] - N / 2);
+            const double a = 1.0 - (t1 + V13) * (t1 + V13) - (t2 + V23) * (t2 + V23);
+            if (a < 0) y[q] = 0.f;
+            const double num = t1 * t1 + t2 * t2 + 2.0 * t1 * V13 + 2.0 * t2 * V23;
+            t3[q] = a >= 0 ? -sg * num / (sqrt(fmax(a, 0.0)) + fabs(V33)) : 0.0;
+            alpha[q] = 2.0 * kPi * plan->dr3 * t3[q];
+            Lq[q] = miller_start(K, alpha[q]);
+            nrm[q] = fabs(alpha[q]) < 1e-3 ? 1.0 : miller_norm(alpha[q], Lq[q]);
+        }
+    }
+    for (int p = 0; p < ns; ++p) {
+        float cs[KEEP], sn[KEEP];
+        if (mode == 3) {
+            const double r3p = plan->r3min + (2 * p + 1) * plan->dr3;
+#pragma unroll
+            for (int q = 0; q < KEEP; ++q) {
+                double ph = 2.0 * kPi * r3p * t3[q];
+                ph -= 2.0 * kPi * rint(ph / (2.0 * kPi));
+                sincosf((float)ph, &sn[q], &cs[q]);
+                // Miller state at order K (recurrence only above)
+                jp1[q] = 0.0;
+                jc[q] = 1e-100;
+                if (fabs(alpha[q]) >= 1e-3) {
+                    const double ia = 1.0 / alpha[q];
+                    for (int n = Lq[q]; n >= K; --n) {
+                        const double jm1 = 2.0 * n * ia * jc[q] - jp1[q];
+                        jp1[q] = jc[q];
+                        jc[q] = jm1;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < KEEP; ++q) { cs[q] = 1.f; sn[q] = 0.f; }
+        }
+        for (int k = K - 1; k >= 0; --k) {
+            // gF = y conj(c_k) e^{-i 2 pi r3p t3}, placed at its bin (conjugated for the inverse-FFT trick)
+            float2 v[E];
+#pragma unroll
+            for (int r = 0; r < E; ++r) v[r] = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < KEEP; ++q) {
+                float jk = 1.f;
+                if (mode == 3) {
+                    const double a = alpha[q];
+                    double J;
+                    if (fabs(a) < 1e-3) {
+                        J = k == 0 ? 1.0 - 0.25 * a * a
+                          : k == 1 ? 0.5 * a * (1.0 - 0.125 * a * a)
+                          : k == 2 ? 0.125 * a * a
+                          : k == 3 ? a * a * a / 48.0 : 0.0;
+                    } else {
+                        J = jc[q] / nrm[q];
+                        if (k > 0) {
+                            const double jm1 = 2.0 * k / a * jc[q] - jp1[q];
+                            jp1[q] = jc[q];
+                            jc[q] = jm1;
+                        }
+                    }
+                    jk = (float)J * (k == 0 ? 1.f : 2.f);
+                }
+                // conj(c_k) = jk * conj(i^k); times e^{-i phi}; conj of the whole for the FFT trick:
+                // conj(y jk conj(i^k) e^{-i phi}) = y jk i^k e^{i phi}
+                float2 e = make_float2(y[q] * jk * cs[q], y[q] * jk * sn[q]);
+                switch (k & 3) {
+                    case 1: e = make_float2(-e.y, e.x); break;
+                    case 2: e = make_float2(-e.x, -e.y); break;
+                    case 3: e = make_float2(e.y, -e.x); break;
+                    default: break;
+                }
+                v[fft_kept_slot<E>(q)] = e;
+            }
+            // natural-order scatter, then the stage-1 pattern
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < E; ++r) lds[threadIdx.x + r * T] = v[r];
+            __syncthreads();
+            constexpr int R1 = fft_first_radix(M, E);
+#pragma unroll
+            for (int b = 0; b < E / R1; ++b)
+#pragma unroll
+                for (int r = 0; r < R1; ++r) v[b * R1 + r] = lds[threadIdx.x + b * T + r * (M / R1)];
+            fft_stages<M, E, 1>(v, lds, tw_s);
+            float2* dst = gh + ((size_t)(p * K + k) * N + j1) * M;
+#pragma unroll
+            for (int r = 0; r < E; ++r) dst[threadIdx.x + r * T] = make_float2(v[r].x, -v[r].y);
+        }
+    }
+}
+
+// 3. row pass of the adjoint (rows of tile rows that hold samples)
+template <int M, int E, int B>
+__global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict__ gh, float2* __restrict__ gg,
+                                                       const float2* __restrict__ tw,
+                                                       const DevPlan* __restrict__ plan, int nbands,
+                                                       const uint32_t* __restrict__ row_bits) {
+    constexpr int N = M / 2;
+    constexpr int KEEP = E / 2;
+    constexpr int T = M / E;
+    constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
+    __shared__ float2 lds[M];
+    __shared__ float2 tw_s[M / 2];
+    const int id = xcd_block_id(blockIdx.x, gridDim.x);
+    const int plane = id / nbands, band = id % nbands;
+    if ((plan->status & kStatusFatal) || plane >= plan->planes) return;
+    const int g = group_of_plane(plane, plan);
+    const int ty = (band * B) / kTile;
+    if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) return;
+    load_twiddles<M>(tw_s, tw);
+    float2 in[B][KEEP];
+#pragma unroll
+    for (int q = 0; q < KEEP; ++q) {
+        const float2* src = gh + ((size_t)plane * N + fft_kept_index<M, E>(q)) * M + band * B;
+#pragma unroll
+        for (int rb = 0; rb < B; ++rb) in[rb][q] = src[rb];
+    }
+#pragma unroll
+    for (int rb = 0; rb < B; ++rb) {
+        float2 v[E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) v[r] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < KEEP; ++q) v[fft_kept_slot<E>(q)] = make_float2(in[rb][q].x, -in[rb][q].y);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < E; ++r) lds[threadIdx.x + r * T] = v[r];
+        __syncthreads();
+        constexpr int R1 = fft_first_radix(M, E);
+#pragma unroll
+        for (int b = 0; b < E / R1; ++b)
+#pragma unroll
+            for (int r = 0; r < R1; ++r) v[b * R1 + r] = lds[threadIdx.x + b * T + r * (M / R1)];
+        fft_stages<M, E, 1>(v, lds, tw_s);
+        float2* dst = gg + ((size_t)plane * M + band * B + rb) * M;
+#pragma unroll
+        for (int r = 0; r < E; ++r) dst[threadIdx.x + r * T] = make_float2(v[r].x, -v[r].y);
+    }
+}
+
+// 4-5. degridding gather, visibility gradients and per-item gain partials
+__global__ __launch_bounds__(256) void k_degrid(
+    const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
+    const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
+    const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_chan, int n_corr,
+    uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, double cell_rad, int n_items,
+    const float2* __restrict__ gg, float2* __restrict__ grad_vis, double2* __restrict__ item_gain) {
+    const int lane = threadIdx.x & 63;
+    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= n_items) return;
+    const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
+    const int r = item / n_chunks;
+    const int c = (item % n_chunks) * kItemChans + lane;
+    const bool live = c < n_chan;
+    const size_t base = ((size_t)r * n_chan + (live ? c : 0)) * n_corr;
+    float gxr = 0.f, gxi = 0.f, yr = 0.f, yi = 0.f;
+    float w = 0.f;
+    if (live) w = sample_value(vis, weight, flag, base, n_corr, mask, yr, yi);
+    if (live && w > 0.f && !(P->status & kStatusFatal)) {
+        const Track trk = row_track(uvw, r, P, M, cell_rad);
+        const double nu = freq[c];
+        int p = 0;
+        float s = 0.f;
+        if (mode == 3 && P->dr3 > 0.0) {
+            const double r3 = trk.a3 * nu;
+            p = slab_index(r3, P);
+            s = (float)((r3 - (P->r3min + (2 * p + 1) * P->dr3)) / P->dr3);
+        }
+        const double X = 0.5 * M + trk.ax * nu, Y = 0.5 * M + trk.ay * nu;
+        const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
+        const int ix = (int)fx0, iy = (int)fy0;
+        const float ox = (float)(X - fx0), oy = (float)(Y - fy0);
+        float wx[8], wy[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            wx[d] = es_kernel(((float)d - ox) * 0.25f);
+            wy[d] = es_kernel(((float)d - oy) * 0.25f);
+        }
+        const int K = P->K;
+        float t = 1.f, tm1 = s;   // T_0, T_{-1} = T_1
+        for (int k = 0; k < K; ++k) {
+            const float2* pl = gg + (size_t)(p * K + k) * M * M;
+            float ar = 0.f, ai = 0.f;
+#pragma unroll
+            for (int dy = 0; dy < 8; ++dy) {
+                const float2* row = pl + (size_t)((iy + dy) & (M - 1)) * M;
+                float rr = 0.f, ri = 0.f;
+#pragma unroll
+                for (int dx = 0; dx < 8; ++dx) {
+                    const float2 gv = row[(ix + dx) & (M - 1)];
+                    rr += wx[dx] * gv.x;
+                    ri += wx[dx] * gv.y;
+                }
+                ar += wy[dy] * rr;
+                ai += wy[dy] * ri;
+            }
+            gxr += t * ar;
+            gxi += t * ai;
+            const float tn = 2.f * s * t - tm1;
+            tm1 = t;
+            t = tn;
+        }
+    }
+    // visibility gradients: conj(g_row) W_k (1 - F_k) grad x on the selected correlations
+    const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
+    const float hr = gr.x * gxr + gr.y * gxi, hi = gr.x * gxi - gr.y * gxr;   // conj(g) * gx
+    if (live && grad_vis) {
+        for (int k = 0; k < n_corr; ++k) {
+            float wk = 0.f;
+            if ((mask >> k) & 1u) {
+                wk = weight ? weight[base + k] : 1.f;
+                if (flag && flag[base + k]) wk = 0.f;
+            }
+            grad_vis[base + k] = make_float2(wk * hr, wk * hi);
+        }
+    }
+    if (item_gain) {   // sum over the item's channels of conj(y) grad x, in FP64
+        double sr = (double)yr * gxr + (double)yi * gxi;
+        double si = (double)yr * gxi - (double)yi * gxr;
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) item_gain[item] = make_double2(sr, si);
+    }
+}
+
+// grad g_a = sum_{rows with ant1 = a} g_ant2 S + sum_{rows with ant2 = a} g_ant1 conj(S), S per item
+__global__ __launch_bounds__(256) void k_gain_grad(const double2* __restrict__ item_gain, int n_items, int n_chunks,
+                                                   const int32_t* __restrict__ ant1, const int32_t* __restrict__ ant2,
+                                                   const float2* __restrict__ gains, int n_ant,
+                                                   float2* __restrict__ grad_gains) {
+    __shared__ double red[2][4];
+    const int a = blockIdx.x;
+    double sr = 0.0, si = 0.0;
+    for (int it = threadIdx.x; it < n_items; it += blockDim.x) {
+        const int r = it / n_chunks;
+        const int a1 = ant1[r], a2 = ant2[r];
+        if (a1 < 0 || a1 >= n_ant || a2 < 0 || a2 >= n_ant) continue;
+        const double2 S = item_gain[it];
+        if (a1 == a) {
+            const float2 g = gains[a2];
+            sr += g.x * S.x - g.y * S.y;
+            si += g.x * S.y + g.y * S.x;
+        }
+        if (a2 == a) {   // g_ant1 conj(S)
+            const float2 g = gains[a1];
+            sr += g.x * S.x + g.y * S.y;
+            si += g.y * S.x - g.x * S.y;
+        }
+    }
+    sr = block_sum(sr, red[0]);
+    si = block_sum(si, red[1]);
+    if (threadIdx.x == 0) grad_gains[a] = make_float2((float)sr, (float)si);
+}
+
+template <int M, int E>
+static void launch_adj_ffts(toi_ctx* c) {
+    constexpr int B = (M >= 8192) ? 2 : 4;
+    const float cell = (float)(c->p.cell_deg * kPi / 180.0);
+    hipLaunchKernelGGL((k_adj_cols<M, E>), dim3(M / 2), dim3(M / E), 0, c->stream, c->adj_tp, c->hbuf, c->twiddle,
+                       c->corr, c->plan, cell, c->p.mode);
+    const int nbands = M / B;
+    hipLaunchKernelGGL((k_adj_rows<M, E, B>), dim3(nbands * c->P_cap), dim3(M / E), 0, c->stream, c->hbuf, c->grid,
+                       c->twiddle, c->plan, nbands, c->row_bits);
+}
+
+hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot& s, float2* grad_vis,
+                         float2* grad_gains) {
+    const toi_params& p = c->p;
+    StageTimer timer(c, TOI_STAGE_DEGRID);
+    const int N = c->N, M = c->M;
+    const double cell = p.cell_deg * kPi / 180.0;
+    hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->adj_tp, (size_t)N * N);
+    hipLaunchKernelGGL(k_reproject_adj, dim3((N + 255) / 256, N), dim3(256), 0, c->stream, grad_image, c->adj_tp,
+                       c->plan, N, cell);
+    switch (M) {
+        case 64: launch_adj_ffts<64, 8>(c); break;
+        case 128: launch_adj_ffts<128, 8>(c); break;
+        case 256: launch_adj_ffts<256, 16>(c); break;
+        case 512: launch_adj_ffts<512, 16>(c); break;
+        case 1024: launch_adj_ffts<1024, 16>(c); break;
+        case 2048: launch_adj_ffts<2048, 16>(c); break;
+        case 4096: launch_adj_ffts<4096, 16>(c); break;
+        case 8192: launch_adj_ffts<8192, 32>(c); break;
+        default: return hipErrorInvalidValue;
+    }
+    const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;
+    const int n_items = s.n_row * n_chunks;
+    if (n_items > 0)
+        hipLaunchKernelGGL(k_degrid, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw, (const float2*)s.vis,
+                           s.weight, s.flag, s.freq, s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan,
+                           p.n_corr, p.corr_mask, p.mode, c->plan, M, cell, n_items, c->grid, grad_vis,
+                           grad_gains ? c->item_gain : nullptr);
+    if (grad_gains)
+        hipLaunchKernelGGL(k_gain_grad, dim3(p.n_ant), dim3(256), 0, c->stream, c->item_gain, n_items, n_chunks,
+                           s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, grad_gains);
+    return hipGetLastError();
+}
+
+}  // namespace toi

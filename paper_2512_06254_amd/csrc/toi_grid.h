@@ -116,4 +116,29 @@ __device__ inline void cheb_start(float s, int k0, float& t, float& tm1) {
     }
 }
 
+// Re-projection (Section 3.3): output pixel (j1, j2) -> reduced SIN map onto the
+// tilted plane (x' = x + r0 z xi, y' = y + r0 z eta with z = 1 - n) -> in-plane
+// 2x2 block of V -> fractional transformed-plane indices, in FP64.  Returns
+// false when the pixel has no valid bilinear source (outside the unit circle
+// or a neighbour outside the image); otherwise the lower-left source pixel
+// (i1, i2) and the FP32 fractions (f1, f2).
+__device__ inline bool reproject_source(const DevPlan* __restrict__ P, int N, double cell_rad, int j1, int j2,
+                                        int& i1, int& i2, float& f1, float& f2) {
+    const double l = -cell_rad * (j1 - N / 2), m = cell_rad * (j2 - N / 2);
+    const double rho2 = l * l + m * m;
+    if (!(rho2 < 1.0)) return false;
+    const double z = rho2 / (1.0 + sqrt(1.0 - rho2));           // 1 - n, stable near the centre
+    const double a = l + P->xi * z, b = m + P->eta * z;
+    const double t1 = P->V[0] * a + P->V[1] * b;
+    const double t2 = P->V[3] * a + P->V[4] * b;
+    const double u1 = 0.5 * N - t1 / cell_rad, u2 = 0.5 * N + t2 / cell_rad;
+    const double f1d = floor(u1), f2d = floor(u2);
+    if (!(f1d >= 0.0 && f1d <= N - 2 && f2d >= 0.0 && f2d <= N - 2)) return false;
+    i1 = (int)f1d;
+    i2 = (int)f2d;
+    f1 = (float)(u1 - f1d);
+    f2 = (float)(u2 - f2d);
+    return true;
+}
+
 }  // namespace toi

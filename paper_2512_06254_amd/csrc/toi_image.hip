@@ -213,25 +213,12 @@ __global__ __launch_bounds__(256) void k_reproject(const float* __restrict__ tpl
     const int j2 = blockIdx.y;
     if (j1 >= N) return;
     float val = 0.f;
-    if (!(plan->status & kStatusFatal)) {
-        const double l = -cell_rad * (j1 - N / 2), m = cell_rad * (j2 - N / 2);
-        const double rho2 = l * l + m * m;
-        if (rho2 < 1.0) {
-            const double z = rho2 / (1.0 + sqrt(1.0 - rho2));       // 1 - n, stable near the centre
-            const double a = l + plan->xi * z, b = m + plan->eta * z;
-            const double t1 = plan->V[0] * a + plan->V[1] * b;
-            const double t2 = plan->V[3] * a + plan->V[4] * b;
-            const double u1 = 0.5 * N - t1 / cell_rad, u2 = 0.5 * N + t2 / cell_rad;
-            const double f1d = floor(u1), f2d = floor(u2);
-            if (f1d >= 0.0 && f1d <= N - 2 && f2d >= 0.0 && f2d <= N - 2) {
-                const int i1 = (int)f1d, i2 = (int)f2d;
-                const float f1 = (float)(u1 - f1d), f2 = (float)(u2 - f2d);
-                const float* c0 = tplane_t + (size_t)i1 * N + i2;      // j1-major t-plane
-                const float* c1 = c0 + N;
-                val = (1.f - f1) * (1.f - f2) * c0[0] + f1 * (1.f - f2) * c1[0] + (1.f - f1) * f2 * c0[1] +
-                      f1 * f2 * c1[1];
-            }
-        }
+    int i1, i2;
+    float f1, f2;
+    if (!(plan->status & kStatusFatal) && reproject_source(plan, N, cell_rad, j1, j2, i1, i2, f1, f2)) {
+        const float* c0 = tplane_t + (size_t)i1 * N + i2;      // j1-major t-plane
+        const float* c1 = c0 + N;
+        val = (1.f - f1) * (1.f - f2) * c0[0] + f1 * (1.f - f2) * c1[0] + (1.f - f1) * f2 * c0[1] + f1 * f2 * c1[1];
     }
     img[(size_t)j2 * N + j1] = val;
 }

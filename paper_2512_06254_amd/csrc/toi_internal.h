@@ -91,6 +91,8 @@ struct toi_ctx {
     uint32_t* row_bits;   // [NG_max][NT/32]      nonempty tile rows
     float2* hbuf;         // [P_cap][N][M]   row-pass output, column major per plane
     float* tplane_t;      // [N][N]          transformed-plane image, j1 major
+    float* adj_tp;        // [N][N]          adjoint: transformed-plane gradient, j1 major
+    double2* item_gain;   // [n_items_max]   adjoint: per-item gain partial sums
     toi::DevPlan* plan;
     toi::RowStat* rows;   // [n_row_max]
     float* corr;          // [N]  (-1)^a / psi(a), a = j - N/2

@@ -4,9 +4,6 @@
 
 namespace toi {
 
-hipError_t launch_degrid(toi_ctx*, const float*, const toi_snapshot&, float2*, float2*) {
-    return hipErrorNotSupported;
-}
 hipError_t launch_detect(toi_ctx*, const float*, int, int32_t*, int, int32_t*) { return hipErrorNotSupported; }
 
 }  // namespace toi

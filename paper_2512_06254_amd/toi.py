@@ -240,3 +240,50 @@ def to_device(snap: dict, device="cuda") -> dict:
         v = snap.get(k)
         out[k] = None if v is None else torch.from_numpy(np.ascontiguousarray(v)).to(device)
     return out
+
+
+def _autograd_function():
+    import torch
+
+    class TOIImage(torch.autograd.Function):
+        """Differentiable snapshot image: forward = toi_grid + toi_image, backward = toi_degrid.
+
+        Gradients follow PyTorch's convention for complex inputs of a real loss
+        (dL/dRe + i dL/dIm) and are returned for ``vis`` and, when given, ``gains``.
+        """
+
+        @staticmethod
+        def forward(ctx, vis, gains, imager, snap):
+            s = dict(snap)
+            s["vis"] = vis.contiguous()
+            if gains is not None:
+                s["gains"] = gains.contiguous()
+            imager.grid(s)
+            img = imager.image()
+            imager._last_snap = s
+            ctx.imager, ctx.snap, ctx.has_gains = imager, s, gains is not None
+            return img
+
+        @staticmethod
+        def backward(ctx, grad_img):
+            im, s = ctx.imager, ctx.snap
+            if getattr(im, "_last_snap", None) is not s:
+                im.grid(s)             # the context imaged another snapshot since: re-establish its plan
+                im._last_snap = s
+            want_g = ctx.has_gains and ctx.needs_input_grad[1]
+            gv, gg = im.degrid(grad_img.contiguous(), s, want_vis=ctx.needs_input_grad[0], want_gains=want_g)
+            return gv, gg, None, None
+
+    return TOIImage
+
+
+_TOIImage = None
+
+
+def toi_image(imager: "Imager", snap: dict, vis=None, gains=None):
+    """Image one snapshot with autograd support for ``vis`` (and ``gains``)."""
+    global _TOIImage
+    if _TOIImage is None:
+        _TOIImage = _autograd_function()
+    return _TOIImage.apply(snap["vis"] if vis is None else vis, gains if gains is not None else snap.get("gains"),
+                           imager, snap)

@@ -1,0 +1,93 @@
+"""GPU adjoint (toi_degrid through the C ABI) against the FP64 oracle adjoint,
+the dot-product identity, and the autograd Function."""
+import numpy as np
+import pytest
+
+import synth_inputs as S
+from oracle import adjoint as A
+from oracle import toi as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n_slab=1, K=8, flags=True, gains=True, n_pix=64, seed=0):
+    wl = S.scaled(S.WORKLOADS["adjoint"], n_ant=8, n_chan=40, n_pix=n_pix, n_steady=4, cell_arcsec=60.0,
+                  diameter_m=2000.0, sigma_h_m=40.0, flag_frac_max=0.3 if flags else 0.0, with_gains=gains,
+                  seed=seed)
+    snap = S.make_snapshot(wl, 0)
+    return wl, snap
+
+
+def _imager(wl, snap, n_slab, K):
+    from paper_2512_06254_amd import toi as T
+    n_row, n_chan, n_corr = snap["vis"].shape
+    return T.Imager(wl.n_pix, wl.cell_deg, n_row, n_chan, n_corr, n_slab=n_slab, cheb_k=K,
+                    n_ant=0 if snap.get("gains") is None else wl.n_ant, max_planes=32)
+
+
+@pytest.mark.parametrize("n_slab,K", [(1, 8), (2, 4), (1, 16)])
+def test_adjoint_matches_oracle(n_slab, K):
+    import torch
+    from paper_2512_06254_amd import toi as T
+    wl, snap = _setup()
+    op = A.SnapshotOperator(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=n_slab, K=K)
+    rng = np.random.default_rng(3)
+    y = rng.normal(size=(wl.n_pix, wl.n_pix))
+    gx = op.adjoint(y)
+    gv_ref, gg_ref = A.vis_gradients(snap, op.res.samples, gx)
+    im = _imager(wl, snap, n_slab, K)
+    d = T.to_device(snap)
+    im.grid(d)
+    gv, gg = im.degrid(torch.from_numpy(y.astype(np.float32)).cuda(), d, want_vis=True, want_gains=True)
+    gv = gv.cpu().numpy()
+    gg = gg.cpu().numpy()
+    e_v = np.abs(gv - gv_ref).max() / np.abs(gv_ref).max()
+    e_g = np.abs(gg - gg_ref).max() / np.abs(gg_ref).max()
+    print(f"[adjoint {n_slab}x{K}] grad_vis err {e_v:.3e}  grad_gains err {e_g:.3e}", flush=True)
+    assert e_v < 1e-4 and e_g < 1e-4
+    im.close()
+
+
+def test_dot_product_identity_through_the_abi():
+    import torch
+    from paper_2512_06254_amd import toi as T
+    wl, snap = _setup(gains=True)
+    im = _imager(wl, snap, 2, 8)
+    d = T.to_device(snap)
+    rng = np.random.default_rng(4)
+    for trial in range(3):
+        v = (rng.normal(size=snap["vis"].shape) + 1j * rng.normal(size=snap["vis"].shape)).astype(np.complex64)
+        d["vis"] = torch.from_numpy(v).cuda()
+        y = torch.from_numpy(rng.normal(size=(wl.n_pix, wl.n_pix)).astype(np.float32)).cuda()
+        im.grid(d)
+        img = im.image()
+        gv, _ = im.degrid(y, d)
+        lhs = float((img.double() * y.double()).sum())
+        rhs = float((torch.conj(gv.to(torch.complex128)) * d["vis"].to(torch.complex128)).real.sum())
+        print(f"[dot] <Gx,y>={lhs:.6e}  Re<x,G^H y>={rhs:.6e}", flush=True)
+        assert abs(lhs - rhs) <= 1e-4 * max(abs(lhs), 1e-6)
+    im.close()
+
+
+def test_autograd_function_gradients():
+    import torch
+    from paper_2512_06254_amd import toi as T
+    wl, snap = _setup()
+    res = O.image_snapshot(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=8)
+    model = torch.from_numpy((0.9 * res.image).astype(np.float32)).cuda()
+    im = _imager(wl, snap, 1, 8)
+    d = T.to_device(snap)
+    vis = d["vis"].clone().requires_grad_(True)
+    gains = d["gains"].clone().requires_grad_(True)
+    img = T.toi_image(im, d, vis=vis, gains=gains)
+    loss = ((img - model) ** 2).sum()
+    loss.backward()
+    # oracle: same loss, adjoint of 2 (I - model)
+    op = A.SnapshotOperator(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=8)
+    gx = op.adjoint(2.0 * (res.image - model.cpu().numpy().astype(np.float64)))
+    gv_ref, gg_ref = A.vis_gradients(snap, op.res.samples, gx)
+    e_v = np.abs(vis.grad.cpu().numpy() - gv_ref).max() / np.abs(gv_ref).max()
+    e_g = np.abs(gains.grad.cpu().numpy() - gg_ref).max() / np.abs(gg_ref).max()
+    print(f"[autograd] grad_vis err {e_v:.3e}  grad_gains err {e_g:.3e}", flush=True)
+    assert e_v < 1e-3 and e_g < 1e-3
+    im.close()
