@@ -136,17 +136,23 @@ toi_status fitrig_tlisi(toi_ctx* ctx, const float* img_tm2, const float* img_tm1
  * maps: per tile, the harmonic-summed DFT power of the window and the
  * non-periodic score sum(1 - tLISI), z-scores over tiles, thresholds 5 and 4,
  * 8-connected components -> boxes (t, x0, y0, x1, y1) in pixels, sorted by
- * (y0, x0, y1, x1).  window: f32[16][N/tile][N/tile], oldest first.
- * boxes_out: i32[max_boxes][5]; n_boxes_out: device i32 (the number found,
- * possibly > max_boxes, in which case only max_boxes are written). */
+ * (y0, x0, y1, x1).  window: f32[16][N/tile][N/tile], oldest first (device).
+ * boxes_out: i32[max_boxes][5] (device); n_boxes_out: device i32 (the number
+ * found, possibly > max_boxes, in which case only max_boxes are written).
+ * TOI_EUNSUPPORTED when (N/tile)^2 > 16384.  The detection details (window,
+ * harmonics, significance, connectivity) are documented readings: the paper
+ * states the steps but not their parameters. */
 toi_status fitrig_detect(toi_ctx* ctx, const float* window, int32_t t,
                          int32_t* boxes_out, int32_t max_boxes, int32_t* n_boxes_out);
 
 /* Several snapshots in one call (uneven sample counts allowed): for each i,
  * toi_grid(snaps[i]) + toi_image(images_out + i*N*N), and for i >= 2 the
- * tLISI map of (i-2, i-1, i) into tlisi_out + (i-2)*(N/tile)^2 (nullable).
- * snaps is a HOST array of n descriptors.  Executed as a captured HIP graph
- * replayed per snapshot. */
+ * tLISI map of (i-2, i-1, i) into tlisi_out + (i-2)*(N/tile)^2 (nullable);
+ * the pipeline of Section 4.1 as one launch.  snaps is a HOST array of n
+ * descriptors.  The whole batch is captured into one HIP graph, cached for
+ * the same descriptors and outputs and replayed on the context's stream (a
+ * new set recaptures; capture allocates graph resources on first use).  The
+ * context's grid workspace holds the last snapshot's planes afterwards. */
 toi_status toi_image_batch(toi_ctx* ctx, const toi_snapshot* snaps, int32_t n,
                            float* images_out, float* tlisi_out);
 
@@ -160,7 +166,8 @@ toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* w
  * TOI_STAGE_PREP (sample statistics, basis, plan), TOI_STAGE_CLEAR (grid
  * clear), TOI_STAGE_GRID (gridding), TOI_STAGE_FFT_ROWS, TOI_STAGE_FFT_COLS
  * (column FFT + correction + combination), TOI_STAGE_REPROJECT,
- * TOI_STAGE_TLISI, TOI_STAGE_DEGRID (adjoint).  toi_profile_enable(ctx, 1)
+ * TOI_STAGE_TLISI, TOI_STAGE_DEGRID (adjoint), TOI_STAGE_BATCH (one whole
+ * toi_image_batch graph launch; its kernels are not timed individually).  toi_profile_enable(ctx, 1)
  * creates the events and clears the totals (0 disables recording);
  * toi_profile_read synchronises the stream and writes, per stage, the summed
  * duration in milliseconds and the number of timed launches (host arrays of
@@ -173,7 +180,9 @@ toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* w
 #define TOI_STAGE_REPROJECT 5
 #define TOI_STAGE_TLISI 6
 #define TOI_STAGE_DEGRID 7
-#define TOI_NSTAGE 8
+#define TOI_STAGE_BATCH 8
+#define TOI_STAGE_DETECT 9
+#define TOI_NSTAGE 10
 toi_status toi_profile_enable(toi_ctx* ctx, int32_t enable);
 toi_status toi_profile_read(toi_ctx* ctx, double* total_ms, int32_t* launches);
 

@@ -81,3 +81,163 @@ hipError_t launch_tlisi(toi_ctx* c, const float* a, const float* b, const float*
 }
 
 }  // namespace toi
+
+// ---------------------------------------------------------------- S9: window detection
+// One workgroup (the window is tile-grid sized): per tile the periodic score
+// (DFT power of the mean-removed 16-map window at f = 1..8, harmonic sums over
+// h in {1, 2, 4, 8} harmonics divided by sqrt(h), maximum over f and h) and the
+// non-periodic score sum(1 - tLISI), both in FP64; z-scores over all tiles
+// with the population standard deviation; tiles with z_periodic > 5 or
+// z_nonperiodic > 4 are grouped into 8-connected components by min-label
+// propagation in LDS; one box per component in pixels, sorted by
+// (y0, x0, y1, x1).  All decisions are made in FP64 in a fixed order.
+namespace toi {
+
+__device__ inline double periodic_score16(const double* x) {
+    double mean = 0.0;
+    for (int t = 0; t < kWindow; ++t) mean += x[t];
+    mean /= kWindow;
+    double P[kWindow / 2 + 1];
+    P[0] = 0.0;
+    for (int f = 1; f <= kWindow / 2; ++f) {
+        double re = 0.0, im = 0.0;
+        for (int t = 0; t < kWindow; ++t) {
+            double sn, cs;
+            sincospi(-2.0 * f * t / kWindow, &sn, &cs);
+            re += (x[t] - mean) * cs;
+            im += (x[t] - mean) * sn;
+        }
+        P[f] = re * re + im * im;
+    }
+    double best = -1e300;
+    const int hs[4] = {1, 2, 4, 8};
+    for (int f = 1; f <= kWindow / 2; ++f) {
+        for (int hi = 0; hi < 4; ++hi) {
+            const int h = hs[hi];
+            double s = 0.0;
+            for (int j = 1; j <= h; ++j)
+                if (j * f <= kWindow / 2) s += P[j * f];
+            best = fmax(best, s / sqrt((double)h));
+        }
+    }
+    return best;
+}
+
+__global__ __launch_bounds__(1024) void k_detect(const float* __restrict__ window, int T, int tile, int t_index,
+                                                 double* __restrict__ scores, int4* __restrict__ boxes_tmp,
+                                                 int32_t* __restrict__ boxes, int max_boxes,
+                                                 int32_t* __restrict__ n_boxes) {
+    extern __shared__ int32_t sh[];            // label[T*T], root_id[T*T]
+    __shared__ double red[16];
+    __shared__ int changed, ncomp;
+    const int n = T * T;
+    int32_t* label = sh;
+    int32_t* root_id = sh + n;
+    double* sp = scores;                       // periodic
+    double* snp = scores + n;                  // non-periodic
+    double s1p = 0, s2p = 0, s1n = 0, s2n = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double x[kWindow];
+        double np = 0.0;
+        for (int t = 0; t < kWindow; ++t) {
+            x[t] = (double)window[(size_t)t * n + i];
+            np += 1.0 - x[t];
+        }
+        sp[i] = periodic_score16(x);
+        snp[i] = np;
+    }
+    __syncthreads();
+    // population mean / std in a fixed order: per-thread strided partial sums, then a tree
+    for (int i = threadIdx.x; i < n; i += blockDim.x) { s1p += sp[i]; s1n += snp[i]; }
+    s1p = block_sum(s1p, red);
+    s1n = block_sum(s1n, red);
+    const double mp = s1p / n, mn = s1n / n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        s2p += (sp[i] - mp) * (sp[i] - mp);
+        s2n += (snp[i] - mn) * (snp[i] - mn);
+    }
+    s2p = block_sum(s2p, red);
+    s2n = block_sum(s2n, red);
+    const double sdp = sqrt(s2p / n), sdn = sqrt(s2n / n);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double zp = sdp > 0 ? (sp[i] - mp) / sdp : 0.0;
+        const double zn = sdn > 0 ? (snp[i] - mn) / sdn : 0.0;
+        label[i] = (zp > 5.0 || zn > 4.0) ? i : -1;
+    }
+    if (threadIdx.x == 0) ncomp = 0;
+    __syncthreads();
+    // 8-connected components: every flagged tile takes the smallest label around it
+    for (;;) {
+        if (threadIdx.x == 0) changed = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            int l = label[i];
+            if (l < 0) continue;
+            const int ty = i / T, tx = i % T;
+            int m = l;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int yy = ty + dy, xx = tx + dx;
+                    if (yy < 0 || yy >= T || xx < 0 || xx >= T) continue;
+                    const int ln = label[yy * T + xx];
+                    if (ln >= 0 && ln < m) m = ln;
+                }
+            m = min(m, label[m]);              // pointer jumping
+            if (m < l) {
+                label[i] = m;
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        if (!changed) break;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (label[i] == i) root_id[i] = atomicAdd(&ncomp, 1);
+    __syncthreads();
+    const int nc = ncomp;
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) boxes_tmp[k] = make_int4(1 << 30, 1 << 30, -1, -1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int l = label[i];
+        if (l < 0) continue;
+        int4* b = boxes_tmp + root_id[l];
+        const int ty = i / T, tx = i % T;
+        atomicMin(&b->x, tx);
+        atomicMin(&b->y, ty);
+        atomicMax(&b->z, tx);
+        atomicMax(&b->w, ty);
+    }
+    __syncthreads();
+    // rank sort by (y0, x0, y1, x1); boxes are distinct (components are disjoint)
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+        const int4 a = boxes_tmp[k];
+        int rank = 0;
+        for (int j = 0; j < nc; ++j) {
+            const int4 b = boxes_tmp[j];
+            const bool less = b.y != a.y ? b.y < a.y : b.x != a.x ? b.x < a.x : b.w != a.w ? b.w < a.w : b.z < a.z;
+            rank += less ? 1 : 0;
+        }
+        if (rank < max_boxes) {
+            int32_t* o = boxes + 5 * rank;
+            o[0] = t_index;
+            o[1] = tile * a.x;
+            o[2] = tile * a.y;
+            o[3] = tile * a.z + tile - 1;
+            o[4] = tile * a.w + tile - 1;
+        }
+    }
+    if (threadIdx.x == 0) *n_boxes = nc;
+}
+
+hipError_t launch_detect(toi_ctx* c, const float* window, int t, int32_t* boxes, int max_boxes, int32_t* n_boxes) {
+    const int T = c->T;
+    const size_t lds = 2 * (size_t)T * T * sizeof(int32_t);
+    if (lds > 128 * 1024) return hipErrorNotSupported;
+    StageTimer timer(c, TOI_STAGE_DETECT);
+    hipLaunchKernelGGL(k_detect, dim3(1), dim3(1024), lds, c->stream, window, T, c->p.tile, t, c->det_scores,
+                       c->det_boxes, boxes, max_boxes, n_boxes);
+    return hipGetLastError();
+}
+
+}  // namespace toi

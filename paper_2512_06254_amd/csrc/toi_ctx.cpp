@@ -205,8 +205,8 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
         {(void**)&c->tiles, T * T * sizeof(TileStat)},
         {(void**)&c->scratch_d, 64 * sizeof(double)},
         {(void**)&c->scratch_i, 64 * sizeof(int32_t)},
-        {(void**)&c->det_scores, 2 * T * T * sizeof(float)},
-        {(void**)&c->det_labels, T * T * sizeof(int32_t)},
+        {(void**)&c->det_scores, 2 * T * T * sizeof(double)},
+        {(void**)&c->det_boxes, T * T * sizeof(int4)},
     };
     for (auto& a : allocs) {
         if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
@@ -243,11 +243,12 @@ toi_status toi_destroy(toi_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     for (auto& e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
     if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
     void* ptrs[] = {c->items, c->bin_order, c->bin_count, c->bin_off, c->bin_cursor, c->bin_list, c->tile_bits, c->row_bits,
                     c->adj_tp, c->item_gain, c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
-                    c->scratch_d, c->scratch_i, c->det_scores, c->det_labels, c->batch_desc};
+                    c->scratch_d, c->scratch_i, c->det_scores, c->det_boxes, c->batch_desc};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete c;

@@ -100,8 +100,8 @@ struct toi_ctx {
     toi::TileStat* tiles; // [T*T]
     double* scratch_d;    // small FP64 scratch (reductions)
     int32_t* scratch_i;   // small integer scratch (detection)
-    float* det_scores;    // [2][T*T] detection z-scores
-    int32_t* det_labels;  // [T*T]
+    double* det_scores;   // [2][T*T] detection scores (periodic, non-periodic)
+    int4* det_boxes;      // [T*T] component bounding boxes in tiles
 
     // per-stage timing (measurement only)
     bool prof_on;
@@ -109,10 +109,13 @@ struct toi_ctx {
     std::vector<int> prof_stage;          // stage of each recorded pair
     size_t prof_n;
 
-    // batched execution
+    // batched execution (a captured graph of the whole batch, cached by descriptor set)
     hipGraph_t batch_graph;
     hipGraphExec_t batch_exec;
-    void* batch_desc;     // device copy of the current snapshot descriptor
+    uint64_t batch_key;
+    int batch_n;
+    hipStream_t cap_stream;   // internal stream the batch is captured on (default priority)
+    void* batch_desc;
 };
 
 namespace toi {

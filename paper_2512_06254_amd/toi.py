@@ -71,7 +71,7 @@ _SIGS = {
     "toi_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
 
-STAGES = ("prep", "clear", "grid", "fft_rows", "fft_cols", "reproject", "tlisi", "degrid")
+STAGES = ("prep", "clear", "grid", "fft_rows", "fft_cols", "reproject", "tlisi", "degrid", "batch", "detect")
 
 
 def lib():
