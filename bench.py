@@ -144,6 +144,98 @@ def cpu_baseline(wl, snap_dev, n_slab, K, n_pixels=6):
     }
 
 
+def time_events(fn, reps):
+    """Average ms of fn() over reps calls, HIP events on the current stream."""
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def batched_leg(n_batch, reps, device):
+    """Uneven flagged snapshots: plain per-snapshot calls vs one captured-graph batch launch."""
+    import torch
+
+    import synth_inputs as S
+    from paper_2512_06254_amd import toi as T
+    wl = S.WORKLOADS["batched"]
+    n_slab, K = wl.forced_planes
+    pool = make_pool(wl, min(8, n_batch), device)
+    snaps = [pool[i % len(pool)] for i in range(n_batch)]
+    N, TT = wl.n_pix, wl.n_pix // 32
+    im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K, tile=32)
+    imgs = torch.zeros((n_batch, N, N), dtype=torch.float32, device=device)
+    tls = torch.zeros((max(n_batch - 2, 1), TT, TT), dtype=torch.float32, device=device)
+
+    def plain():
+        for i, sn in enumerate(snaps):
+            im.grid(sn)
+            im.image(out=imgs[i])
+            if i >= 2:
+                im.tlisi(imgs[i - 2], imgs[i - 1], imgs[i], out=tls[i - 2])
+
+    def batched():
+        im.image_batch(snaps, imgs, tls)
+
+    plain()
+    t0 = time.perf_counter()
+    batched()                                   # capture + instantiate + first replay
+    torch.cuda.synchronize()
+    capture_s = time.perf_counter() - t0
+    ms_plain = time_events(plain, reps) / n_batch
+    ms_batch = time_events(batched, reps) / n_batch
+    kept = [float(1.0 - p["flag"][:, :, 0].float().mean()) for p in pool]
+    im.close()
+    return {"workload": wl.name, "snapshots_per_launch": n_batch, "launches_timed": reps,
+            "ms_per_snapshot_batched": round(ms_batch, 4), "ms_per_snapshot_plain": round(ms_plain, 4),
+            "first_launch_with_capture_s": round(capture_s, 3),
+            "kept_sample_fraction": [round(k, 3) for k in kept]}
+
+
+def adjoint_leg(reps, device):
+    """Forward image and the hand-written adjoint (vis + gain gradients) on the 1024-channel workload."""
+    import torch
+
+    import synth_inputs as S
+    from paper_2512_06254_amd import toi as T
+    wl = S.WORKLOADS["adjoint"]
+    n_slab, K = wl.forced_planes
+    pool = make_pool(wl, 2, device)
+    N = wl.n_pix
+    im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K, n_ant=wl.n_ant)
+    out = torch.zeros((N, N), dtype=torch.float32, device=device)
+    grad = torch.randn((N, N), dtype=torch.float32, device=device)
+    gv = torch.empty_like(pool[0]["vis"])
+    gg = torch.empty_like(pool[0]["gains"])
+    state = {"i": 0}
+
+    def fwd():
+        sn = pool[state["i"] % 2]
+        im.grid(sn)
+        im.image(out=out)
+
+    def bwd():
+        import ctypes
+        sn = pool[state["i"] % 2]
+        desc = T.snapshot_struct(sn)
+        im._sync_stream()
+        T._check(T.lib().toi_degrid(im.ctx, T._ptr(grad), ctypes.byref(desc), T._ptr(gv), T._ptr(gg)), im.ctx)
+
+    fwd(); bwd()
+    torch.cuda.synchronize()
+    ms_f = time_events(fwd, reps)
+    fwd()
+    ms_b = time_events(bwd, reps)
+    im.close()
+    return {"workload": wl.name, "baselines": wl.n_row, "channels": wl.n_chan, "image": f"{N}x{N}",
+            "ms_forward": round(ms_f, 4), "ms_adjoint": round(ms_b, 4),
+            "gradients": "vis (complex64, all correlations) and 64 antenna gains"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +244,8 @@ def main():
     ap.add_argument("--workload", default="meerkat")
     ap.add_argument("--pool", type=int, default=4, help="distinct resident snapshots cycled through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=32, help="snapshots per batched graph launch (0 = skip)")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -247,10 +341,16 @@ def main():
         "stages": stages,
         "step_effective_GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
     }
+    im.close()
+    if args.batch > 0:
+        log(f"[bench] batched leg: {args.batch} uneven snapshots per graph launch")
+        out["batched"] = batched_leg(args.batch, 2, device)
+    if not args.no_adjoint:
+        log("[bench] adjoint leg")
+        out["adjoint"] = adjoint_leg(max(3, args.steps // 4), device)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(wl, pool[0], n_slab, K)
-    im.close()
     print(json.dumps(out), flush=True)
 
 

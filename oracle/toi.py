@@ -344,17 +344,20 @@ def image_cheb_at(r, x, W, omega, V, plan: Plan, j1, j2, n_pix, cell_deg):
     t1 = t1a[j1]; t2 = t2a[j2]
     t3 = t3_of(t1, t2, V)
     p, s = slab_of(r[:, 2], plan)
-    T = cheb_T(plan.K, s)                                           # (Nq, K)
+    order = np.argsort(p, kind="stable")                             # samples grouped by slab
+    bounds = np.searchsorted(p[order], np.arange(plan.n_slab + 1))
+    rs, xs = r[order], x[order]
+    T = cheb_T(plan.K, s[order])                                     # (Nq, K)
     out = np.zeros(j1.size)
     for i in range(j1.size):
         if not np.isfinite(t3[i]):
             continue
-        e = x * np.exp(2j * math.pi * (r[:, 0] * t1[i] + r[:, 1] * t2[i]))
+        e = xs * np.exp(2j * math.pi * (rs[:, 0] * t1[i] + rs[:, 1] * t2[i]))
         c = cheb_coeffs(2.0 * math.pi * plan.dr3 * t3[i], plan.K)
         acc = 0.0 + 0.0j
         for ps in range(plan.n_slab):
-            sel = p == ps
-            mk = T[sel].T @ e[sel]                                     # M_{p,k} at this pixel
+            a, b = bounds[ps], bounds[ps + 1]
+            mk = T[a:b].T @ e[a:b]                                   # M_{p,k} at this pixel
             acc += np.exp(2j * math.pi * plan.centre(ps) * t3[i]) * (c @ mk)
         out[i] = np.real(acc) / (omega * W)
     return out
