@@ -168,6 +168,7 @@ def batched_leg(n_batch, reps, device):
     snaps = [pool[i % len(pool)] for i in range(n_batch)]
     N, TT = wl.n_pix, wl.n_pix // 32
     im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K, tile=32)
+    variant, _ = im.tune(pool[0])
     imgs = torch.zeros((n_batch, N, N), dtype=torch.float32, device=device)
     tls = torch.zeros((max(n_batch - 2, 1), TT, TT), dtype=torch.float32, device=device)
 
@@ -192,7 +193,7 @@ def batched_leg(n_batch, reps, device):
     im.close()
     return {"workload": wl.name, "snapshots_per_launch": n_batch, "launches_timed": reps,
             "ms_per_snapshot_batched": round(ms_batch, 4), "ms_per_snapshot_plain": round(ms_plain, 4),
-            "first_launch_with_capture_s": round(capture_s, 3),
+            "first_launch_with_capture_s": round(capture_s, 3), "tuned_variant": variant,
             "kept_sample_fraction": [round(k, 3) for k in kept]}
 
 
@@ -279,6 +280,8 @@ def main():
     pool = make_pool(wl, args.pool, device)
     im = T.Imager(wl.n_pix, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, mode=3, n_slab=n_slab, cheb_k=K,
                   n_ant=wl.n_ant, tile=32)
+    variant, tune_ms = im.tune(pool[0])
+    log(f"[bench] autotuned gridder variant {variant}: " + ", ".join(f"{m:.2f}" for m in tune_ms) + " ms")
     N = wl.n_pix
     ring = [torch.zeros((N, N), dtype=torch.float32, device=device) for _ in range(3)]
     tl = torch.zeros((N // 32, N // 32), dtype=torch.float32, device=device)
@@ -340,6 +343,8 @@ def main():
         "roofline": roofline,
         "stages": stages,
         "step_effective_GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+        "tuning": {"variant": variant, "grid_plus_image_ms_per_variant": [round(m, 3) for m in tune_ms],
+                   "variants": "bit0 two cells/lane, bit1 1024-thread groups, bit2 8 planes per LDS pass"},
     }
     im.close()
     if args.batch > 0:

@@ -156,6 +156,19 @@ toi_status fitrig_detect(toi_ctx* ctx, const float* window, int32_t t,
 toi_status toi_image_batch(toi_ctx* ctx, const toi_snapshot* snaps, int32_t n,
                            float* images_out, float* tlisi_out);
 
+/* Autotuning of the gridder (batched use): the variants differ in footprint
+ * cells per lane (bit 0: two, else one), workgroup width (bit 1: 1024 threads,
+ * else 512) and the plane schedule (bit 2: 8 planes per LDS pass of a grid
+ * tile, else 16).  All variants compute the same image.  toi_tune
+ * synchronises, times grid + image of `sample` with every variant (HIP events,
+ * after one warm-up), keeps the fastest in the context and returns it in
+ * *variant_out; ms_out (host, TOI_TUNE_VARIANTS entries, nullable) receives
+ * each variant's time.  It overwrites the context's workspaces.
+ * toi_set_tuning selects a variant directly (default 0). */
+#define TOI_TUNE_VARIANTS 8
+toi_status toi_tune(toi_ctx* ctx, const toi_snapshot* sample, int32_t* variant_out, float* ms_out);
+toi_status toi_set_tuning(toi_ctx* ctx, int32_t variant);
+
 /* Synchronise and report the last gridded snapshot's plan (host outputs, each
  * nullable): V row-major, omega, W (sum of weights), N_slab, K, and the status
  * word.  Diagnostics only: the imaging loop never calls it. */

@@ -179,7 +179,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
 
     const size_t N = c->N, M = c->M, P = c->P_cap, T = c->T;
     c->NT = c->M / kTile;
-    c->NG_max = std::max(1, (c->P_cap + 7) / 8);
+    c->NG_max = std::max(1, 2 * ((c->P_cap + 7) / 8));   // covers plane groups of 8 or 16
     c->n_items_max = std::max(1, p.n_row_max * ((p.n_chan + kItemChans - 1) / kItemChans));
     c->bin_cap = c->n_items_max * 8 + 1024;
     const size_t NT = c->NT, NG = c->NG_max, words = (NT + 31) / 32;
@@ -363,6 +363,52 @@ toi_status toi_profile_read(toi_ctx* c, double* total_ms, int32_t* launches) {
         if (total_ms) total_ms[s] = tot[s];
         if (launches) launches[s] = cnt[s];
     }
+    return TOI_OK;
+}
+
+toi_status toi_set_tuning(toi_ctx* c, int32_t variant) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_set_tuning: ctx is NULL");
+    if (variant < 0 || variant >= TOI_TUNE_VARIANTS) return fail(c, TOI_EINVAL, "toi_set_tuning: variant out of range");
+    c->tuning = variant;
+    return TOI_OK;
+}
+
+toi_status toi_tune(toi_ctx* c, const toi_snapshot* s, int32_t* variant_out, float* ms_out) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_tune: ctx is NULL");
+    toi_status st = check_snapshot(c, s, "toi_tune");
+    if (st != TOI_OK) return st;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    int best = c->tuning;
+    float best_ms = 1e30f;
+    for (int v = 0; v < TOI_TUNE_VARIANTS && e == hipSuccess; ++v) {
+        c->tuning = v;
+        float ms = 0.f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {   // first repetition warms up
+            if (rep == 1) e = hipEventRecord(a, c->stream);
+            if (e == hipSuccess) e = launch_prep(c, *s);
+            if (e == hipSuccess) e = launch_grid(c, *s);
+            if (e == hipSuccess) e = launch_image(c, c->adj_tp, nullptr);
+        }
+        if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        ms *= 0.5f;
+        if (ms_out) ms_out[v] = ms;
+        if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    c->prof_on = prof;
+    c->tuning = best;
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_check(c, e, "toi_tune");
+    if (variant_out) *variant_out = best;
     return TOI_OK;
 }
 

@@ -76,26 +76,27 @@ __device__ inline int slab_index(double r3, const DevPlan* __restrict__ P) {
     return max(0, min(P->n_slab - 1, p));
 }
 
-// Plane groups: whole slabs (sg of them) when K <= kGroupPlanes, otherwise
-// two groups per slab holding orders [0, kp) and [kp, K).
+// Plane groups (one LDS pass of the gridder each, at most gp planes): whole
+// slabs (sg of them) when K <= gp, otherwise `parts` groups per slab holding
+// orders [part kp, min(K, (part + 1) kp)).
 __device__ inline int group_of_slab(int p, const DevPlan* __restrict__ P) {
-    return P->K <= kGroupPlanes ? p / P->sg : 2 * p;
+    return P->K <= P->gp ? p / P->sg : p * P->parts;
 }
 __device__ inline int group_of_plane(int plane, const DevPlan* __restrict__ P) {
     const int p = plane / P->K, k = plane % P->K;
-    return P->K <= kGroupPlanes ? p / P->sg : 2 * p + (k >= P->kp ? 1 : 0);
+    return P->K <= P->gp ? p / P->sg : p * P->parts + k / P->kp;
 }
 __device__ inline void group_range(int g, const DevPlan* __restrict__ P, int& s0, int& s1, int& k0, int& k1) {
-    if (P->K <= kGroupPlanes) {
+    if (P->K <= P->gp) {
         s0 = g * P->sg;
         s1 = min(P->n_slab, s0 + P->sg);
         k0 = 0;
         k1 = P->K;
     } else {
-        s0 = g / 2;
+        s0 = g / P->parts;
         s1 = s0 + 1;
-        k0 = (g & 1) ? P->kp : 0;
-        k1 = (g & 1) ? P->K : P->kp;
+        k0 = (g % P->parts) * P->kp;
+        k1 = min(P->K, k0 + P->kp);
     }
 }
 

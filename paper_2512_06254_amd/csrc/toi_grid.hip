@@ -20,6 +20,8 @@
 // Coordinates are formed in FP64 (X = M/2 - r1 M Delta, Y = M/2 + r2 M Delta)
 // and split into an integer cell and an FP32 offset before the kernel is
 // evaluated; values and accumulation are FP32.
+#include <algorithm>
+
 #include "toi_device.h"
 #include "toi_grid.h"
 #include "toi_internal.h"
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     box.ty1 = ((int)ceil(yhi - 4.0) + 7) >> 5;
     const int p0 = mode == 3 ? slab_index(rlo, P) : 0, p1 = mode == 3 ? slab_index(rhi, P) : 0;
     box.g0 = group_of_slab(min(p0, p1), P);
-    box.g1 = group_of_slab(max(p0, p1), P) + ((P->K > kGroupPlanes) ? 1 : 0);
+    box.g1 = group_of_slab(max(p0, p1), P) + (P->K > P->gp ? P->parts - 1 : 0);
     if (lane == 0) items[item] = box;
     // count into bins, lanes spread over the (group, tile) combinations
     const int nx = box.tx1 - box.tx0 + 1, ny = box.ty1 - box.ty0 + 1, ng = box.g1 - box.g0 + 1;
@@ -180,15 +182,29 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
 }
 
 // ---------------------------------------------------------------- 3. tiles
-template <int KACC>
-__global__ __launch_bounds__(512) void k_grid_tiles(
+// LDS tile layout: planar real and imaginary parts, [plane][ly][swizzled lx],
+// the column rotated by 8 (ly / 2 mod 4) so that the 64 cells of one 8 x 8
+// footprint fall in distinct banks when they are added together.
+__device__ inline int tile_index(int ly, int lx) { return ly * kTile + ((lx + 8 * ((ly >> 1) & 3)) & (kTile - 1)); }
+
+// Variants (chosen by the autotuner): CELLS footprint cells per lane.  With
+// CELLS = 1 all 64 lanes serve one sample, lane (i, j) owning x = i (mod 8),
+// y = j (mod 8); with CELLS = 2 the two half-waves take alternate samples and
+// lane (i, j) of a half owns x = i (mod 4) -- cells dx and dx + 4 -- and
+// y = j (mod 8).  Each lane keeps its cells' plane values in registers until
+// the track moves them (Romein, ICS 2012), then adds them to LDS.
+template <int KACC, int CELLS>
+__global__ __launch_bounds__(1024) void k_grid_tiles(
     const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
     const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
     const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_chan, int n_corr,
     uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
     const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
     const int32_t* __restrict__ order, const int32_t* __restrict__ n_active, float2* __restrict__ grid) {
-    extern __shared__ float lds[];                      // [planes][kTile][kTile] x (re, im)
+    extern __shared__ float lds[];                      // re[gp][kTile*kTile], then im[gp][kTile*kTile]
+    constexpr int TT = kTile * kTile;
+    constexpr int XM = 8 / CELLS;                       // x residue modulus of a lane
+    constexpr int SUBL = 64 / CELLS;                    // lanes per sample
     const int tiles = NT * NT;
     // Non-empty bins in decreasing order of work, dealt round-robin over the
     // XCDs by the dispatcher (tiles with samples cluster around the uv centre,
@@ -200,18 +216,21 @@ __global__ __launch_bounds__(512) void k_grid_tiles(
     if (g >= P->ng) return;
     const int b0 = bin_off[(size_t)g * tiles + tile];
     const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
-    if (b1 <= b0) return;                               // empty tile: never written
+    if (b1 <= b0) return;
     int s0, s1, k0, k1;
     group_range(g, P, s0, s1, k0, k1);
     const int nk = k1 - k0;
     const int n_planes = (s1 - s0) * nk;
-    for (int i = threadIdx.x; i < n_planes * kTile * kTile * 2; i += blockDim.x) lds[i] = 0.f;
+    float* lre = lds;
+    float* lim = lds + P->gp * TT;
+    for (int i = threadIdx.x; i < n_planes * TT; i += blockDim.x) { lre[i] = 0.f; lim[i] = 0.f; }
     __syncthreads();
 
     const int tx = tile % NT, ty = tile / NT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    const int li = lane & 7, lj = lane >> 3;
-    const double half = 0.5 * M;
+    const int sub = lane / SUBL, sl = lane % SUBL;
+    const int li = sl % XM, lj = sl / XM;
+    const double hM = 0.5 * M;
     const bool cheb = (mode == 3) && (P->dr3 > 0.0);
     const double dr3 = P->dr3, r3min = P->r3min;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
@@ -239,13 +258,12 @@ __global__ __launch_bounds__(512) void k_grid_tiles(
                         sp = slab_index(r3, P);
                         ss = (float)((r3 - (r3min + (2 * sp + 1) * dr3)) / dr3);
                     }
-                    const double X = half + trk.ax * nu, Y = half + trk.ay * nu;
+                    const double X = hM + trk.ax * nu, Y = hM + trk.ay * nu;
                     const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
                     ix = (int)fx0;
                     iy = (int)fy0;
                     ox = (float)(X - fx0);                 // in (3, 4]
                     oy = (float)(Y - fy0);
-                    // does the 8 x 8 footprint touch this tile (periodic grid)?
                     const int ddx = (ix - tx * kTile) & (M - 1), ddy = (iy - ty * kTile) & (M - 1);
                     act = (sp >= s0 && sp < s1) && (ddx < kTile || ddx >= M - 7) && (ddy < kTile || ddy >= M - 7);
                     vr0 = xr * gr.x - xi * gr.y;
@@ -255,52 +273,100 @@ __global__ __launch_bounds__(512) void k_grid_tiles(
         }
         uint64_t pending = __ballot(act);
         int cur_x = 0, cur_y = 0, cur_p = -1;
-        bool cur_in = false;
-        float ar[KACC], ai[KACC];
+        bool in[CELLS];
+        float ar[CELLS][KACC], ai[CELLS][KACC];
 #pragma unroll
-        for (int k = 0; k < KACC; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
+        for (int m = 0; m < CELLS; ++m) {
+            in[m] = false;
+#pragma unroll
+            for (int k = 0; k < KACC; ++k) { ar[m][k] = 0.f; ai[m][k] = 0.f; }
+        }
 
         auto flush = [&]() {
-            if (!cur_in) return;
-            const int lx = cur_x & (kTile - 1), ly = cur_y & (kTile - 1);
-            float* base = lds + 2 * ((size_t)((cur_p - s0) * nk) * kTile * kTile + ly * kTile + lx);
+            const int ly = cur_y & (kTile - 1);
+            const int base = (cur_p - s0) * nk * TT;
 #pragma unroll
-            for (int k = 0; k < KACC; ++k) {
-                if (k < nk) {
-                    atomicAdd(base + 2 * (size_t)k * kTile * kTile, ar[k]);
-                    atomicAdd(base + 2 * (size_t)k * kTile * kTile + 1, ai[k]);
+            for (int m = 0; m < CELLS; ++m) {
+                if (!in[m]) continue;
+                const int ci = base + tile_index(ly, (cur_x + m * XM) & (kTile - 1));
+#pragma unroll
+                for (int k = 0; k < KACC; ++k) {
+                    if (k < nk) {
+                        atomicAdd(lre + ci + k * TT, ar[m][k]);
+                        atomicAdd(lim + ci + k * TT, ai[m][k]);
+                    }
                 }
             }
         };
 
-        while (pending) {                               // wave-uniform walk over the active samples
-            const int q = __ffsll((unsigned long long)pending) - 1;
-            pending &= pending - 1;
-            const int qx = __builtin_amdgcn_readlane(ix, q), qy = __builtin_amdgcn_readlane(iy, q);
-            const int p = __builtin_amdgcn_readlane(sp, q);
-            const float qox = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ox), q));
-            const float qoy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(oy), q));
-            const float qvr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vr0), q));
-            const float qvi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vi0), q));
-            const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ss), q));
-            const int dx = (li - qx) & 7, dy = (lj - qy) & 7;
+        while (pending) {                               // wave-uniform walk, CELLS samples per step
+            int qs[CELLS];
+            bool have[CELLS];
+#pragma unroll
+            for (int m = 0; m < CELLS; ++m) {
+                have[m] = pending != 0;
+                qs[m] = have[m] ? __ffsll((unsigned long long)pending) - 1 : 0;
+                if (have[m]) pending &= pending - 1;
+            }
+            bool mine = have[0];
+            int qx = __builtin_amdgcn_readlane(ix, qs[0]), qy = __builtin_amdgcn_readlane(iy, qs[0]);
+            int p = __builtin_amdgcn_readlane(sp, qs[0]);
+            int bx = __builtin_amdgcn_readlane(__float_as_int(ox), qs[0]);
+            int by = __builtin_amdgcn_readlane(__float_as_int(oy), qs[0]);
+            int br = __builtin_amdgcn_readlane(__float_as_int(vr0), qs[0]);
+            int bi = __builtin_amdgcn_readlane(__float_as_int(vi0), qs[0]);
+            int bs = __builtin_amdgcn_readlane(__float_as_int(ss), qs[0]);
+#pragma unroll
+            for (int m = 1; m < CELLS; ++m) {
+                if (sub == m) {
+                    mine = have[m];
+                    qx = __builtin_amdgcn_readlane(ix, qs[m]);
+                    qy = __builtin_amdgcn_readlane(iy, qs[m]);
+                    p = __builtin_amdgcn_readlane(sp, qs[m]);
+                    bx = __builtin_amdgcn_readlane(__float_as_int(ox), qs[m]);
+                    by = __builtin_amdgcn_readlane(__float_as_int(oy), qs[m]);
+                    br = __builtin_amdgcn_readlane(__float_as_int(vr0), qs[m]);
+                    bi = __builtin_amdgcn_readlane(__float_as_int(vi0), qs[m]);
+                    bs = __builtin_amdgcn_readlane(__float_as_int(ss), qs[m]);
+                }
+            }
+            if (!mine) continue;
+            const float qox = __int_as_float(bx), qoy = __int_as_float(by);
+            const float qvr = __int_as_float(br), qvi = __int_as_float(bi), s = __int_as_float(bs);
+            const int dx = (li - qx) & (XM - 1), dy = (lj - qy) & 7;
             const int cx = qx + dx, cy = qy + dy;
             if (cx != cur_x || cy != cur_y || p != cur_p) {
                 flush();
                 cur_x = cx; cur_y = cy; cur_p = p;
-                cur_in = (((cx & (M - 1)) >> 5) == tx) && (((cy & (M - 1)) >> 5) == ty);
+                const bool yin = ((cy & (M - 1)) >> 5) == ty;
 #pragma unroll
-                for (int k = 0; k < KACC; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
+                for (int m = 0; m < CELLS; ++m) {
+                    in[m] = yin && ((((cx + m * XM) & (M - 1)) >> 5) == tx);
+#pragma unroll
+                    for (int k = 0; k < KACC; ++k) { ar[m][k] = 0.f; ai[m][k] = 0.f; }
+                }
             }
-            if (!cur_in) continue;
-            const float wgt = es_kernel(((float)dx - qox) * 0.25f) * es_kernel(((float)dy - qoy) * 0.25f);
-            const float vr = wgt * qvr, vi = wgt * qvi;
+            bool any = false;
+#pragma unroll
+            for (int m = 0; m < CELLS; ++m) any |= in[m];
+            if (!any) continue;
+            const float wy = es_kernel(((float)dy - qoy) * 0.25f);
+            float vr[CELLS], vi[CELLS];
+#pragma unroll
+            for (int m = 0; m < CELLS; ++m) {
+                const float w = es_kernel(((float)(dx + m * XM) - qox) * 0.25f) * wy;
+                vr[m] = w * qvr;
+                vi[m] = w * qvi;
+            }
             float t, tm1;
             cheb_start(s, k0, t, tm1);                  // t = T_{k0}(s), tm1 = T_{k0 - 1}(s)
 #pragma unroll
             for (int k = 0; k < KACC; ++k) {
-                ar[k] += t * vr;
-                ai[k] += t * vi;
+#pragma unroll
+                for (int m = 0; m < CELLS; ++m) {
+                    ar[m][k] += t * vr[m];
+                    ai[m][k] += t * vi[m];
+                }
                 const float tn = 2.f * s * t - tm1;
                 tm1 = t;
                 t = tn;
@@ -310,11 +376,12 @@ __global__ __launch_bounds__(512) void k_grid_tiles(
     }
     __syncthreads();
     // write the tile's planes (only the planes of this group)
-    for (int i = threadIdx.x; i < n_planes * kTile * kTile; i += blockDim.x) {
-        const int pl = i / (kTile * kTile), cell = i % (kTile * kTile);
+    for (int i = threadIdx.x; i < n_planes * TT; i += blockDim.x) {
+        const int pl = i / TT, cell = i % TT;
+        const int ly = cell / kTile, lx = cell % kTile;
         const int pg = (s0 + pl / nk) * P->K + k0 + pl % nk;   // global plane index
-        const int y = ty * kTile + cell / kTile, x = tx * kTile + cell % kTile;
-        grid[((size_t)pg * M + y) * M + x] = make_float2(lds[2 * i], lds[2 * i + 1]);
+        const int li2 = pl * TT + tile_index(ly, lx);
+        grid[((size_t)pg * M + ty * kTile + ly) * M + tx * kTile + lx] = make_float2(lre[li2], lim[li2]);
     }
 }
 
@@ -341,20 +408,32 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
     }
     if (n_items == 0) return hipGetLastError();
     StageTimer timer(c, TOI_STAGE_GRID);
-    const size_t lds_bytes = (size_t)kGroupPlanes * kTile * kTile * 2 * sizeof(float);
+    const int gp = (c->tuning & kTuneEightPlanes) ? 8 : kGroupPlanes;
+    const size_t lds_bytes = (size_t)gp * kTile * kTile * 2 * sizeof(float);
+    const int threads = (c->tuning & kTuneWide) ? 1024 : 512;
+    const int kacc = std::min(c->kmax, gp);
+    const bool two = (c->tuning & kTuneTwoCells) != 0;
     const int blocks = n_bins;
 #define TOI_TILE_ARGS                                                                                         \
-    dim3(blocks), dim3(512), lds_bytes, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag, s.freq,      \
+    dim3(blocks), dim3(threads), lds_bytes, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag, s.freq,   \
         s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, NT, \
         cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
-    if (c->kmax <= 1)
-        hipLaunchKernelGGL(k_grid_tiles<1>, TOI_TILE_ARGS);
-    else if (c->kmax <= 4)
-        hipLaunchKernelGGL(k_grid_tiles<4>, TOI_TILE_ARGS);
-    else if (c->kmax <= 8)
-        hipLaunchKernelGGL(k_grid_tiles<8>, TOI_TILE_ARGS);
+#define TOI_TILE_LAUNCH(KA)                                        \
+    do {                                                           \
+        if (two)                                                   \
+            hipLaunchKernelGGL((k_grid_tiles<KA, 2>), TOI_TILE_ARGS); \
+        else                                                       \
+            hipLaunchKernelGGL((k_grid_tiles<KA, 1>), TOI_TILE_ARGS); \
+    } while (0)
+    if (kacc <= 1)
+        TOI_TILE_LAUNCH(1);
+    else if (kacc <= 4)
+        TOI_TILE_LAUNCH(4);
+    else if (kacc <= 8)
+        TOI_TILE_LAUNCH(8);
     else
-        hipLaunchKernelGGL(k_grid_tiles<16>, TOI_TILE_ARGS);
+        TOI_TILE_LAUNCH(16);
+#undef TOI_TILE_LAUNCH
 #undef TOI_TILE_ARGS
     return hipGetLastError();
 }

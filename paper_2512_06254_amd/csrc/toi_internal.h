@@ -32,16 +32,25 @@ struct DevPlan {
     int32_t n_slab, K, planes;
     uint32_t status;
     int32_t miller_top;   // starting order of the Bessel backward recurrence
-    int32_t ng;           // plane groups gridded together (<= kGroupPlanes planes each)
-    int32_t sg;           // slabs per group when K <= kGroupPlanes
-    int32_t kp;           // Chebyshev orders per group when K > kGroupPlanes
+    int32_t ng;           // plane groups gridded together (at most gp planes each)
+    int32_t sg;           // slabs per group when K <= gp
+    int32_t kp;           // Chebyshev orders per group when K > gp
+    int32_t parts;        // groups per slab when K > gp (1 otherwise)
+    int32_t gp;           // planes per group (LDS pass of the gridder)
+    int32_t pad2_[3];
 };
 
 // Binned gridding: grid tiles of kTile x kTile cells, work items of kItemChans
 // channels of one row, up to kGroupPlanes planes accumulated per tile pass.
 constexpr int kTile = 32;
 constexpr int kItemChans = 64;
-constexpr int kGroupPlanes = 16;
+constexpr int kGroupPlanes = 16;   // largest plane group held in LDS
+
+// Gridder variant chosen by the autotuner (toi_tune / toi_set_tuning):
+// bit 0: two footprint cells per lane (else one); bit 1: 1024-thread
+// workgroups (else 512); bit 2: 8 planes per LDS pass (else 16).
+constexpr int kTuneTwoCells = 1, kTuneWide = 2, kTuneEightPlanes = 4;
+constexpr int kTuneDefault = 0;
 
 // Bin of one work item: tile and group ranges it touches (unwrapped tile
 // indices; wrapped modulo the tiles per axis when used).
@@ -73,6 +82,7 @@ struct toi_ctx {
     int P_cap;            // plane capacity
     int forced_K;         // 0 when chosen on the device
     int kmax;             // accumulator width of the gridder (>= K)
+    int tuning;           // gridder variant (kTune* bits)
     std::string err;
 
     // workspace (device)

@@ -94,7 +94,7 @@ __device__ inline void positive_major(double e[3]) {
 }
 
 __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, const RowStat* __restrict__ rows,
-                                               int n_row, int mode, DevPlan* __restrict__ plan) {
+                                               int n_row, int mode, int gp, DevPlan* __restrict__ plan) {
     __shared__ double red[16][4];
     __shared__ double V_s[9];
     __shared__ uint32_t status_s;
@@ -160,8 +160,10 @@ __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, c
         P.K = 1;
         P.planes = 1;
         P.ng = 1;
-        P.sg = kGroupPlanes;
+        P.sg = gp;
         P.kp = 1;
+        P.parts = 1;
+        P.gp = gp;
         P.status = st;
         *plan = P;
         for (int i = 0; i < 9; ++i) V_s[i] = P.V[i];
@@ -295,14 +297,17 @@ __global__ __launch_bounds__(256) void k_plan(double alpha_target, double gamma,
         plan->K = K;
         plan->planes = plan->n_slab * K;
         plan->miller_top = 2 * ((K + 16 + (int)ceil(1.5 * fabs(a_slab))) / 2);
-        if (K <= kGroupPlanes) {
-            plan->sg = kGroupPlanes / K;
+        const int gp = plan->gp;
+        if (K <= gp) {
+            plan->sg = gp / K;
             plan->kp = K;
+            plan->parts = 1;
             plan->ng = (plan->n_slab + plan->sg - 1) / plan->sg;
         } else {
             plan->sg = 1;
-            plan->kp = (K + 1) / 2;
-            plan->ng = 2 * plan->n_slab;
+            plan->parts = (K + gp - 1) / gp;
+            plan->kp = (K + plan->parts - 1) / plan->parts;
+            plan->ng = plan->parts * plan->n_slab;
         }
         if (plan->planes > p_cap || plan->ng > ng_cap) plan->status |= TOI_STATUS_PLANES;
     }
@@ -314,7 +319,8 @@ hipError_t launch_prep(toi_ctx* c, const toi_snapshot& s) {
     if (s.n_row > 0)
         hipLaunchKernelGGL(k_row_stats, dim3(s.n_row), dim3(256), 0, c->stream, s.weight, s.flag, s.freq,
                            p.n_chan, p.n_corr, p.corr_mask, c->rows);
-    hipLaunchKernelGGL(k_basis, dim3(1), dim3(256), 0, c->stream, s.uvw, c->rows, s.n_row, p.mode, c->plan);
+    const int gp = (c->tuning & kTuneEightPlanes) ? 8 : kGroupPlanes;
+    hipLaunchKernelGGL(k_basis, dim3(1), dim3(256), 0, c->stream, s.uvw, c->rows, s.n_row, p.mode, gp, c->plan);
     if (p.mode == 3) {
         const double cell = p.cell_deg * kPi / 180.0;
         const long total = (long)c->N * c->N;

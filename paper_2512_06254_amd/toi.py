@@ -68,8 +68,13 @@ _SIGS = {
     "toi_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "toi_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int32)]),
+    "toi_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Snapshot), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_float)]),
+    "toi_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "toi_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
+
+TUNE_VARIANTS = 8
 
 STAGES = ("prep", "clear", "grid", "fft_rows", "fft_cols", "reproject", "tlisi", "degrid", "batch", "detect")
 
@@ -217,6 +222,18 @@ class Imager:
         self._sync_stream()
         _check(lib().toi_profile_read(self.ctx, ms, n), self.ctx)
         return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+    def tune(self, snap: dict):
+        """Time every gridder variant on ``snap``, keep the fastest; (variant, [ms per variant])."""
+        desc = snapshot_struct(snap)
+        v = ctypes.c_int32()
+        ms = (ctypes.c_float * TUNE_VARIANTS)()
+        self._sync_stream()
+        _check(lib().toi_tune(self.ctx, ctypes.byref(desc), ctypes.byref(v), ms), self.ctx)
+        return v.value, list(ms)
+
+    def set_tuning(self, variant: int):
+        _check(lib().toi_set_tuning(self.ctx, variant), self.ctx)
 
     def plan_info(self) -> dict:
         V = (ctypes.c_double * 9)()

@@ -113,3 +113,23 @@ def test_three_snapshot_tlisi_end_to_end():
     print("end-to-end tlisi max err", np.abs(got - want).max(), flush=True)
     assert np.abs(got - want).max() < 1e-3
     im.close()
+
+
+@pytest.mark.parametrize("ns,k", [(1, 16), (3, 8), (2, 12), (1, 24)])
+def test_every_gridder_variant_matches_oracle(ns, k):
+    from paper_2512_06254_amd import toi as T
+    wl = S.scaled(S.WORKLOADS["tiny"], n_ant=12, n_chan=80, n_pix=128, cell_arcsec=30.0, sigma_h_m=80.0, seed=7)
+    snap = S.make_snapshot(wl, 0)
+    ref = O.image_snapshot(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=ns, K=k)
+    im = T.Imager(wl.n_pix, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=ns, cheb_k=k, max_planes=48)
+    d = T.to_device(snap)
+    best, ms = im.tune(d)
+    assert 0 <= best < T.TUNE_VARIANTS and all(m > 0 for m in ms)
+    for v in range(T.TUNE_VARIANTS):
+        im.set_tuning(v)
+        im.grid(d)
+        img, tp = im.image(tplane=True)
+        e = max_rel_err(tp.cpu().numpy(), ref.tplane)
+        print(f"[variant {v} ({ns},{k})] t-plane err {e:.3e}", flush=True)
+        assert e <= IMAGE_TOL
+    im.close()
