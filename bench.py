@@ -61,7 +61,8 @@ def make_pool(wl, n_pool, device):
     return pool
 
 
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (dense)
+FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X FP32 matrix cores (dense)
 
 
 def grid_flops(wl, P):
@@ -320,12 +321,15 @@ def main():
         stages["grid"]["TFLOPs"] = round(grid_flops(wl, P) / (stages["grid"]["avg_ms"] * 1e-3) / 1e12, 2)
         stages["grid"]["GBps"] = None
     dom = max((s for s in stages if s in sb), key=lambda s: stages[s]["avg_ms"] * stages[s]["launches"])
-    if dom == "grid":   # the gridder is bound by FP32 vector arithmetic, not by HBM
+    if dom == "grid":   # the gridder is bound by FP32 arithmetic (matrix cores or vector ALU), not by HBM
         ach = grid_flops(wl, P) / (stages[dom]["avg_ms"] * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
-                    "traffic": recorded_traffic() if wl.name == "meerkat" else None,
-                    "kernel": "k_grid_tiles", "algorithmic_flops": grid_flops(wl, P)}
+        mfma = bool(variant & 1) and K >= 8
+        kname = "k_grid_tiles_mfma" if mfma else "k_grid_tiles"
+        roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(ach, 2),
+                    "peak": FP32_MFMA_PEAK_TFLOPS if mfma else FP32_VECTOR_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(ach / (FP32_MFMA_PEAK_TFLOPS if mfma else FP32_VECTOR_PEAK_TFLOPS), 4),
+                    "traffic": recorded_traffic(kname) if wl.name == "meerkat" else None,
+                    "kernel": kname, "algorithmic_flops": grid_flops(wl, P)}
     else:
         ach = sb[dom] / (stages[dom]["avg_ms"] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -344,7 +348,7 @@ def main():
         "stages": stages,
         "step_effective_GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
         "tuning": {"variant": variant, "grid_plus_image_ms_per_variant": [round(m, 3) for m in tune_ms],
-                   "variants": "bit0 two cells/lane, bit1 1024-thread groups, bit2 8 planes per LDS pass"},
+                   "variants": "bit0 matrix cores (v_mfma), bit1 1024-thread groups, bit2 8 planes per LDS pass"},
     }
     im.close()
     if args.batch > 0:

@@ -11,7 +11,7 @@
 //   3. row pass: the same along x, giving the gradient of every grid plane in
 //      the rows that hold samples;
 //   4. degridding: each sample gathers the kernel-weighted plane gradients of
-//      its 8 x 8 footprint and sums them with T_k(s);
+//      its 8 x 8 footprint and sums them with T_k(s) (Romein-style walk);
 //   5. visibilities: grad V_k = conj(g_a1 conj(g_a2)) W_k (1 - F_k) grad x;
 //      gains: per work item sum_c conj(y_c) grad x_c (y = pre-gain weighted
 //      sum), reduced per antenna in FP64 in a fixed order.
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
     constexpr int KEEP = E / 2;
     constexpr int T = M / E;
     __shared__ float2 lds[M];
-    __shared__ float2 tw_s[M / 2];
+    __shared__ float2 tw_s[M];
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
     if (plan->status & kStatusFatal) return;
     load_twiddles<M>(tw_s, tw);
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict_
     constexpr int T = M / E;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[M];
-    __shared__ float2 tw_s[M / 2];
+    __shared__ float2 tw_s[M];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
     const int plane = id / nbands, band = id % nbands;
     if ((plan->status & kStatusFatal) || plane >= plan->planes) return;
@@ -233,16 +233,28 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict_
     }
 }
 
-// 4-5. degridding gather, visibility gradients and per-item gain partials
+// 4-5. Gather degridding (transpose of S4), one wavefront per work item (64
+// channels of a row), walked in channel order like the gridder: lane (i, j)
+// holds the plane gradients G_k of its footprint cell (x = i, y = j mod 8),
+// reloaded from the grid only when the footprint start or the slab moves
+// (Romein, ICS 2012).  Per sample q: grad x_q = sum over the 64 cells of
+// w_q(cell) sum_k T_k(s_q) G_k(cell) -- each lane forms its cell's term with
+// the weights and Chebyshev values staged in LDS, and a DPP reduction over
+// the wavefront sums them; lane q keeps the result.  KACC >= K orders are
+// held in registers.
+template <int KACC>
 __global__ __launch_bounds__(256) void k_degrid(
     const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
     const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
     const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_chan, int n_corr,
     uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, double cell_rad, int n_items,
     const float2* __restrict__ gg, float2* __restrict__ grad_vis, double2* __restrict__ item_gain) {
-    const int lane = threadIdx.x & 63;
-    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    __shared__ float stage[4][64 * (16 + KACC)];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int item = blockIdx.x * (blockDim.x >> 6) + wave;
     if (item >= n_items) return;
+    float* sw = stage[wave];         // [64][16]: wx[0..7], wy[0..7]
+    float* sT = sw + 64 * 16;        // [64][KACC]: T_k(s)
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int r = item / n_chunks;
     const int c = (item % n_chunks) * kItemChans + lane;
@@ -251,11 +263,12 @@ __global__ __launch_bounds__(256) void k_degrid(
     float gxr = 0.f, gxi = 0.f, yr = 0.f, yi = 0.f;
     float w = 0.f;
     if (live) w = sample_value(vis, weight, flag, base, n_corr, mask, yr, yi);
-    if (live && w > 0.f && !(P->status & kStatusFatal)) {
+    const bool act = live && w > 0.f && !(P->status & kStatusFatal);
+    int pk = 0, p = 0;
+    float s = 0.f, ox = 4.f, oy = 4.f;
+    if (act) {
         const Track trk = row_track(uvw, r, P, M, cell_rad);
         const double nu = freq[c];
-        int p = 0;
-        float s = 0.f;
         if (mode == 3 && P->dr3 > 0.0) {
             const double r3 = trk.a3 * nu;
             p = slab_index(r3, P);
@@ -263,37 +276,75 @@ __global__ __launch_bounds__(256) void k_degrid(
         }
         const double X = 0.5 * M + trk.ax * nu, Y = 0.5 * M + trk.ay * nu;
         const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
-        const int ix = (int)fx0, iy = (int)fy0;
-        const float ox = (float)(X - fx0), oy = (float)(Y - fy0);
-        float wx[8], wy[8];
+        pk = ((int)fx0 & (M - 1)) | (((int)fy0 & (M - 1)) << 13);   // footprint start, M <= 8192
+        ox = (float)(X - fx0);
+        oy = (float)(Y - fy0);
+    }
+    uint64_t pending = __ballot(act);
+    if (pending) {
+        {
+            float wv[16];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            wx[d] = es_kernel(((float)d - ox) * 0.25f);
-            wy[d] = es_kernel(((float)d - oy) * 0.25f);
-        }
-        const int K = P->K;
-        float t = 1.f, tm1 = s;   // T_0, T_{-1} = T_1
-        for (int k = 0; k < K; ++k) {
-            const float2* pl = gg + (size_t)(p * K + k) * M * M;
-            float ar = 0.f, ai = 0.f;
-#pragma unroll
-            for (int dy = 0; dy < 8; ++dy) {
-                const float2* row = pl + (size_t)((iy + dy) & (M - 1)) * M;
-                float rr = 0.f, ri = 0.f;
-#pragma unroll
-                for (int dx = 0; dx < 8; ++dx) {
-                    const float2 gv = row[(ix + dx) & (M - 1)];
-                    rr += wx[dx] * gv.x;
-                    ri += wx[dx] * gv.y;
-                }
-                ar += wy[dy] * rr;
-                ai += wy[dy] * ri;
+            for (int d = 0; d < 8; ++d) {
+                wv[d] = es_kernel(((float)d - ox) * 0.25f);
+                wv[8 + d] = es_kernel(((float)d - oy) * 0.25f);
             }
-            gxr += t * ar;
-            gxi += t * ai;
-            const float tn = 2.f * s * t - tm1;
-            tm1 = t;
-            t = tn;
+            float4* d4 = reinterpret_cast<float4*>(sw + lane * 16);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) d4[v] = make_float4(wv[4 * v], wv[4 * v + 1], wv[4 * v + 2], wv[4 * v + 3]);
+            float tv[KACC];
+            float t = 1.f, tm1 = s;   // T_0, T_{-1} = T_1
+#pragma unroll
+            for (int k = 0; k < KACC; ++k) {
+                tv[k] = t;
+                const float tn = 2.f * s * t - tm1;
+                tm1 = t;
+                t = tn;
+            }
+            float4* t4 = reinterpret_cast<float4*>(sT + lane * KACC);
+#pragma unroll
+            for (int v = 0; v < KACC / 4; ++v) t4[v] = make_float4(tv[4 * v], tv[4 * v + 1], tv[4 * v + 2], tv[4 * v + 3]);
+        }
+        __builtin_amdgcn_wave_barrier();   // staging writes precede the walk's reads
+        const int K = P->K;
+        const size_t MM = (size_t)M * M;
+        const int ax = lane & 7, ay = lane >> 3;
+        int cur_pk = -1, cur_p = -1;
+        float gre[KACC], gim[KACC];
+#pragma unroll
+        for (int k = 0; k < KACC; ++k) { gre[k] = 0.f; gim[k] = 0.f; }
+        while (pending) {
+            const int q = __ffsll((unsigned long long)pending) - 1;
+            pending &= pending - 1;
+            const int qpk = __builtin_amdgcn_readlane(pk, q), qp = __builtin_amdgcn_readlane(p, q);
+            const int qx = qpk & 8191, qy = qpk >> 13;
+            const int dx = (ax - qx) & 7, dy = (ay - qy) & 7;
+            if (qpk != cur_pk || qp != cur_p) {     // wave-uniform: reload this lane's cell
+                const int cx = (qx + dx) & (M - 1), cy = (qy + dy) & (M - 1);
+                const float2* src = gg + (size_t)qp * K * MM + (size_t)cy * M + cx;
+#pragma unroll
+                for (int k = 0; k < KACC; ++k) {
+                    const float2 v = k < K ? src[k * MM] : make_float2(0.f, 0.f);
+                    gre[k] = v.x;
+                    gim[k] = v.y;
+                }
+                cur_pk = qpk;
+                cur_p = qp;
+            }
+            const float wq = sw[q * 16 + dx] * sw[q * 16 + 8 + dy];
+            const float4* tq = reinterpret_cast<const float4*>(sT + q * KACC);
+            float hr = 0.f, hi = 0.f;
+#pragma unroll
+            for (int v = 0; v < KACC / 4; ++v) {
+                const float4 t4 = tq[v];
+                hr += t4.x * gre[4 * v] + t4.y * gre[4 * v + 1] + t4.z * gre[4 * v + 2] + t4.w * gre[4 * v + 3];
+                hi += t4.x * gim[4 * v] + t4.y * gim[4 * v + 1] + t4.z * gim[4 * v + 2] + t4.w * gim[4 * v + 3];
+            }
+            const float Hr = wave_total(wq * hr), Hi = wave_total(wq * hi);
+            if (lane == q) {
+                gxr = Hr;
+                gxi = Hi;
+            }
         }
     }
     // visibility gradients: conj(g_row) W_k (1 - F_k) grad x on the selected correlations
@@ -380,11 +431,22 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
     }
     const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;
     const int n_items = s.n_row * n_chunks;
-    if (n_items > 0)
-        hipLaunchKernelGGL(k_degrid, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw, (const float2*)s.vis,
-                           s.weight, s.flag, s.freq, s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan,
-                           p.n_corr, p.corr_mask, p.mode, c->plan, M, cell, n_items, c->grid, grad_vis,
-                           grad_gains ? c->item_gain : nullptr);
+#define TOI_DEGRID(KA)                                                                                       \
+    hipLaunchKernelGGL((k_degrid<KA>), dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw,                \
+                       (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2, (const float2*)s.gains,   \
+                       p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, cell, n_items, c->grid,     \
+                       grad_vis, grad_gains ? c->item_gain : nullptr)
+    if (n_items > 0) {
+        if (c->kmax <= 4)
+            TOI_DEGRID(4);
+        else if (c->kmax <= 8)
+            TOI_DEGRID(8);
+        else if (c->kmax <= 16)
+            TOI_DEGRID(16);
+        else
+            TOI_DEGRID(32);
+    }
+#undef TOI_DEGRID
     if (grad_gains)
         hipLaunchKernelGGL(k_gain_grad, dim3(p.n_ant), dim3(256), 0, c->stream, c->item_gain, n_items, n_chunks,
                            s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, grad_gains);

@@ -13,6 +13,22 @@ __device__ inline T wave_sum(T v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+// Sum over a 64-lane wavefront with DPP row shifts and row broadcasts (fixed
+// order); the total is returned to every lane (from lane 63).
+template <int CTRL, int ROWS>
+__device__ inline float dpp_add(float x) {
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf, false));
+}
+__device__ inline float wave_total(float v) {
+    v = dpp_add<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);   // row_shr:8   (lane 15 of each row: the row's sum)
+    v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 (rows 1, 3)
+    v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 (rows 2, 3): lane 63 holds the total
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 template <typename T>
 __device__ inline T wave_max(T v) {
 #pragma unroll

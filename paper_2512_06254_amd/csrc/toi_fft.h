@@ -75,19 +75,17 @@ __host__ __device__ constexpr int fft_radix_at(int M, int E, int NS) {
     return NS == 1 ? fft_first_radix(M, E) : E;
 }
 
-// e^{+2 pi i n / M} from a half-period table tw[n] (n < M/2), which the
-// kernels keep in LDS: e^{i pi} = -1 supplies the second half.
+// e^{+2 pi i n / M} from the full-period table tw[n] (n < M), which the
+// kernels keep in LDS.
 template <int M>
 __device__ inline float2 twiddle(const float2* tw, int n) {
-    n &= M - 1;
-    const float2 w = tw[n & (M / 2 - 1)];
-    return n < M / 2 ? w : make_float2(-w.x, -w.y);
+    return tw[n & (M - 1)];
 }
 
-// Copy the half-period twiddle table into LDS (all threads; ends with a barrier).
+// Copy the twiddle table into LDS (all threads; ends with a barrier).
 template <int M>
 __device__ inline void load_twiddles(float2* tw_s, const float2* __restrict__ tw) {
-    for (int i = threadIdx.x; i < M / 2; i += blockDim.x) tw_s[i] = tw[i];
+    for (int i = threadIdx.x; i < M; i += blockDim.x) tw_s[i] = tw[i];
     __syncthreads();
 }
 

@@ -6,7 +6,8 @@
 //     lie on a radial track (b = uvw nu / c), so an item's 8 x 8 footprints
 //     cover a small box; k_items computes the box and the slabs it touches and
 //     counts the item into every (plane group, 32 x 32 tile) bin it overlaps.
-//  2. k_bin_scan turns the counts into list offsets and occupancy bit masks;
+//  2. k_scan_local / k_scan_top / k_scan_apply turn the counts into list
+//     offsets, a heaviest-first launch order and occupancy bit masks;
 //     k_bin_fill writes the item lists.
 //  3. k_grid_tiles: one workgroup per (group, tile) accumulates the tile's
 //     planes in LDS and writes it to HBM once.  Inside a workgroup each
@@ -27,10 +28,6 @@
 #include "toi_internal.h"
 
 namespace toi {
-
-__global__ __launch_bounds__(256) void k_fill_zero_i32(int32_t* __restrict__ p, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-}
 
 // ---------------------------------------------------------------- 1. items
 __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, const float* __restrict__ weight,
@@ -53,20 +50,21 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
         return;
     }
     const Track tr = row_track(uvw, r, P, M, cell_rad);
-    double xlo = 1e300, xhi = -1e300, ylo = 1e300, yhi = -1e300, rlo = 1e300, rhi = -1e300;
-    if (c < n_chan && sample_kept(weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask)) {
-        const double nu = freq[c];
-        xlo = xhi = 0.5 * M + tr.ax * nu;
-        ylo = yhi = 0.5 * M + tr.ay * nu;
-        rlo = rhi = tr.a3 * nu;
-    }
-    xlo = wave_min(xlo); xhi = wave_max(xhi);
-    ylo = wave_min(ylo); yhi = wave_max(yhi);
-    rlo = wave_min(rlo); rhi = wave_max(rhi);
-    if (xlo > xhi) {   // no kept sample
+    // X, Y and r3 are linear in nu along the row: their extremes over the kept
+    // channels sit at the extreme kept frequencies
+    double nlo = 1e300, nhi = -1e300;
+    if (c < n_chan && sample_kept(weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask)) nlo = nhi = freq[c];
+    nlo = wave_min(nlo);
+    nhi = wave_max(nhi);
+    if (nlo > nhi) {   // no kept sample
         if (lane == 0) items[item] = box;
         return;
     }
+    const double xa = 0.5 * M + tr.ax * nlo, xb = 0.5 * M + tr.ax * nhi;
+    const double ya = 0.5 * M + tr.ay * nlo, yb = 0.5 * M + tr.ay * nhi;
+    const double ra = tr.a3 * nlo, rb = tr.a3 * nhi;
+    const double xlo = fmin(xa, xb), xhi = fmax(xa, xb), ylo = fmin(ya, yb), yhi = fmax(ya, yb);
+    const double rlo = fmin(ra, rb), rhi = fmax(ra, rb);
     // footprint cells [ceil(X - 4), ceil(X - 4) + 7] -> tiles (floor division)
     box.tx0 = ((int)ceil(xlo - 4.0)) >> 5;
     box.tx1 = ((int)ceil(xhi - 4.0) + 7) >> 5;
@@ -88,76 +86,149 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
 }
 
 // ---------------------------------------------------------------- 2. scan
-// One workgroup of 1024 threads: exclusive scan of the counts, bin cursors and
-// occupancy masks (tile_bits[g][ty][tx/32], row_bits[g][ty/32]).
-__global__ __launch_bounds__(1024) void k_bin_scan(const int32_t* __restrict__ count, int n_bins, int NT,
-                                                   int bin_cap, DevPlan* __restrict__ P, int32_t* __restrict__ off,
-                                                   int32_t* __restrict__ cursor, uint32_t* __restrict__ tile_bits,
-                                                   uint32_t* __restrict__ row_bits, int32_t* __restrict__ order,
-                                                   int32_t* __restrict__ n_active) {
-    __shared__ int32_t part[1024];
+// Three passes over the bin counts, kScanBlock bins per workgroup:
+//  local: exclusive scan inside the workgroup, its total, and the global
+//         histogram of non-empty bins by floor(log2(count));
+//  top:   one workgroup scans the workgroup totals, writes the list length
+//         (overflow check) and turns the histogram into bucket offsets,
+//         heaviest bucket first;
+//  apply: adds the workgroup offsets (bin offsets and cursors), lists the
+//         non-empty bins in launch order (heaviest bucket first; order inside
+//         a bucket is arbitrary) and writes the occupancy masks
+//         tile_bits[g][ty][tx/32] and row_bits[g][ty/32].
+// aux: [0, 32) bucket sizes, [32, 64) bucket cursors, [64, 64 + blocks) totals.
+constexpr int kScanPer = kScanBlock / 1024;
+
+__global__ __launch_bounds__(256) void k_scan_clear(int32_t* __restrict__ count, int n_bins,
+                                                    int32_t* __restrict__ aux, uint32_t* __restrict__ row_bits,
+                                                    int n_row_words) {
+    const int stride = gridDim.x * blockDim.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int i = t; i < n_bins; i += stride) count[i] = 0;
+    if (t < 64) aux[t] = 0;
+    for (int i = t; i < n_row_words; i += stride) row_bits[i] = 0;
+}
+
+__device__ inline int block_exclusive_scan(int v, int& total) {
+    __shared__ int32_t wsum[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    __syncthreads();
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__ count, int n_bins,
+                                                     int32_t* __restrict__ off, int32_t* __restrict__ aux) {
     __shared__ int32_t hist[32];
-    const int per = (n_bins + 1023) / 1024;
-    const int b0 = min(n_bins, (int)threadIdx.x * per), b1 = min(n_bins, b0 + per);
-    int s = 0;
-    for (int i = b0; i < b1; ++i) s += count[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {   // inclusive Hillis-Steele scan of the partial sums
-        const int v = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int run = part[threadIdx.x] - s;
-    for (int i = b0; i < b1; ++i) {
-        off[i] = run;
-        cursor[i] = run;
-        run += count[i];
-    }
-    if (threadIdx.x == 1023) {
-        off[n_bins] = part[1023];
-        if (part[1023] > bin_cap) atomicOr(&P->status, (uint32_t)TOI_STATUS_OVERFLOW);
-    }
-    // launch order of the non-empty bins: heaviest first, bucketed by floor(log2(count))
     if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    int c[kScanPer], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        c[j] = base + j < n_bins ? count[base + j] : 0;
+        sum += c[j];
+    }
+    int total;
+    int run = block_exclusive_scan(sum, total);   // its barriers also order the hist clear
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        if (base + j < n_bins) off[base + j] = run;
+        run += c[j];
+        if (c[j] > 0) atomicAdd(&hist[31 - __clz(c[j])], 1);
+    }
     __syncthreads();
-    for (int i = b0; i < b1; ++i)
-        if (count[i] > 0) atomicAdd(&hist[31 - __clz(count[i])], 1);
-    __syncthreads();
+    if (threadIdx.x < 32 && hist[threadIdx.x]) atomicAdd(&aux[threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x == 0) aux[64 + blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int n_blocks, int n_bins, int bin_cap, DevPlan* __restrict__ P,
+                                                   int32_t* __restrict__ aux, int32_t* __restrict__ off,
+                                                   int32_t* __restrict__ n_active) {
+    int carry = 0;
+    for (int b0 = 0; b0 < n_blocks; b0 += 1024) {
+        const int b = b0 + (int)threadIdx.x;
+        const int v = b < n_blocks ? aux[64 + b] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, total);
+        if (b < n_blocks) aux[64 + b] = carry + ex;
+        carry += total;
+    }
     if (threadIdx.x == 0) {
+        off[n_bins] = carry;
+        if (carry > bin_cap) atomicOr(&P->status, (uint32_t)TOI_STATUS_OVERFLOW);
         int acc = 0;
-        for (int b = 31; b >= 0; --b) {
-            const int h = hist[b];
-            hist[b] = acc;
-            acc += h;
+        for (int k = 31; k >= 0; --k) {
+            aux[32 + k] = acc;
+            acc += aux[k];
         }
         *n_active = acc;
     }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__ count, int n_bins, int NT,
+                                                     int32_t* __restrict__ off, int32_t* __restrict__ cursor,
+                                                     int32_t* __restrict__ order, int32_t* __restrict__ aux,
+                                                     uint32_t* __restrict__ tile_bits,
+                                                     uint32_t* __restrict__ row_bits) {
+    __shared__ int32_t hist[32], start[32];
+    if (threadIdx.x < 32) hist[threadIdx.x] = 0;
     __syncthreads();
-    for (int i = b0; i < b1; ++i)
-        if (count[i] > 0) order[atomicAdd(&hist[31 - __clz(count[i])], 1)] = i;
-    // occupancy masks
-    const int words = (NT + 31) / 32;
-    const int n_groups = n_bins / (NT * NT);
-    for (int w = threadIdx.x; w < n_groups * NT * words; w += blockDim.x) {
-        const int g = w / (NT * words), ty = (w / words) % NT, wd = w % words;
-        uint32_t bits = 0;
-        for (int b = 0; b < 32 && wd * 32 + b < NT; ++b)
-            if (count[(size_t)g * NT * NT + ty * NT + wd * 32 + b] > 0) bits |= 1u << b;
-        tile_bits[w] = bits;
+    const int add = aux[64 + blockIdx.x];
+    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    int c[kScanPer];
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        c[j] = 0;
+        if (base + j < n_bins) {
+            c[j] = count[base + j];
+            const int o = off[base + j] + add;
+            off[base + j] = o;
+            cursor[base + j] = o;
+            if (c[j] > 0) atomicAdd(&hist[31 - __clz(c[j])], 1);
+        }
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < n_groups * words; w += blockDim.x) {
-        const int g = w / words, wd = w % words;
-        uint32_t bits = 0;
-        for (int b = 0; b < 32 && wd * 32 + b < NT; ++b) {
-            const int ty = wd * 32 + b;
-            uint32_t any = 0;
-            for (int x = 0; x < words; ++x) any |= tile_bits[((size_t)g * NT + ty) * words + x];
-            if (any) bits |= 1u << b;
+    if (threadIdx.x < 32) {
+        const int h = hist[threadIdx.x];
+        start[threadIdx.x] = h ? atomicAdd(&aux[32 + threadIdx.x], h) : 0;
+        hist[threadIdx.x] = 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j)
+        if (c[j] > 0) {
+            const int k = 31 - __clz(c[j]);
+            order[start[k] + atomicAdd(&hist[k], 1)] = base + j;
         }
-        row_bits[w] = bits;
+    // occupancy words of the tile rows that start in this workgroup's range
+    const int words = (NT + 31) / 32;
+    const int row0 = (blockIdx.x * kScanBlock + NT - 1) / NT;
+    const int row1 = min(n_bins, (blockIdx.x + 1) * kScanBlock + NT - 1) / NT;   // rows [row0, row1)
+    for (int w = row0 * words + (int)threadIdx.x; w < row1 * words; w += blockDim.x) {
+        const int row = w / words, wd = w % words;
+        const int32_t* cr = count + (size_t)row * NT + wd * 32;
+        const int nb = min(32, NT - wd * 32);
+        uint32_t bits = 0;
+        for (int i = 0; i < nb; ++i)
+            if (cr[i] > 0) bits |= 1u << i;
+        tile_bits[w] = bits;
+        if (bits) {
+            const int g = row / NT, ty = row % NT;
+            atomicOr(&row_bits[g * words + (ty >> 5)], 1u << (ty & 31));
+        }
     }
 }
 
@@ -182,18 +253,80 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
 }
 
 // ---------------------------------------------------------------- 3. tiles
+// Shared by both tile kernels.  Lane l prepares channel c0 + l of an item for
+// tile (tx, ty): its footprint start (ix, iy) (first of the 8 x 8 cells, in
+// [0, M) after wrapping), slab sp, Chebyshev argument ss, value g x and the
+// offsets (ox, oy) of the sample from the start, in (3, 4].  act: the sample
+// is kept, its slab is in [s0, s1) and its footprint overlaps the tile.
+struct Prep {
+    int ix, iy, sp;
+    float ss, vr, vi, ox, oy;
+    bool act;
+};
+__device__ inline Prep prepare_sample(const double* __restrict__ uvw, const float2* __restrict__ vis,
+                                      const float* __restrict__ weight, const uint8_t* __restrict__ flag,
+                                      const double* __restrict__ freq, int n_chan, int n_corr, uint32_t mask,
+                                      const DevPlan* __restrict__ P, int M, bool cheb, const Track& trk, float2 gr,
+                                      int r, int c, int c1, int tx, int ty, int s0, int s1) {
+    Prep q;
+    q.ix = 0; q.iy = 0; q.sp = 0;
+    q.ss = 0.f; q.vr = 0.f; q.vi = 0.f; q.ox = 4.f; q.oy = 4.f;
+    q.act = false;
+    if (c >= c1) return q;
+    float xr, xi;
+    const float w = sample_value(vis, weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask, xr, xi);
+    if (!(w > 0.f)) return q;
+    const double nu = freq[c];   // FP64 coordinates once per sample
+    if (cheb) {
+        const double r3 = trk.a3 * nu;
+        q.sp = slab_index(r3, P);
+        q.ss = (float)((r3 - (P->r3min + (2 * q.sp + 1) * P->dr3)) / P->dr3);
+    }
+    const double hM = 0.5 * M;
+    const double X = hM + trk.ax * nu, Y = hM + trk.ay * nu;
+    const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
+    const int ix = (int)fx0, iy = (int)fy0;
+    q.ox = (float)(X - fx0);
+    q.oy = (float)(Y - fy0);
+    const int ddx = (ix - tx * kTile) & (M - 1), ddy = (iy - ty * kTile) & (M - 1);
+    q.act = (q.sp >= s0 && q.sp < s1) && (ddx < kTile || ddx >= M - 7) && (ddy < kTile || ddy >= M - 7);
+    q.ix = ix & (M - 1);
+    q.iy = iy & (M - 1);
+    q.vr = xr * gr.x - xi * gr.y;
+    q.vi = xr * gr.y + xi * gr.x;
+    return q;
+}
+
+// The eight x and eight y kernel weights of a footprint with offsets (ox, oy).
+__device__ inline void footprint_weights(float ox, float oy, float* wv) {
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        wv[d] = es_kernel(((float)d - ox) * 0.25f);
+        wv[8 + d] = es_kernel(((float)d - oy) * 0.25f);
+    }
+}
+
+__device__ inline void store16(float* dst, const float* v) {
+    float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d4[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+}
+
+// ------------------------------------------------- 3a. tiles, vector ALU
 // LDS tile layout: planar real and imaginary parts, [plane][ly][swizzled lx],
 // the column rotated by 8 (ly / 2 mod 4) so that the 64 cells of one 8 x 8
 // footprint fall in distinct banks when they are added together.
 __device__ inline int tile_index(int ly, int lx) { return ly * kTile + ((lx + 8 * ((ly >> 1) & 3)) & (kTile - 1)); }
 
-// Variants (chosen by the autotuner): CELLS footprint cells per lane.  With
-// CELLS = 1 all 64 lanes serve one sample, lane (i, j) owning x = i (mod 8),
-// y = j (mod 8); with CELLS = 2 the two half-waves take alternate samples and
-// lane (i, j) of a half owns x = i (mod 4) -- cells dx and dx + 4 -- and
-// y = j (mod 8).  Each lane keeps its cells' plane values in registers until
-// the track moves them (Romein, ICS 2012), then adds them to LDS.
-template <int KACC, int CELLS>
+// Each wavefront walks one item at a time.  Lane l first prepares channel
+// c0 + l and writes the eight x and eight y kernel weights of its footprint
+// to the wave's LDS staging area.  The walk then takes the item's samples
+// that touch this tile and plane group in channel order: lane (i, j) owns the
+// footprint cell with x = i, y = j (mod 8) and reads its weight wx[dx] wy[dy]
+// from the staging area; the plane values of that cell (Chebyshev recurrence
+// per sample) stay in registers until the track moves the cell (Romein, ICS
+// 2012), then they are added to LDS.
+template <int KACC>
 __global__ __launch_bounds__(1024) void k_grid_tiles(
     const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
     const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
@@ -201,10 +334,8 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
     uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
     const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
     const int32_t* __restrict__ order, const int32_t* __restrict__ n_active, float2* __restrict__ grid) {
-    extern __shared__ float lds[];                      // re[gp][kTile*kTile], then im[gp][kTile*kTile]
+    extern __shared__ float lds[];   // re[gp][TT], im[gp][TT], then per wave: w[64][16]
     constexpr int TT = kTile * kTile;
-    constexpr int XM = 8 / CELLS;                       // x residue modulus of a lane
-    constexpr int SUBL = 64 / CELLS;                    // lanes per sample
     const int tiles = NT * NT;
     // Non-empty bins in decreasing order of work, dealt round-robin over the
     // XCDs by the dispatcher (tiles with samples cluster around the uv centre,
@@ -228,11 +359,9 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
 
     const int tx = tile % NT, ty = tile / NT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    const int sub = lane / SUBL, sl = lane % SUBL;
-    const int li = sl % XM, lj = sl / XM;
-    const double hM = 0.5 * M;
+    const int li = lane & 7, lj = lane >> 3;
+    float* sw = lds + 2 * P->gp * TT + wave * 64 * 16;   // [64][16]: wx[0..7], wy[0..7]
     const bool cheb = (mode == 3) && (P->dr3 > 0.0);
-    const double dr3 = P->dr3, r3min = P->r3min;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
 
     for (int it = b0 + wave; it < b1; it += n_waves) {
@@ -241,138 +370,98 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
         const int c0 = (item % n_chunks) * kItemChans, c1 = min(n_chan, c0 + kItemChans);
         const Track trk = row_track(uvw, r, P, M, cell_rad);
         const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
-        // lane-parallel prefetch: lane l prepares channel c0 + l (FP64 coordinates once per sample)
-        int ix = 0, iy = 0, sp = 0;
-        float ox = 0.f, oy = 0.f, vr0 = 0.f, vi0 = 0.f, ss = 0.f;
-        bool act = false;
+        const Prep pr = prepare_sample(uvw, vis, weight, flag, freq, n_chan, n_corr, mask, P, M, cheb, trk, gr, r,
+                                       c0 + lane, c1, tx, ty, s0, s1);
+        uint64_t pending = __ballot(pr.act);
+        if (pending == 0) continue;
         {
-            const int c = c0 + lane;
-            if (c < c1) {
-                float xr, xi;
-                const float w =
-                    sample_value(vis, weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask, xr, xi);
-                if (w > 0.f) {
-                    const double nu = freq[c];
-                    if (cheb) {
-                        const double r3 = trk.a3 * nu;
-                        sp = slab_index(r3, P);
-                        ss = (float)((r3 - (r3min + (2 * sp + 1) * dr3)) / dr3);
-                    }
-                    const double X = hM + trk.ax * nu, Y = hM + trk.ay * nu;
-                    const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
-                    ix = (int)fx0;
-                    iy = (int)fy0;
-                    ox = (float)(X - fx0);                 // in (3, 4]
-                    oy = (float)(Y - fy0);
-                    const int ddx = (ix - tx * kTile) & (M - 1), ddy = (iy - ty * kTile) & (M - 1);
-                    act = (sp >= s0 && sp < s1) && (ddx < kTile || ddx >= M - 7) && (ddy < kTile || ddy >= M - 7);
-                    vr0 = xr * gr.x - xi * gr.y;
-                    vi0 = xr * gr.y + xi * gr.x;
-                }
-            }
+            float wv[16];
+            footprint_weights(pr.ox, pr.oy, wv);
+            store16(sw + lane * 16, wv);
         }
-        uint64_t pending = __ballot(act);
+        __builtin_amdgcn_wave_barrier();   // staging writes precede the walk's reads (LDS is in order per wave)
         int cur_x = 0, cur_y = 0, cur_p = -1;
-        bool in[CELLS];
-        float ar[CELLS][KACC], ai[CELLS][KACC];
+        bool in = false;
+        float ar[KACC], ai[KACC];
 #pragma unroll
-        for (int m = 0; m < CELLS; ++m) {
-            in[m] = false;
-#pragma unroll
-            for (int k = 0; k < KACC; ++k) { ar[m][k] = 0.f; ai[m][k] = 0.f; }
-        }
+        for (int k = 0; k < KACC; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
 
         auto flush = [&]() {
-            const int ly = cur_y & (kTile - 1);
-            const int base = (cur_p - s0) * nk * TT;
+            if (!in) return;
+            const int ci = (cur_p - s0) * nk * TT + tile_index(cur_y & (kTile - 1), cur_x & (kTile - 1));
+            if (nk == KACC) {
 #pragma unroll
-            for (int m = 0; m < CELLS; ++m) {
-                if (!in[m]) continue;
-                const int ci = base + tile_index(ly, (cur_x + m * XM) & (kTile - 1));
+                for (int k = 0; k < KACC; ++k) {
+                    atomicAdd(lre + ci + k * TT, ar[k]);
+                    atomicAdd(lim + ci + k * TT, ai[k]);
+                }
+            } else {
 #pragma unroll
                 for (int k = 0; k < KACC; ++k) {
                     if (k < nk) {
-                        atomicAdd(lre + ci + k * TT, ar[m][k]);
-                        atomicAdd(lim + ci + k * TT, ai[m][k]);
+                        atomicAdd(lre + ci + k * TT, ar[k]);
+                        atomicAdd(lim + ci + k * TT, ai[k]);
                     }
                 }
             }
         };
-
-        while (pending) {                               // wave-uniform walk, CELLS samples per step
-            int qs[CELLS];
-            bool have[CELLS];
-#pragma unroll
-            for (int m = 0; m < CELLS; ++m) {
-                have[m] = pending != 0;
-                qs[m] = have[m] ? __ffsll((unsigned long long)pending) - 1 : 0;
-                if (have[m]) pending &= pending - 1;
-            }
-            bool mine = have[0];
-            int qx = __builtin_amdgcn_readlane(ix, qs[0]), qy = __builtin_amdgcn_readlane(iy, qs[0]);
-            int p = __builtin_amdgcn_readlane(sp, qs[0]);
-            int bx = __builtin_amdgcn_readlane(__float_as_int(ox), qs[0]);
-            int by = __builtin_amdgcn_readlane(__float_as_int(oy), qs[0]);
-            int br = __builtin_amdgcn_readlane(__float_as_int(vr0), qs[0]);
-            int bi = __builtin_amdgcn_readlane(__float_as_int(vi0), qs[0]);
-            int bs = __builtin_amdgcn_readlane(__float_as_int(ss), qs[0]);
-#pragma unroll
-            for (int m = 1; m < CELLS; ++m) {
-                if (sub == m) {
-                    mine = have[m];
-                    qx = __builtin_amdgcn_readlane(ix, qs[m]);
-                    qy = __builtin_amdgcn_readlane(iy, qs[m]);
-                    p = __builtin_amdgcn_readlane(sp, qs[m]);
-                    bx = __builtin_amdgcn_readlane(__float_as_int(ox), qs[m]);
-                    by = __builtin_amdgcn_readlane(__float_as_int(oy), qs[m]);
-                    br = __builtin_amdgcn_readlane(__float_as_int(vr0), qs[m]);
-                    bi = __builtin_amdgcn_readlane(__float_as_int(vi0), qs[m]);
-                    bs = __builtin_amdgcn_readlane(__float_as_int(ss), qs[m]);
-                }
-            }
-            if (!mine) continue;
-            const float qox = __int_as_float(bx), qoy = __int_as_float(by);
-            const float qvr = __int_as_float(br), qvi = __int_as_float(bi), s = __int_as_float(bs);
-            const int dx = (li - qx) & (XM - 1), dy = (lj - qy) & 7;
-            const int cx = qx + dx, cy = qy + dy;
-            if (cx != cur_x || cy != cur_y || p != cur_p) {
+        // Software-pipelined walk (wave-uniform, one sample per step): the
+        // staged weights of the next sample are read from LDS while the
+        // current sample's planes are accumulated.
+        struct Smp {
+            int cx, cy, p;
+            float wx, wy, vr, vi, s;
+        };
+        auto fetch = [&](Smp& m) {
+            const int q = __ffsll((unsigned long long)pending) - 1;
+            pending &= pending - 1;
+            const int qx = __builtin_amdgcn_readlane(pr.ix, q), qy = __builtin_amdgcn_readlane(pr.iy, q);
+            m.p = __builtin_amdgcn_readlane(pr.sp, q);
+            m.vr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.vr), q));
+            m.vi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.vi), q));
+            m.s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.ss), q));
+            const int dx = (li - qx) & 7, dy = (lj - qy) & 7;
+            m.cx = qx + dx;
+            m.cy = qy + dy;
+            m.wx = sw[q * 16 + dx];
+            m.wy = sw[q * 16 + 8 + dy];
+        };
+        auto process = [&](const Smp& m) {
+            if (m.cx != cur_x || m.cy != cur_y || m.p != cur_p) {
                 flush();
-                cur_x = cx; cur_y = cy; cur_p = p;
-                const bool yin = ((cy & (M - 1)) >> 5) == ty;
+                cur_x = m.cx; cur_y = m.cy; cur_p = m.p;
+                in = (((m.cy & (M - 1)) >> 5) == ty) && (((m.cx & (M - 1)) >> 5) == tx);
 #pragma unroll
-                for (int m = 0; m < CELLS; ++m) {
-                    in[m] = yin && ((((cx + m * XM) & (M - 1)) >> 5) == tx);
-#pragma unroll
-                    for (int k = 0; k < KACC; ++k) { ar[m][k] = 0.f; ai[m][k] = 0.f; }
-                }
+                for (int k = 0; k < KACC; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
             }
-            bool any = false;
-#pragma unroll
-            for (int m = 0; m < CELLS; ++m) any |= in[m];
-            if (!any) continue;
-            const float wy = es_kernel(((float)dy - qoy) * 0.25f);
-            float vr[CELLS], vi[CELLS];
-#pragma unroll
-            for (int m = 0; m < CELLS; ++m) {
-                const float w = es_kernel(((float)(dx + m * XM) - qox) * 0.25f) * wy;
-                vr[m] = w * qvr;
-                vi[m] = w * qvi;
-            }
+            if (!in) return;
+            const float w = m.wx * m.wy;
+            const float vr = w * m.vr, vi = w * m.vi;
             float t, tm1;
-            cheb_start(s, k0, t, tm1);                  // t = T_{k0}(s), tm1 = T_{k0 - 1}(s)
+            cheb_start(m.s, k0, t, tm1);                // t = T_{k0}(s), tm1 = T_{k0 - 1}(s)
 #pragma unroll
             for (int k = 0; k < KACC; ++k) {
-#pragma unroll
-                for (int m = 0; m < CELLS; ++m) {
-                    ar[m][k] += t * vr[m];
-                    ai[m][k] += t * vi[m];
-                }
-                const float tn = 2.f * s * t - tm1;
+                ar[k] += t * vr;
+                ai[k] += t * vi;
+                const float tn = 2.f * m.s * t - tm1;
                 tm1 = t;
                 t = tn;
             }
+        };
+        Smp sa, sb;
+        fetch(sa);                                      // pending is non-zero here
+        while (true) {
+            const bool m1 = pending != 0;
+            if (m1) fetch(sb);
+            process(sa);
+            if (!m1) break;
+            const bool m2 = pending != 0;
+            if (m2) fetch(sa);
+            process(sb);
+            if (!m2) break;
         }
         flush();
+        __builtin_amdgcn_wave_barrier();   // the walk's reads precede the next item's staging writes
     }
     __syncthreads();
     // write the tile's planes (only the planes of this group)
@@ -385,6 +474,173 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
     }
 }
 
+// ------------------------------------------------- 3b. tiles, matrix cores
+// The contribution of one sample to its footprint is an outer product: the
+// 64 footprint weights w(cell) times the 2 KACC values T_k(s) Re(g x) and
+// T_k(s) Im(g x).  One v_mfma_f32_32x32x1f32 (KACC = 16: two 32 x 32 blocks,
+// rows = footprint cells, columns = (order, re/im)) or v_mfma_f32_16x16x1f32
+// (KACC = 8: four 16 x 16 blocks) adds it to accumulators that stay in
+// registers while the footprint start of the walked samples does not move;
+// when it moves, they are added to the LDS tile.  Lane l supplies the weight
+// of footprint cell (l mod 8, l / 8) (A operand) and the value of column
+// l mod 2KACC (B operand); accumulator register r of lane l holds cell
+// (4 h + r mod 4, r / 4) (KACC = 16, h = l / 32) or (4 h + r mod 4,
+// 2 (r / 4) + l / 32) (KACC = 8, h = (l / 16) mod 2) of column l mod 2KACC
+// (hardware output layout of these instructions).
+// LDS tile layout: [cell = ly * 32 + lx][slot], slot = 2 plane + re/im XOR
+// 2 (lx mod gp): a flush writes 32 consecutive words per half-wave and the
+// tile write-out reads 16 cells of one plane from distinct banks.
+// Items are staged in halves of 32 samples: per wave [32][16] weights and
+// [32][KACC] Chebyshev values.
+template <int KACC>
+__global__ __launch_bounds__(1024) void k_grid_tiles_mfma(
+    const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
+    const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
+    const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_chan, int n_corr,
+    uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
+    const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ n_active, float2* __restrict__ grid) {
+    static_assert(KACC == 8 || KACC == 16, "matrix-core gridder handles 8 or 16 orders per pass");
+    constexpr int NREG = KACC == 16 ? 32 : 16;
+    typedef float acc_t __attribute__((ext_vector_type(NREG)));
+    extern __shared__ float lds[];
+    constexpr int TT = kTile * kTile;
+    const int tiles = NT * NT;
+    if ((int)blockIdx.x >= *n_active) return;
+    const int bid = order[blockIdx.x];
+    const int g = bid / tiles, tile = bid % tiles;
+    if (P->status & kStatusFatal) return;
+    if (g >= P->ng) return;
+    const int b0 = bin_off[(size_t)g * tiles + tile];
+    const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
+    if (b1 <= b0) return;
+    int s0, s1, k0, k1;
+    group_range(g, P, s0, s1, k0, k1);
+    const int nk = k1 - k0;
+    const int n_planes = (s1 - s0) * nk;
+    const int gp = P->gp, SS = 2 * gp;
+    float* tl = lds;   // [TT][SS]
+    for (int i = threadIdx.x; i < TT * SS / 4; i += blockDim.x)
+        reinterpret_cast<float4*>(tl)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+
+    const int tx = tile % NT, ty = tile / NT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    float* sw = lds + TT * SS + wave * 32 * (16 + KACC);   // [32][16] weights
+    float* sT = sw + 32 * 16;                               // [32][KACC] T_{k0 + k}(s)
+    const bool cheb = (mode == 3) && (P->dr3 > 0.0);
+    const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
+    // operand roles of this lane
+    const int ax = lane & 7, ay = lane >> 3;                // A: footprint cell residue
+    const int col = lane & (2 * KACC - 1);                  // B / accumulator column
+    const int kcol = col & (KACC - 1), reim = col / KACC;
+    const int hx = KACC == 16 ? 4 * (lane >> 5) : 4 * ((lane >> 4) & 1);
+    const int hy = KACC == 16 ? 0 : (lane >> 5);
+    const acc_t zero = {};
+
+    for (int it = b0 + wave; it < b1; it += n_waves) {
+        const int item = list[it];
+        const int r = item / n_chunks;
+        const int c0 = (item % n_chunks) * kItemChans, c1 = min(n_chan, c0 + kItemChans);
+        const Track trk = row_track(uvw, r, P, M, cell_rad);
+        const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
+        const Prep pr = prepare_sample(uvw, vis, weight, flag, freq, n_chan, n_corr, mask, P, M, cheb, trk, gr, r,
+                                       c0 + lane, c1, tx, ty, s0, s1);
+        const uint64_t all = __ballot(pr.act);
+        if (all == 0) continue;
+        float wv[16], tv[KACC];
+        footprint_weights(pr.ox, pr.oy, wv);
+        {
+            float t, tm1;
+            cheb_start(pr.ss, k0, t, tm1);
+#pragma unroll
+            for (int k = 0; k < KACC; ++k) {
+                tv[k] = t;
+                const float tn = 2.f * pr.ss * t - tm1;
+                tm1 = t;
+                t = tn;
+            }
+        }
+        const int pk = pr.ix | (pr.iy << 13);                // footprint start, M <= 8192
+        int cur_pk = -1, cur_p = 0;
+        acc_t acc = zero;
+
+        // Add the accumulators to the LDS tile for footprint start cur_pk:
+        // register r holds cell (hx + r mod 4, ry(r)) of column col.  Cells
+        // outside the tile and unused columns add 0 at a valid address.
+        auto flush = [&]() {
+            const int qx = cur_pk & 8191, qy = cur_pk >> 13;
+            const bool colok = kcol < nk;
+            const int slot0 = colok ? 2 * ((cur_p - s0) * nk + kcol) + reim : reim;
+            int xo[4];
+            bool xin[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int cx = qx + ((hx + m - qx) & 7);
+                const int lx = cx & (kTile - 1);
+                xin[m] = colok && (((cx & (M - 1)) >> 5) == tx);
+                xo[m] = lx * SS + (slot0 ^ ((lx & (gp - 1)) << 1));
+            }
+#pragma unroll
+            for (int yy = 0; yy < NREG / 4; ++yy) {
+                const int ry = KACC == 16 ? yy : 2 * yy + hy;
+                const int cy = qy + ((ry - qy) & 7);
+                const bool yin = ((cy & (M - 1)) >> 5) == ty;
+                if (KACC == 16 && !yin) continue;        // wave-uniform row
+                float* row = tl + (cy & (kTile - 1)) * kTile * SS;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) atomicAdd(row + xo[m], (xin[m] && yin) ? acc[4 * yy + m] : 0.f);
+            }
+        };
+
+        for (int h = 0; h < 2; ++h) {
+            uint64_t pending = all & (h ? 0xFFFFFFFF00000000ull : 0xFFFFFFFFull);
+            if (pending == 0) continue;
+            if ((lane >> 5) == h) {
+                store16(sw + (lane & 31) * 16, wv);
+                if constexpr (KACC == 16) {
+                    store16(sT + (lane & 31) * 16, tv);
+                } else {
+                    float4* d4 = reinterpret_cast<float4*>(sT + (lane & 31) * 8);
+                    d4[0] = make_float4(tv[0], tv[1], tv[2], tv[3]);
+                    d4[1] = make_float4(tv[4], tv[5], tv[6], tv[7]);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();   // staging writes precede the walk's reads
+            while (pending) {
+                const int q = __ffsll((unsigned long long)pending) - 1;
+                pending &= pending - 1;
+                const int slot = q & 31;
+                const int qpk = __builtin_amdgcn_readlane(pk, q);
+                const int qp = __builtin_amdgcn_readlane(pr.sp, q);
+                const float qvr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.vr), q));
+                const float qvi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.vi), q));
+                const int qx = qpk & 8191, qy = qpk >> 13;
+                const float a = sw[slot * 16 + ((ax - qx) & 7)] * sw[slot * 16 + 8 + ((ay - qy) & 7)];
+                const float b = sT[slot * KACC + kcol] * (reim ? qvi : qvr);
+                if (qpk != cur_pk || qp != cur_p) {      // wave-uniform: the footprint start moved
+                    if (cur_pk >= 0) flush();
+                    cur_pk = qpk;
+                    cur_p = qp;
+                    acc = zero;
+                }
+                if constexpr (KACC == 16) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, acc, 0, 0, 0);
+                else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(a, b, acc, 0, 0, 0);
+            }
+            __builtin_amdgcn_wave_barrier();   // the walk's reads precede the next staging writes
+        }
+        flush();
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_planes * TT; i += blockDim.x) {
+        const int pl = i / TT, cell = i % TT;
+        const int ly = cell / kTile, lx = cell % kTile;
+        const int pg = (s0 + pl / nk) * P->K + k0 + pl % nk;   // global plane index
+        const float2 v = *reinterpret_cast<const float2*>(tl + cell * SS + ((2 * pl) ^ ((lx & (gp - 1)) << 1)));
+        grid[((size_t)pg * M + ty * kTile + ly) * M + tx * kTile + lx] = v;
+    }
+}
+
 hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
     const toi_params& p = c->p;
     const int M = c->M, NT = c->NT;
@@ -394,45 +650,47 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
     const int n_bins = c->NG_max * NT * NT;
     {
         StageTimer timer(c, TOI_STAGE_CLEAR);   // binning
-        hipLaunchKernelGGL(k_fill_zero_i32, dim3(256), dim3(256), 0, c->stream, c->bin_count, n_bins);
+        const int words = (NT + 31) / 32;
+        const int n_scan = (n_bins + kScanBlock - 1) / kScanBlock;
+        hipLaunchKernelGGL(k_scan_clear, dim3(256), dim3(256), 0, c->stream, c->bin_count, n_bins, c->bin_aux,
+                           c->row_bits, c->NG_max * words);
         if (n_items > 0)
             hipLaunchKernelGGL(k_items, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw, s.weight, s.flag,
                                s.freq, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, NT, cell, n_items,
                                c->items, c->bin_count);
-        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, c->bin_count, n_bins, NT, c->bin_cap,
-                           c->plan, c->bin_off, c->bin_cursor, c->tile_bits, c->row_bits, c->bin_order,
-                           c->scratch_i);
+        hipLaunchKernelGGL(k_scan_local, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, c->bin_off,
+                           c->bin_aux);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, n_scan, n_bins, c->bin_cap, c->plan,
+                           c->bin_aux, c->bin_off, c->scratch_i);
+        hipLaunchKernelGGL(k_scan_apply, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, NT,
+                           c->bin_off, c->bin_cursor, c->bin_order, c->bin_aux, c->tile_bits, c->row_bits);
         if (n_items > 0)
             hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, c->items, n_items, NT,
                                c->bin_cap, c->bin_cursor, c->bin_list);
     }
     if (n_items == 0) return hipGetLastError();
     StageTimer timer(c, TOI_STAGE_GRID);
-    const int gp = (c->tuning & kTuneEightPlanes) ? 8 : kGroupPlanes;
-    const size_t lds_bytes = (size_t)gp * kTile * kTile * 2 * sizeof(float);
-    const int threads = (c->tuning & kTuneWide) ? 1024 : 512;
-    const int kacc = std::min(c->kmax, gp);
-    const bool two = (c->tuning & kTuneTwoCells) != 0;
+    const GridShape gs = grid_shape(c->tuning, c->kmax);
     const int blocks = n_bins;
 #define TOI_TILE_ARGS                                                                                         \
-    dim3(blocks), dim3(threads), lds_bytes, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag, s.freq,   \
-        s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, NT, \
-        cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
-#define TOI_TILE_LAUNCH(KA)                                        \
-    do {                                                           \
-        if (two)                                                   \
-            hipLaunchKernelGGL((k_grid_tiles<KA, 2>), TOI_TILE_ARGS); \
-        else                                                       \
-            hipLaunchKernelGGL((k_grid_tiles<KA, 1>), TOI_TILE_ARGS); \
-    } while (0)
-    if (kacc <= 1)
+    dim3(blocks), dim3(gs.threads), gs.lds_bytes, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag,    \
+        s.freq, s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode,       \
+        c->plan, M, NT, cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
+#define TOI_TILE_LAUNCH(KA) hipLaunchKernelGGL((k_grid_tiles<KA>), TOI_TILE_ARGS)
+    if (gs.mfma) {
+        if (gs.kacc == 16)
+            hipLaunchKernelGGL((k_grid_tiles_mfma<16>), TOI_TILE_ARGS);
+        else
+            hipLaunchKernelGGL((k_grid_tiles_mfma<8>), TOI_TILE_ARGS);
+    } else if (gs.kacc <= 1) {
         TOI_TILE_LAUNCH(1);
-    else if (kacc <= 4)
+    } else if (gs.kacc <= 4) {
         TOI_TILE_LAUNCH(4);
-    else if (kacc <= 8)
+    } else if (gs.kacc <= 8) {
         TOI_TILE_LAUNCH(8);
-    else
+    } else {
         TOI_TILE_LAUNCH(16);
+    }
 #undef TOI_TILE_LAUNCH
 #undef TOI_TILE_ARGS
     return hipGetLastError();

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict_
     constexpr int KEEP = E / 2;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[M];
-    __shared__ float2 tw_s[M / 2];
+    __shared__ float2 tw_s[M];
     __shared__ uint32_t tb[WORDS];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
     const int plane = id / nbands, band = id % nbands;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict_
     constexpr int KEEP = E / 2;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[M];
-    __shared__ float2 tw_s[M / 2];
+    __shared__ float2 tw_s[M];
     extern __shared__ uint32_t rb_s[];                 // [ng][WORDS] nonempty tile rows per group
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
     int j2[KEEP];

@@ -45,12 +45,48 @@ struct DevPlan {
 constexpr int kTile = 32;
 constexpr int kItemChans = 64;
 constexpr int kGroupPlanes = 16;   // largest plane group held in LDS
+constexpr int kScanBlock = 4096;   // bins per workgroup of the bin scan
 
 // Gridder variant chosen by the autotuner (toi_tune / toi_set_tuning):
-// bit 0: two footprint cells per lane (else one); bit 1: 1024-thread
+// bit 0: matrix-core accumulation (v_mfma, when 8 or 16 orders are
+// accumulated per pass; else the vector-ALU kernel); bit 1: 1024-thread
 // workgroups (else 512); bit 2: 8 planes per LDS pass (else 16).
-constexpr int kTuneTwoCells = 1, kTuneWide = 2, kTuneEightPlanes = 4;
-constexpr int kTuneDefault = 0;
+constexpr int kTuneMfma = 1, kTuneWide = 2, kTuneEightPlanes = 4;
+constexpr int kTuneDefault = kTuneMfma;
+constexpr size_t kLdsBytes = 160 * 1024;   // per workgroup on gfx950
+
+// Launch shape of the tile gridder for a variant.  LDS holds the plane group
+// (gp planes of kTile x kTile complex cells) and, per wavefront, a staging
+// area: 64 samples x 16 kernel weights (vector ALU) or 32 samples x (16
+// weights + kacc Chebyshev values) (matrix cores).  A variant whose LDS would
+// exceed a workgroup's 160 KB runs with 8 planes per pass.
+struct GridShape {
+    int gp, threads, kacc;
+    bool mfma;
+    size_t lds_bytes;
+};
+inline int gridder_kacc(int kmax, int gp) {
+    const int k = kmax < gp ? kmax : gp;
+    return k <= 1 ? 1 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+}
+inline size_t gridder_lds(int gp, int threads, int kacc, bool mfma) {
+    const size_t stage = mfma ? (size_t)32 * (16 + kacc) : (size_t)64 * 16;
+    return (size_t)gp * kTile * kTile * 2 * sizeof(float) + (size_t)(threads / 64) * stage * sizeof(float);
+}
+inline GridShape grid_shape(int tuning, int kmax) {
+    GridShape g;
+    g.threads = (tuning & kTuneWide) ? 1024 : 512;
+    g.gp = (tuning & kTuneEightPlanes) ? 8 : kGroupPlanes;
+    g.kacc = gridder_kacc(kmax, g.gp);
+    g.mfma = (tuning & kTuneMfma) && g.kacc >= 8;
+    if (gridder_lds(g.gp, g.threads, g.kacc, g.mfma) > kLdsBytes) {
+        g.gp = 8;
+        g.kacc = gridder_kacc(kmax, g.gp);
+        g.mfma = (tuning & kTuneMfma) && g.kacc >= 8;
+    }
+    g.lds_bytes = gridder_lds(g.gp, g.threads, g.kacc, g.mfma);
+    return g;
+}
 
 // Bin of one work item: tile and group ranges it touches (unwrapped tile
 // indices; wrapped modulo the tiles per axis when used).
@@ -96,6 +132,7 @@ struct toi_ctx {
     int32_t* bin_cursor;  // [NG_max][NT*NT]
     int32_t* bin_list;    // [bin capacity]
     int32_t* bin_order;   // [NG_max][NT*NT] non-empty bins, heaviest first (count in scratch_i[0])
+    int32_t* bin_aux;     // [32] bucket sizes, [32] bucket cursors, then one total per scan block
     int bin_cap;
     uint32_t* tile_bits;  // [NG_max][NT][NT/32]  nonempty tiles of each tile row
     uint32_t* row_bits;   // [NG_max][NT/32]      nonempty tile rows

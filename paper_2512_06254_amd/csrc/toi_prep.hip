@@ -319,7 +319,7 @@ hipError_t launch_prep(toi_ctx* c, const toi_snapshot& s) {
     if (s.n_row > 0)
         hipLaunchKernelGGL(k_row_stats, dim3(s.n_row), dim3(256), 0, c->stream, s.weight, s.flag, s.freq,
                            p.n_chan, p.n_corr, p.corr_mask, c->rows);
-    const int gp = (c->tuning & kTuneEightPlanes) ? 8 : kGroupPlanes;
+    const int gp = grid_shape(c->tuning, c->kmax).gp;
     hipLaunchKernelGGL(k_basis, dim3(1), dim3(256), 0, c->stream, s.uvw, c->rows, s.n_row, p.mode, gp, c->plan);
     if (p.mode == 3) {
         const double cell = p.cell_deg * kPi / 180.0;
