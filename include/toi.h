@@ -157,17 +157,17 @@ toi_status toi_image_batch(toi_ctx* ctx, const toi_snapshot* snaps, int32_t n,
                            float* images_out, float* tlisi_out);
 
 /* Autotuning of the gridder (batched use): the variants differ in the
- * accumulation unit (bit 0: matrix cores, one v_mfma outer product per sample,
- * when 8 or 16 Chebyshev orders are accumulated per pass; else vector ALU),
- * workgroup width (bit 1: 1024 threads, else 512) and the plane schedule
- * (bit 2: 8 planes per LDS pass of a grid tile, else 16; a variant whose LDS
- * would exceed 160 KB uses 8).  All variants compute the same image up to
- * FP32 rounding order.  toi_tune
+ * accumulation unit (bit 0: matrix cores -- one v_mfma outer product per
+ * sample and 8 x 8 grid tile, accumulators in registers; else vector ALU with
+ * the plane group in LDS), workgroup width of the vector-ALU kernel (bit 1:
+ * 1024 threads, else 512) and the plane schedule (bit 2: 8 planes per pass
+ * over a tile, else 16; a variant whose LDS would exceed 160 KB uses 8).  All
+ * variants compute the same image up to FP32 rounding order.  toi_tune
  * synchronises, times grid + image of `sample` with every variant (HIP events,
  * after one warm-up), keeps the fastest in the context and returns it in
  * *variant_out; ms_out (host, TOI_TUNE_VARIANTS entries, nullable) receives
  * each variant's time.  It overwrites the context's workspaces.
- * toi_set_tuning selects a variant directly (default 0). */
+ * toi_set_tuning selects a variant directly (default 1, matrix cores). */
 #define TOI_TUNE_VARIANTS 8
 toi_status toi_tune(toi_ctx* ctx, const toi_snapshot* sample, int32_t* variant_out, float* ms_out);
 toi_status toi_set_tuning(toi_ctx* ctx, int32_t variant);

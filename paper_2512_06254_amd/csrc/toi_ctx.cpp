@@ -172,6 +172,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
     }
     const int k = c->forced_K;
     c->kmax = (k == 1) ? 1 : (k > 0 && k <= 4) ? 4 : (k > 0 && k <= 8) ? 8 : (k > 0 && k <= 16) ? 16 : 32;
+    c->tuning = kTuneDefault;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, TOI_EDEVICE, "toi_create: no HIP device");
@@ -181,7 +182,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
     c->NT = c->M / kTile;
     c->NG_max = std::max(1, 2 * ((c->P_cap + 7) / 8));   // covers plane groups of 8 or 16
     c->n_items_max = std::max(1, p.n_row_max * ((p.n_chan + kItemChans - 1) / kItemChans));
-    c->bin_cap = c->n_items_max * 8 + 1024;
+    c->bin_cap = c->n_items_max * 32 + 4096;
     const size_t NT = c->NT, NG = c->NG_max, words = (NT + 31) / 32;
     struct Alloc { void** ptr; size_t bytes; };
     Alloc allocs[] = {

@@ -28,23 +28,65 @@ __global__ __launch_bounds__(256) void k_zero_f32(float* __restrict__ p, size_t 
         p[i] = 0.f;
 }
 
-// 1. transpose of the bilinear re-projection (t-plane gradient, j1-major)
+// 1. transpose of the bilinear re-projection (t-plane gradient, j1-major).
+// A workgroup takes 16 x 16 output pixels; their bilinear sources cover a
+// small box of the t-plane, which is accumulated in LDS and then added to HBM
+// once (about 1.3 global atomics per output pixel instead of 4).  A box larger
+// than kRaBox x kRaBox (an extreme stretch of the map) falls back to direct
+// global atomics.
+constexpr int kRaTile = 16, kRaBox = 48;
 __global__ __launch_bounds__(256) void k_reproject_adj(const float* __restrict__ gimg, float* __restrict__ gtp,
                                                        const DevPlan* __restrict__ plan, int N, double cell_rad) {
-    const int j1 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j2 = blockIdx.y;
-    if (j1 >= N || (plan->status & kStatusFatal)) return;
-    int i1, i2;
-    float f1, f2;
-    if (!reproject_source(plan, N, cell_rad, j1, j2, i1, i2, f1, f2)) return;
-    const float y = gimg[(size_t)j2 * N + j1];
-    if (y == 0.f) return;
-    float* c0 = gtp + (size_t)i1 * N + i2;
-    float* c1 = c0 + N;
-    unsafeAtomicAdd(c0, (1.f - f1) * (1.f - f2) * y);
-    unsafeAtomicAdd(c1, f1 * (1.f - f2) * y);
-    unsafeAtomicAdd(c0 + 1, (1.f - f1) * f2 * y);
-    unsafeAtomicAdd(c1 + 1, f1 * f2 * y);
+    __shared__ float box[kRaBox * kRaBox];
+    __shared__ int red[4][4];
+    if (plan->status & kStatusFatal) return;
+    const int j1 = blockIdx.x * kRaTile + (threadIdx.x & (kRaTile - 1));
+    const int j2 = blockIdx.y * kRaTile + (threadIdx.x / kRaTile);
+    int i1 = 0, i2 = 0;
+    float f1 = 0.f, f2 = 0.f, y = 0.f;
+    bool ok = j1 < N && j2 < N && reproject_source(plan, N, cell_rad, j1, j2, i1, i2, f1, f2);
+    if (ok) y = gimg[(size_t)j2 * N + j1];
+    ok = ok && y != 0.f;
+    // bounding box of the sources (i1, i2) .. (i1 + 1, i2 + 1)
+    int lo1 = ok ? i1 : 0x7fffffff, lo2 = ok ? i2 : 0x7fffffff, hi1 = ok ? i1 : -1, hi2 = ok ? i2 : -1;
+    lo1 = wave_min(lo1); lo2 = wave_min(lo2); hi1 = wave_max(hi1); hi2 = wave_max(hi2);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[w][0] = lo1; red[w][1] = lo2; red[w][2] = hi1; red[w][3] = hi2; }
+    __syncthreads();
+    for (int k = 0; k < 4; ++k) {
+        lo1 = min(lo1, red[k][0]); lo2 = min(lo2, red[k][1]);
+        hi1 = max(hi1, red[k][2]); hi2 = max(hi2, red[k][3]);
+    }
+    if (hi1 < 0) return;                                   // no contribution (uniform)
+    const int w1 = hi1 - lo1 + 2, w2 = hi2 - lo2 + 2;       // box extent in i1, i2
+    const float a00 = (1.f - f1) * (1.f - f2) * y, a10 = f1 * (1.f - f2) * y;
+    const float a01 = (1.f - f1) * f2 * y, a11 = f1 * f2 * y;
+    if (w1 > kRaBox || w2 > kRaBox) {                       // uniform fallback
+        if (ok) {
+            float* c0 = gtp + (size_t)i1 * N + i2;
+            float* c1 = c0 + N;
+            unsafeAtomicAdd(c0, a00);
+            unsafeAtomicAdd(c1, a10);
+            unsafeAtomicAdd(c0 + 1, a01);
+            unsafeAtomicAdd(c1 + 1, a11);
+        }
+        return;
+    }
+    for (int e = threadIdx.x; e < w1 * kRaBox; e += blockDim.x) box[e] = 0.f;
+    __syncthreads();
+    if (ok) {
+        float* b0 = box + (i1 - lo1) * kRaBox + (i2 - lo2);
+        atomicAdd(b0, a00);
+        atomicAdd(b0 + kRaBox, a10);
+        atomicAdd(b0 + 1, a01);
+        atomicAdd(b0 + kRaBox + 1, a11);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < w1 * w2; e += blockDim.x) {
+        const int d1 = e / w2, d2 = e % w2;
+        const float v = box[d1 * kRaBox + d2];
+        if (v != 0.f) unsafeAtomicAdd(gtp + (size_t)(lo1 + d1) * N + lo2 + d2, v);
+    }
 }
 
 // Miller backward recurrence for J_n(alpha) in FP64 from a per-pixel start
@@ -305,7 +347,7 @@ __global__ __launch_bounds__(256) void k_degrid(
 #pragma unroll
             for (int v = 0; v < KACC / 4; ++v) t4[v] = make_float4(tv[4 * v], tv[4 * v + 1], tv[4 * v + 2], tv[4 * v + 3]);
         }
-        __builtin_amdgcn_wave_barrier();   // staging writes precede the walk's reads
+        lds_order();                       // staging writes precede the walk's reads
         const int K = P->K;
         const size_t MM = (size_t)M * M;
         const int ax = lane & 7, ay = lane >> 3;
@@ -416,8 +458,8 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
     const int N = c->N, M = c->M;
     const double cell = p.cell_deg * kPi / 180.0;
     hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->adj_tp, (size_t)N * N);
-    hipLaunchKernelGGL(k_reproject_adj, dim3((N + 255) / 256, N), dim3(256), 0, c->stream, grad_image, c->adj_tp,
-                       c->plan, N, cell);
+    hipLaunchKernelGGL(k_reproject_adj, dim3((N + kRaTile - 1) / kRaTile, (N + kRaTile - 1) / kRaTile), dim3(256), 0,
+                       c->stream, grad_image, c->adj_tp, c->plan, N, cell);
     switch (M) {
         case 64: launch_adj_ffts<64, 8>(c); break;
         case 128: launch_adj_ffts<128, 8>(c); break;

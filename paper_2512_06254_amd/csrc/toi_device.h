@@ -13,6 +13,14 @@ __device__ inline T wave_sum(T v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+// Order LDS accesses of one wavefront that pass data between its lanes: the
+// hardware executes a wave's LDS instructions in order; this keeps the
+// compiler from moving them across the point.
+__device__ inline void lds_order() {
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Sum over a 64-lane wavefront with DPP row shifts and row broadcasts (fixed
 // order); the total is returned to every lane (from lane 63).
 template <int CTRL, int ROWS>

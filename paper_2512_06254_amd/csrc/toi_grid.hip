@@ -66,10 +66,10 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     const double xlo = fmin(xa, xb), xhi = fmax(xa, xb), ylo = fmin(ya, yb), yhi = fmax(ya, yb);
     const double rlo = fmin(ra, rb), rhi = fmax(ra, rb);
     // footprint cells [ceil(X - 4), ceil(X - 4) + 7] -> tiles (floor division)
-    box.tx0 = ((int)ceil(xlo - 4.0)) >> 5;
-    box.tx1 = ((int)ceil(xhi - 4.0) + 7) >> 5;
-    box.ty0 = ((int)ceil(ylo - 4.0)) >> 5;
-    box.ty1 = ((int)ceil(yhi - 4.0) + 7) >> 5;
+    box.tx0 = ((int)ceil(xlo - 4.0)) >> kTileShift;
+    box.tx1 = ((int)ceil(xhi - 4.0) + 7) >> kTileShift;
+    box.ty0 = ((int)ceil(ylo - 4.0)) >> kTileShift;
+    box.ty1 = ((int)ceil(yhi - 4.0) + 7) >> kTileShift;
     const int p0 = mode == 3 ? slab_index(rlo, P) : 0, p1 = mode == 3 ? slab_index(rhi, P) : 0;
     box.g0 = group_of_slab(min(p0, p1), P);
     box.g1 = group_of_slab(max(p0, p1), P) + (P->K > P->gp ? P->parts - 1 : 0);
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
             footprint_weights(pr.ox, pr.oy, wv);
             store16(sw + lane * 16, wv);
         }
-        __builtin_amdgcn_wave_barrier();   // staging writes precede the walk's reads (LDS is in order per wave)
+        lds_order();                       // staging writes precede the walk's reads
         int cur_x = 0, cur_y = 0, cur_p = -1;
         bool in = false;
         float ar[KACC], ai[KACC];
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
             if (m.cx != cur_x || m.cy != cur_y || m.p != cur_p) {
                 flush();
                 cur_x = m.cx; cur_y = m.cy; cur_p = m.p;
-                in = (((m.cy & (M - 1)) >> 5) == ty) && (((m.cx & (M - 1)) >> 5) == tx);
+                in = (((m.cy & (M - 1)) >> kTileShift) == ty) && (((m.cx & (M - 1)) >> kTileShift) == tx);
 #pragma unroll
                 for (int k = 0; k < KACC; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
             }
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
             if (!m2) break;
         }
         flush();
-        __builtin_amdgcn_wave_barrier();   // the walk's reads precede the next item's staging writes
+        lds_order();                       // the walk's reads precede the next item's staging writes
     }
     __syncthreads();
     // write the tile's planes (only the planes of this group)
@@ -475,36 +475,82 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
 }
 
 // ------------------------------------------------- 3b. tiles, matrix cores
-// The contribution of one sample to its footprint is an outer product: the
-// 64 footprint weights w(cell) times the 2 KACC values T_k(s) Re(g x) and
-// T_k(s) Im(g x).  One v_mfma_f32_32x32x1f32 (KACC = 16: two 32 x 32 blocks,
-// rows = footprint cells, columns = (order, re/im)) or v_mfma_f32_16x16x1f32
-// (KACC = 8: four 16 x 16 blocks) adds it to accumulators that stay in
-// registers while the footprint start of the walked samples does not move;
-// when it moves, they are added to the LDS tile.  Lane l supplies the weight
-// of footprint cell (l mod 8, l / 8) (A operand) and the value of column
-// l mod 2KACC (B operand); accumulator register r of lane l holds cell
-// (4 h + r mod 4, r / 4) (KACC = 16, h = l / 32) or (4 h + r mod 4,
-// 2 (r / 4) + l / 32) (KACC = 8, h = (l / 16) mod 2) of column l mod 2KACC
-// (hardware output layout of these instructions).
-// LDS tile layout: [cell = ly * 32 + lx][slot], slot = 2 plane + re/im XOR
-// 2 (lx mod gp): a flush writes 32 consecutive words per half-wave and the
-// tile write-out reads 16 cells of one plane from distinct banks.
-// Items are staged in halves of 32 samples: per wave [32][16] weights and
-// [32][KACC] Chebyshev values.
-template <int KACC>
-__global__ __launch_bounds__(1024) void k_grid_tiles_mfma(
+// Per-lane raw inputs of one sample.  The matrix-core kernel loads them one
+// work item ahead of use, so the loads overlap the previous item's walk.
+struct SampleRaw {
+    float2 v[4];
+    float wt[4];
+    uint32_t fl;   // flag bytes of the four correlations
+    double nu;
+    bool live;
+};
+__device__ inline void load_sample(SampleRaw& s, const float2* __restrict__ vis, const float* __restrict__ weight,
+                                   const uint8_t* __restrict__ flag, const double* __restrict__ freq, int n_chan,
+                                   int n_corr, uint32_t mask, int r, int c, bool live) {
+    s.live = live;
+    s.nu = 0.0;
+    s.fl = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        s.v[k] = make_float2(0.f, 0.f);
+        s.wt[k] = 0.f;
+    }
+    if (!live) return;
+    const size_t base = ((size_t)r * n_chan + c) * n_corr;
+    s.nu = freq[c];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < n_corr && ((mask >> k) & 1u)) {
+            s.v[k] = vis[base + k];
+            s.wt[k] = weight ? weight[base + k] : 1.f;
+            if (flag) s.fl |= (uint32_t)flag[base + k] << (8 * k);
+        }
+    }
+}
+// Same arithmetic, in the same order, as sample_value.
+__device__ inline float raw_value(const SampleRaw& s, float& xr, float& xi) {
+    float w = 0.f;
+    xr = 0.f;
+    xi = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float wk = ((s.fl >> (8 * k)) & 0xffu) ? 0.f : s.wt[k];
+        w += wk;
+        xr += wk * s.v[k].x;
+        xi += wk * s.v[k].y;
+    }
+    return w;
+}
+
+// Matrix-core gridder.  Tiles are 8 x 8 cells, one v_mfma block: the tile's
+// 64 cells are the rows, the group's planes (order, slab) x {Re, Im} the
+// columns.  The contribution of one sample to the tile is the outer product
+// of its kernel weights at the 64 cells (zero outside its footprint) and the
+// values T_k(s) Re(g x), T_k(s) Im(g x) of the planes of its slab (zero for
+// the group's other planes).  One v_mfma_f32_32x32x1f32 (NCOL = 32: two
+// 32 x 32 blocks) or v_mfma_f32_16x16x1f32 (NCOL = 16: four 16 x 16 blocks)
+// per sample and tile adds it to accumulators that hold the whole tile in
+// registers: no LDS accumulation, no atomics, nothing to flush.  Lane l
+// supplies the weight of cell (l mod 8, l / 8) (A operand) and column
+// l mod NCOL (B operand); accumulator register r of lane l then holds cell
+// (4 (l / 32) + r mod 4, r / 4) (NCOL = 32) or (4 ((l / 16) mod 2) + r mod 4,
+// 2 (r / 4) + l / 32) (NCOL = 16), column l mod NCOL (hardware output layout).
+// One wavefront per tile.  LDS: staging of the item's 64 samples (footprint
+// weights wx[8], wy[8] and the NCOL B values), then the write-out buffer.
+template <int NCOL>
+__global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
     const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
     const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_chan, int n_corr,
     uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
     const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
     const int32_t* __restrict__ order, const int32_t* __restrict__ n_active, float2* __restrict__ grid) {
-    static_assert(KACC == 8 || KACC == 16, "matrix-core gridder handles 8 or 16 orders per pass");
-    constexpr int NREG = KACC == 16 ? 32 : 16;
+    static_assert(NCOL == 16 || NCOL == 32, "one 16- or 32-column matrix block");
+    static_assert(kTile == 8, "a tile is one 64-row matrix block");
+    constexpr int NREG = NCOL;                 // accumulator registers per lane (64 x NCOL / 64)
+    constexpr int NPL = NCOL / 2;              // planes per block
     typedef float acc_t __attribute__((ext_vector_type(NREG)));
     extern __shared__ float lds[];
-    constexpr int TT = kTile * kTile;
     const int tiles = NT * NT;
     if ((int)blockIdx.x >= *n_active) return;
     const int bid = order[blockIdx.x];
@@ -517,127 +563,124 @@ __global__ __launch_bounds__(1024) void k_grid_tiles_mfma(
     int s0, s1, k0, k1;
     group_range(g, P, s0, s1, k0, k1);
     const int nk = k1 - k0;
-    const int n_planes = (s1 - s0) * nk;
-    const int gp = P->gp, SS = 2 * gp;
-    float* tl = lds;   // [TT][SS]
-    for (int i = threadIdx.x; i < TT * SS / 4; i += blockDim.x)
-        reinterpret_cast<float4*>(tl)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    __syncthreads();
+    const int n_planes = (s1 - s0) * nk;       // <= gp <= NPL
+    float* sw = lds;                           // [64][16] footprint weights
+    float* sB = lds + 64 * 16;                 // [64][NCOL] B values
 
     const int tx = tile % NT, ty = tile / NT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    float* sw = lds + TT * SS + wave * 32 * (16 + KACC);   // [32][16] weights
-    float* sT = sw + 32 * 16;                               // [32][KACC] T_{k0 + k}(s)
+    const int lane = threadIdx.x;
     const bool cheb = (mode == 3) && (P->dr3 > 0.0);
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
-    // operand roles of this lane
-    const int ax = lane & 7, ay = lane >> 3;                // A: footprint cell residue
-    const int col = lane & (2 * KACC - 1);                  // B / accumulator column
-    const int kcol = col & (KACC - 1), reim = col / KACC;
-    const int hx = KACC == 16 ? 4 * (lane >> 5) : 4 * ((lane >> 4) & 1);
-    const int hy = KACC == 16 ? 0 : (lane >> 5);
-    const acc_t zero = {};
+    const int col = lane & (NCOL - 1);
+    const int kpl = col % NPL, reim = col / NPL;           // this lane's B column: plane, Re/Im
+    acc_t acc = {};
 
-    for (int it = b0 + wave; it < b1; it += n_waves) {
-        const int item = list[it];
+    int item = list[b0];
+    SampleRaw raw;
+    load_sample(raw, vis, weight, flag, freq, n_chan, n_corr, mask, item / n_chunks,
+                (item % n_chunks) * kItemChans + lane, (item % n_chunks) * kItemChans + lane < n_chan);
+    for (int it = b0; it < b1; ++it) {
         const int r = item / n_chunks;
-        const int c0 = (item % n_chunks) * kItemChans, c1 = min(n_chan, c0 + kItemChans);
         const Track trk = row_track(uvw, r, P, M, cell_rad);
         const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
-        const Prep pr = prepare_sample(uvw, vis, weight, flag, freq, n_chan, n_corr, mask, P, M, cheb, trk, gr, r,
-                                       c0 + lane, c1, tx, ty, s0, s1);
-        const uint64_t all = __ballot(pr.act);
-        if (all == 0) continue;
-        float wv[16], tv[KACC];
-        footprint_weights(pr.ox, pr.oy, wv);
+        int ix = 0, iy = 0, sp = 0;
+        float ss = 0.f, vr = 0.f, vi = 0.f, ox = 4.f, oy = 4.f;
+        bool act = false;
         {
-            float t, tm1;
-            cheb_start(pr.ss, k0, t, tm1);
+            float xr, xi;
+            const float w = raw_value(raw, xr, xi);
+            if (raw.live && w > 0.f) {
+                const double nu = raw.nu;
+                if (cheb) {
+                    const double r3 = trk.a3 * nu;
+                    sp = slab_index(r3, P);
+                    ss = (float)((r3 - (P->r3min + (2 * sp + 1) * P->dr3)) / P->dr3);
+                }
+                const double hM = 0.5 * M;
+                const double X = hM + trk.ax * nu, Y = hM + trk.ay * nu;
+                const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
+                const int jx = (int)fx0, jy = (int)fy0;
+                ox = (float)(X - fx0);
+                oy = (float)(Y - fy0);
+                const int ddx = (jx - tx * kTile) & (M - 1), ddy = (jy - ty * kTile) & (M - 1);
+                act = (sp >= s0 && sp < s1) && (ddx < kTile || ddx >= M - 7) && (ddy < kTile || ddy >= M - 7);
+                ix = jx & (M - 1);
+                iy = jy & (M - 1);
+                vr = xr * gr.x - xi * gr.y;
+                vi = xr * gr.y + xi * gr.x;
+            }
+        }
+        if (it + 1 < b1) {                                  // prefetch the next item's inputs
+            item = list[it + 1];
+            const int cn = (item % n_chunks) * kItemChans + lane;
+            load_sample(raw, vis, weight, flag, freq, n_chan, n_corr, mask, item / n_chunks, cn, cn < n_chan);
+        }
+        uint64_t pending = __ballot(act);
+        if (pending == 0) continue;
+        // staging: this lane's sample (weights by offset from the footprint start; B values)
+        {
+            float wv[16], tv[32], bv[NCOL];
 #pragma unroll
-            for (int k = 0; k < KACC; ++k) {
-                tv[k] = t;
-                const float tn = 2.f * pr.ss * t - tm1;
+            for (int d = 0; d < 8; ++d) {
+                wv[d] = es_kernel(((float)d - ox) * 0.25f);
+                wv[8 + d] = es_kernel(((float)d - oy) * 0.25f);
+            }
+            float t, tm1;
+            cheb_start(ss, k0, t, tm1);
+            const int kmax = nk < 32 ? nk : 32;
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                tv[k] = k < kmax ? t : 0.f;
+                const float tn = 2.f * ss * t - tm1;
                 tm1 = t;
                 t = tn;
             }
+            // plane pl of the group = (slab s0 + pl / nk, order k0 + pl % nk)
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) {
+                const int pl = c % NPL;
+                float v = 0.f;
+                if (pl < n_planes && s0 + pl / nk == sp) v = tv[pl % nk] * (c < NPL ? vr : vi);
+                bv[c] = v;
+            }
+            store16(sw + lane * 16, wv);
+#pragma unroll
+            for (int v = 0; v < NCOL / 16; ++v) store16(sB + lane * NCOL + 16 * v, bv + 16 * v);
         }
-        const int pk = pr.ix | (pr.iy << 13);                // footprint start, M <= 8192
-        int cur_pk = -1, cur_p = 0;
-        acc_t acc = zero;
-
-        // Add the accumulators to the LDS tile for footprint start cur_pk:
-        // register r holds cell (hx + r mod 4, ry(r)) of column col.  Cells
-        // outside the tile and unused columns add 0 at a valid address.
-        auto flush = [&]() {
-            const int qx = cur_pk & 8191, qy = cur_pk >> 13;
-            const bool colok = kcol < nk;
-            const int slot0 = colok ? 2 * ((cur_p - s0) * nk + kcol) + reim : reim;
-            int xo[4];
-            bool xin[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int cx = qx + ((hx + m - qx) & 7);
-                const int lx = cx & (kTile - 1);
-                xin[m] = colok && (((cx & (M - 1)) >> 5) == tx);
-                xo[m] = lx * SS + (slot0 ^ ((lx & (gp - 1)) << 1));
-            }
-#pragma unroll
-            for (int yy = 0; yy < NREG / 4; ++yy) {
-                const int ry = KACC == 16 ? yy : 2 * yy + hy;
-                const int cy = qy + ((ry - qy) & 7);
-                const bool yin = ((cy & (M - 1)) >> 5) == ty;
-                if (KACC == 16 && !yin) continue;        // wave-uniform row
-                float* row = tl + (cy & (kTile - 1)) * kTile * SS;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) atomicAdd(row + xo[m], (xin[m] && yin) ? acc[4 * yy + m] : 0.f);
-            }
-        };
-
-        for (int h = 0; h < 2; ++h) {
-            uint64_t pending = all & (h ? 0xFFFFFFFF00000000ull : 0xFFFFFFFFull);
-            if (pending == 0) continue;
-            if ((lane >> 5) == h) {
-                store16(sw + (lane & 31) * 16, wv);
-                if constexpr (KACC == 16) {
-                    store16(sT + (lane & 31) * 16, tv);
-                } else {
-                    float4* d4 = reinterpret_cast<float4*>(sT + (lane & 31) * 8);
-                    d4[0] = make_float4(tv[0], tv[1], tv[2], tv[3]);
-                    d4[1] = make_float4(tv[4], tv[5], tv[6], tv[7]);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();   // staging writes precede the walk's reads
-            while (pending) {
-                const int q = __ffsll((unsigned long long)pending) - 1;
-                pending &= pending - 1;
-                const int slot = q & 31;
-                const int qpk = __builtin_amdgcn_readlane(pk, q);
-                const int qp = __builtin_amdgcn_readlane(pr.sp, q);
-                const float qvr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.vr), q));
-                const float qvi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.vi), q));
-                const int qx = qpk & 8191, qy = qpk >> 13;
-                const float a = sw[slot * 16 + ((ax - qx) & 7)] * sw[slot * 16 + 8 + ((ay - qy) & 7)];
-                const float b = sT[slot * KACC + kcol] * (reim ? qvi : qvr);
-                if (qpk != cur_pk || qp != cur_p) {      // wave-uniform: the footprint start moved
-                    if (cur_pk >= 0) flush();
-                    cur_pk = qpk;
-                    cur_p = qp;
-                    acc = zero;
-                }
-                if constexpr (KACC == 16) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, acc, 0, 0, 0);
-                else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(a, b, acc, 0, 0, 0);
-            }
-            __builtin_amdgcn_wave_barrier();   // the walk's reads precede the next staging writes
+        lds_order();                                        // staging writes precede the walk's reads
+        const int cxl = tx * kTile + (lane & 7), cyl = ty * kTile + (lane >> 3);   // this lane's A cell
+        while (pending) {
+            const int q = __ffsll((unsigned long long)pending) - 1;
+            pending &= pending - 1;
+            const int qpk = __builtin_amdgcn_readlane(ix | (iy << 13), q);
+            const int dx = (cxl - (qpk & 8191)) & (M - 1), dy = (cyl - (qpk >> 13)) & (M - 1);
+            const float wa = sw[q * 16 + (dx & 7)], wb = sw[q * 16 + 8 + (dy & 7)];
+            const float a = (dx < 8 && dy < 8) ? wa * wb : 0.f;
+            const float b = sB[q * NCOL + col];
+            if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, acc, 0, 0, 0);
+            else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(a, b, acc, 0, 0, 0);
         }
-        flush();
+        lds_order();                                        // the walk's reads precede the next staging writes
+        (void)kpl;
+        (void)reim;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n_planes * TT; i += blockDim.x) {
-        const int pl = i / TT, cell = i % TT;
+    // write-out: accumulators -> LDS [cell][NCOL + 1] -> planes of the group in HBM
+    float* wo = lds;
+    const int hx = NCOL == 32 ? 4 * (lane >> 5) : 4 * ((lane >> 4) & 1);
+    const int hy = NCOL == 32 ? 0 : (lane >> 5);
+#pragma unroll
+    for (int rg = 0; rg < NREG; ++rg) {
+        const int cx = hx + (rg & 3);
+        const int cy = NCOL == 32 ? (rg >> 2) : 2 * (rg >> 2) + hy;
+        wo[(cy * kTile + cx) * (NCOL + 1) + col] = acc[rg];
+    }
+    lds_order();
+    for (int i = threadIdx.x; i < n_planes * 64; i += blockDim.x) {
+        const int pl = i / 64, cell = i % 64;
         const int ly = cell / kTile, lx = cell % kTile;
         const int pg = (s0 + pl / nk) * P->K + k0 + pl % nk;   // global plane index
-        const float2 v = *reinterpret_cast<const float2*>(tl + cell * SS + ((2 * pl) ^ ((lx & (gp - 1)) << 1)));
-        grid[((size_t)pg * M + ty * kTile + ly) * M + tx * kTile + lx] = v;
+        const float* e = wo + cell * (NCOL + 1);
+        grid[((size_t)pg * M + ty * kTile + ly) * M + tx * kTile + lx] = make_float2(e[pl], e[NPL + pl]);
     }
 }
 
@@ -678,10 +721,10 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
         c->plan, M, NT, cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
 #define TOI_TILE_LAUNCH(KA) hipLaunchKernelGGL((k_grid_tiles<KA>), TOI_TILE_ARGS)
     if (gs.mfma) {
-        if (gs.kacc == 16)
-            hipLaunchKernelGGL((k_grid_tiles_mfma<16>), TOI_TILE_ARGS);
+        if (gs.gp > 8)
+            hipLaunchKernelGGL((k_grid_tiles_mfma<32>), TOI_TILE_ARGS);
         else
-            hipLaunchKernelGGL((k_grid_tiles_mfma<8>), TOI_TILE_ARGS);
+            hipLaunchKernelGGL((k_grid_tiles_mfma<16>), TOI_TILE_ARGS);
     } else if (gs.kacc <= 1) {
         TOI_TILE_LAUNCH(1);
     } else if (gs.kacc <= 4) {

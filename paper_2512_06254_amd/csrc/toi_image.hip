@@ -36,7 +36,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict_
     if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) return;   // empty tile row
     if (threadIdx.x < WORDS) tb[threadIdx.x] = tile_bits[((size_t)g * NT + ty) * WORDS + threadIdx.x];
     load_twiddles<M>(tw_s, tw);
-    auto occupied = [&](int x) { return (tb[x >> 10] >> ((x >> 5) & 31)) & 1u; };
+    auto occupied = [&](int x) { return (tb[x >> (kTileShift + 5)] >> ((x >> kTileShift) & 31)) & 1u; };
     float2 keep[B][KEEP];
 #pragma unroll
     for (int rb = 0; rb < B; ++rb) {
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict_
 
     if (mode == 2) {
         float2 v[E];
-        fft_load_masked<M, E>(v, hbuf + (size_t)j1 * M, [&](int y) { return (rb_s[y >> 10] >> ((y >> 5) & 31)) & 1u; });
+        fft_load_masked<M, E>(v, hbuf + (size_t)j1 * M, [&](int y) { return (rb_s[y >> (kTileShift + 5)] >> ((y >> kTileShift) & 31)) & 1u; });
         fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) tr[q] = v[fft_kept_slot<E>(q)].x;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict_
                 float2 v[E];
                 const uint32_t* rbg = rb_s + group_of_plane(p * K + k, plan) * WORDS;
                 fft_load_masked<M, E>(v, hbuf + ((size_t)(p * K + k) * N + j1) * M,
-                                      [&](int y) { return (rbg[y >> 10] >> ((y >> 5) & 31)) & 1u; });
+                                      [&](int y) { return (rbg[y >> (kTileShift + 5)] >> ((y >> kTileShift) & 31)) & 1u; });
                 fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
                 for (int q = 0; q < KEEP; ++q) {

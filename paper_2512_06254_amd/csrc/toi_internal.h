@@ -42,7 +42,7 @@ struct DevPlan {
 
 // Binned gridding: grid tiles of kTile x kTile cells, work items of kItemChans
 // channels of one row, up to kGroupPlanes planes accumulated per tile pass.
-constexpr int kTile = 32;
+constexpr int kTile = 8, kTileShift = 3;
 constexpr int kItemChans = 64;
 constexpr int kGroupPlanes = 16;   // largest plane group held in LDS
 constexpr int kScanBlock = 4096;   // bins per workgroup of the bin scan
@@ -55,11 +55,11 @@ constexpr int kTuneMfma = 1, kTuneWide = 2, kTuneEightPlanes = 4;
 constexpr int kTuneDefault = kTuneMfma;
 constexpr size_t kLdsBytes = 160 * 1024;   // per workgroup on gfx950
 
-// Launch shape of the tile gridder for a variant.  LDS holds the plane group
-// (gp planes of kTile x kTile complex cells) and, per wavefront, a staging
-// area: 64 samples x 16 kernel weights (vector ALU) or 32 samples x (16
-// weights + kacc Chebyshev values) (matrix cores).  A variant whose LDS would
-// exceed a workgroup's 160 KB runs with 8 planes per pass.
+// Launch shape of the tile gridder for a variant.  The matrix-core kernel
+// runs one wavefront per 8 x 8 tile with LDS for staging only; the vector-ALU
+// kernel holds the plane group (gp planes of kTile x kTile complex cells) in
+// LDS plus 64 samples x 16 kernel weights per wavefront.  A variant whose LDS
+// would exceed a workgroup's 160 KB runs with 8 planes per pass.
 struct GridShape {
     int gp, threads, kacc;
     bool mfma;
@@ -70,20 +70,24 @@ inline int gridder_kacc(int kmax, int gp) {
     return k <= 1 ? 1 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
 }
 inline size_t gridder_lds(int gp, int threads, int kacc, bool mfma) {
-    const size_t stage = mfma ? (size_t)32 * (16 + kacc) : (size_t)64 * 16;
-    return (size_t)gp * kTile * kTile * 2 * sizeof(float) + (size_t)(threads / 64) * stage * sizeof(float);
+    if (mfma) {   // staging [64][16 + 2 gp], then reused as the write-out buffer [64][2 gp + 1]
+        const size_t stage = (size_t)64 * (16 + 2 * gp), wout = (size_t)64 * (2 * gp + 1);
+        return (stage > wout ? stage : wout) * sizeof(float);
+    }
+    (void)kacc;
+    return (size_t)gp * kTile * kTile * 2 * sizeof(float) + (size_t)(threads / 64) * 64 * 16 * sizeof(float);
 }
 inline GridShape grid_shape(int tuning, int kmax) {
     GridShape g;
-    g.threads = (tuning & kTuneWide) ? 1024 : 512;
+    g.threads = (tuning & kTuneMfma) ? 64 : (tuning & kTuneWide) ? 1024 : 512;
     g.gp = (tuning & kTuneEightPlanes) ? 8 : kGroupPlanes;
     g.kacc = gridder_kacc(kmax, g.gp);
-    g.mfma = (tuning & kTuneMfma) && g.kacc >= 8;
+    g.mfma = (tuning & kTuneMfma) != 0;
     if (gridder_lds(g.gp, g.threads, g.kacc, g.mfma) > kLdsBytes) {
         g.gp = 8;
         g.kacc = gridder_kacc(kmax, g.gp);
-        g.mfma = (tuning & kTuneMfma) && g.kacc >= 8;
     }
+    if (!g.mfma && g.threads == 64) g.threads = (tuning & kTuneWide) ? 1024 : 512;
     g.lds_bytes = gridder_lds(g.gp, g.threads, g.kacc, g.mfma);
     return g;
 }
