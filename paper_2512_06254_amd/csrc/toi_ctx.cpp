@@ -180,7 +180,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
 
     const size_t N = c->N, M = c->M, P = c->P_cap, T = c->T;
     c->NT = c->M / kTile;
-    c->NG_max = std::max(1, 2 * ((c->P_cap + 7) / 8));   // covers plane groups of 8 or 16
+    c->NG_max = std::max(1, c->P_cap);   // every group holds at least one plane
     c->n_items_max = std::max(1, p.n_row_max * ((p.n_chan + kItemChans - 1) / kItemChans));
     c->bin_cap = c->n_items_max * 32 + 4096;
     const size_t NT = c->NT, NG = c->NG_max, words = (NT + 31) / 32;

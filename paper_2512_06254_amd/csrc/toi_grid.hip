@@ -338,16 +338,18 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
     constexpr int TT = kTile * kTile;
     const int tiles = NT * NT;
     // Non-empty bins in decreasing order of work, dealt round-robin over the
-    // XCDs by the dispatcher (tiles with samples cluster around the uv centre,
-    // so contiguous ranges per XCD would leave most XCDs idle).
-    if ((int)blockIdx.x >= *n_active) return;
-    const int bid = order[blockIdx.x];
-    const int g = bid / tiles, tile = bid % tiles;
+    // workgroups (the dispatcher spreads consecutive workgroups over the
+    // XCDs; tiles with samples cluster around the uv centre, so contiguous
+    // ranges per XCD would leave most XCDs idle).
     if (P->status & kStatusFatal) return;
-    if (g >= P->ng) return;
+    const int n_bins_active = *n_active;
+    for (int ob = blockIdx.x; ob < n_bins_active; ob += gridDim.x) {
+    const int bid = order[ob];
+    const int g = bid / tiles, tile = bid % tiles;
+    if (g >= P->ng) continue;
     const int b0 = bin_off[(size_t)g * tiles + tile];
     const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
-    if (b1 <= b0) return;
+    if (b1 <= b0) continue;
     int s0, s1, k0, k1;
     group_range(g, P, s0, s1, k0, k1);
     const int nk = k1 - k0;
@@ -472,6 +474,8 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
         const int li2 = pl * TT + tile_index(ly, lx);
         grid[((size_t)pg * M + ty * kTile + ly) * M + tx * kTile + lx] = make_float2(lre[li2], lim[li2]);
     }
+    __syncthreads();   // the write-out reads precede the next tile's clear
+    }
 }
 
 // ------------------------------------------------- 3b. tiles, matrix cores
@@ -522,6 +526,9 @@ __device__ inline float raw_value(const SampleRaw& s, float& xr, float& xi) {
     return w;
 }
 
+constexpr int kMfmaWorkgroups = 8192;   // 32 single-wave workgroups per CU
+constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
+
 // Matrix-core gridder.  Tiles are 8 x 8 cells, one v_mfma block: the tile's
 // 64 cells are the rows, the group's planes (order, slab) x {Re, Im} the
 // columns.  The contribution of one sample to the tile is the outer product
@@ -535,8 +542,9 @@ __device__ inline float raw_value(const SampleRaw& s, float& xr, float& xi) {
 // l mod NCOL (B operand); accumulator register r of lane l then holds cell
 // (4 (l / 32) + r mod 4, r / 4) (NCOL = 32) or (4 ((l / 16) mod 2) + r mod 4,
 // 2 (r / 4) + l / 32) (NCOL = 16), column l mod NCOL (hardware output layout).
-// One wavefront per tile.  LDS: staging of the item's 64 samples (footprint
-// weights wx[8], wy[8] and the NCOL B values), then the write-out buffer.
+// One wavefront per tile.  LDS: staging of the item's 64 samples (kernel
+// weights at the tile's eight columns and eight rows, zero outside the
+// footprint, and the NCOL B values), then the write-out buffer.
 template <int NCOL>
 __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
@@ -552,27 +560,27 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     typedef float acc_t __attribute__((ext_vector_type(NREG)));
     extern __shared__ float lds[];
     const int tiles = NT * NT;
-    if ((int)blockIdx.x >= *n_active) return;
-    const int bid = order[blockIdx.x];
-    const int g = bid / tiles, tile = bid % tiles;
     if (P->status & kStatusFatal) return;
-    if (g >= P->ng) return;
-    const int b0 = bin_off[(size_t)g * tiles + tile];
-    const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
-    if (b1 <= b0) return;
-    int s0, s1, k0, k1;
-    group_range(g, P, s0, s1, k0, k1);
-    const int nk = k1 - k0;
-    const int n_planes = (s1 - s0) * nk;       // <= gp <= NPL
     float* sw = lds;                           // [64][16] footprint weights
     float* sB = lds + 64 * 16;                 // [64][NCOL] B values
-
-    const int tx = tile % NT, ty = tile / NT;
     const int lane = threadIdx.x;
     const bool cheb = (mode == 3) && (P->dr3 > 0.0);
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & (NCOL - 1);
-    const int kpl = col % NPL, reim = col / NPL;           // this lane's B column: plane, Re/Im
+    // non-empty bins in decreasing order of work, dealt round-robin over the
+    // workgroups (the dispatcher spreads consecutive workgroups over the XCDs)
+    const int n_bins_active = *n_active;
+    for (int ob = blockIdx.x; ob < n_bins_active; ob += gridDim.x) {
+    const int bid = order[ob];
+    const int g = bid / tiles, tile = bid % tiles;
+    if (g >= P->ng) continue;
+    const int b0 = bin_off[(size_t)g * tiles + tile];
+    const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
+    if (b1 <= b0) continue;
+    int s0, s1, k0, k1;
+    group_range(g, P, s0, s1, k0, k1);         // one slab per group (max_sg = 1)
+    const int nk = k1 - k0;                    // <= gp <= NPL planes
+    const int tx = tile % NT, ty = tile / NT;
     acc_t acc = {};
 
     int item = list[b0];
@@ -619,50 +627,43 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
         if (pending == 0) continue;
         // staging: this lane's sample (weights by offset from the footprint start; B values)
         {
-            float wv[16], tv[32], bv[NCOL];
+            // weights at the tile's columns / rows i = 0..7 (0 outside the footprint)
+            float wv[16], bv[NCOL];
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                wv[d] = es_kernel(((float)d - ox) * 0.25f);
-                wv[8 + d] = es_kernel(((float)d - oy) * 0.25f);
+            for (int i = 0; i < 8; ++i) {
+                const int dx = (tx * kTile + i - ix) & (M - 1), dy = (ty * kTile + i - iy) & (M - 1);
+                wv[i] = dx < 8 ? es_kernel(((float)dx - ox) * 0.25f) : 0.f;
+                wv[8 + i] = dy < 8 ? es_kernel(((float)dy - oy) * 0.25f) : 0.f;
             }
+            // column c: order k0 + c mod NPL of the group's slab, Re (c < NPL) or Im
             float t, tm1;
             cheb_start(ss, k0, t, tm1);
-            const int kmax = nk < 32 ? nk : 32;
 #pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                tv[k] = k < kmax ? t : 0.f;
+            for (int k = 0; k < NPL; ++k) {
+                const float tk = k < nk ? t : 0.f;
+                bv[k] = tk * vr;
+                bv[NPL + k] = tk * vi;
                 const float tn = 2.f * ss * t - tm1;
                 tm1 = t;
                 t = tn;
-            }
-            // plane pl of the group = (slab s0 + pl / nk, order k0 + pl % nk)
-#pragma unroll
-            for (int c = 0; c < NCOL; ++c) {
-                const int pl = c % NPL;
-                float v = 0.f;
-                if (pl < n_planes && s0 + pl / nk == sp) v = tv[pl % nk] * (c < NPL ? vr : vi);
-                bv[c] = v;
             }
             store16(sw + lane * 16, wv);
 #pragma unroll
             for (int v = 0; v < NCOL / 16; ++v) store16(sB + lane * NCOL + 16 * v, bv + 16 * v);
         }
         lds_order();                                        // staging writes precede the walk's reads
-        const int cxl = tx * kTile + (lane & 7), cyl = ty * kTile + (lane >> 3);   // this lane's A cell
+        const float* wa_l = sw + (lane & 7);                // this lane's A cell (lane mod 8, lane / 8)
+        const float* wb_l = sw + 8 + (lane >> 3);
+        const float* b_l = sB + col;
         while (pending) {
             const int q = __ffsll((unsigned long long)pending) - 1;
             pending &= pending - 1;
-            const int qpk = __builtin_amdgcn_readlane(ix | (iy << 13), q);
-            const int dx = (cxl - (qpk & 8191)) & (M - 1), dy = (cyl - (qpk >> 13)) & (M - 1);
-            const float wa = sw[q * 16 + (dx & 7)], wb = sw[q * 16 + 8 + (dy & 7)];
-            const float a = (dx < 8 && dy < 8) ? wa * wb : 0.f;
-            const float b = sB[q * NCOL + col];
+            const float a = wa_l[q * 16] * wb_l[q * 16];
+            const float b = b_l[q * NCOL];
             if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, acc, 0, 0, 0);
             else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(a, b, acc, 0, 0, 0);
         }
         lds_order();                                        // the walk's reads precede the next staging writes
-        (void)kpl;
-        (void)reim;
     }
     // write-out: accumulators -> LDS [cell][NCOL + 1] -> planes of the group in HBM
     float* wo = lds;
@@ -675,12 +676,14 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
         wo[(cy * kTile + cx) * (NCOL + 1) + col] = acc[rg];
     }
     lds_order();
-    for (int i = threadIdx.x; i < n_planes * 64; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nk * 64; i += blockDim.x) {
         const int pl = i / 64, cell = i % 64;
         const int ly = cell / kTile, lx = cell % kTile;
-        const int pg = (s0 + pl / nk) * P->K + k0 + pl % nk;   // global plane index
+        const int pg = s0 * P->K + k0 + pl;    // global plane index
         const float* e = wo + cell * (NCOL + 1);
         grid[((size_t)pg * M + ty * kTile + ly) * M + tx * kTile + lx] = make_float2(e[pl], e[NPL + pl]);
+    }
+    lds_order();                               // the write-out reads precede the next tile's staging writes
     }
 }
 
@@ -714,17 +717,23 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
     if (n_items == 0) return hipGetLastError();
     StageTimer timer(c, TOI_STAGE_GRID);
     const GridShape gs = grid_shape(c->tuning, c->kmax);
-    const int blocks = n_bins;
+    const int blocks = std::min(n_bins, kValuWorkgroups);
 #define TOI_TILE_ARGS                                                                                         \
     dim3(blocks), dim3(gs.threads), gs.lds_bytes, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag,    \
         s.freq, s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode,       \
         c->plan, M, NT, cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
 #define TOI_TILE_LAUNCH(KA) hipLaunchKernelGGL((k_grid_tiles<KA>), TOI_TILE_ARGS)
-    if (gs.mfma) {
+    if (gs.mfma) {   // a fixed grid of single-wave workgroups takes the non-empty bins in turn
+        const int mblocks = std::min(n_bins, kMfmaWorkgroups);
+#define TOI_MFMA_ARGS                                                                                         \
+    dim3(mblocks), dim3(64), gs.lds_bytes, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag, s.freq,     \
+        s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, NT, \
+        cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
         if (gs.gp > 8)
-            hipLaunchKernelGGL((k_grid_tiles_mfma<32>), TOI_TILE_ARGS);
+            hipLaunchKernelGGL((k_grid_tiles_mfma<32>), TOI_MFMA_ARGS);
         else
-            hipLaunchKernelGGL((k_grid_tiles_mfma<16>), TOI_TILE_ARGS);
+            hipLaunchKernelGGL((k_grid_tiles_mfma<16>), TOI_MFMA_ARGS);
+#undef TOI_MFMA_ARGS
     } else if (gs.kacc <= 1) {
         TOI_TILE_LAUNCH(1);
     } else if (gs.kacc <= 4) {

@@ -37,7 +37,8 @@ struct DevPlan {
     int32_t kp;           // Chebyshev orders per group when K > gp
     int32_t parts;        // groups per slab when K > gp (1 otherwise)
     int32_t gp;           // planes per group (LDS pass of the gridder)
-    int32_t pad2_[3];
+    int32_t max_sg;       // at most this many slabs share a group (1: matrix-core gridder)
+    int32_t pad2_[2];
 };
 
 // Binned gridding: grid tiles of kTile x kTile cells, work items of kItemChans
@@ -48,9 +49,9 @@ constexpr int kGroupPlanes = 16;   // largest plane group held in LDS
 constexpr int kScanBlock = 4096;   // bins per workgroup of the bin scan
 
 // Gridder variant chosen by the autotuner (toi_tune / toi_set_tuning):
-// bit 0: matrix-core accumulation (v_mfma, when 8 or 16 orders are
-// accumulated per pass; else the vector-ALU kernel); bit 1: 1024-thread
-// workgroups (else 512); bit 2: 8 planes per LDS pass (else 16).
+// bit 0: matrix-core accumulation (v_mfma; one slab per plane group), else the
+// vector-ALU kernel; bit 1: 1024-thread workgroups for the vector-ALU kernel
+// (else 512); bit 2: 8 planes per pass over a tile (else 16).
 constexpr int kTuneMfma = 1, kTuneWide = 2, kTuneEightPlanes = 4;
 constexpr int kTuneDefault = kTuneMfma;
 constexpr size_t kLdsBytes = 160 * 1024;   // per workgroup on gfx950
@@ -61,7 +62,7 @@ constexpr size_t kLdsBytes = 160 * 1024;   // per workgroup on gfx950
 // LDS plus 64 samples x 16 kernel weights per wavefront.  A variant whose LDS
 // would exceed a workgroup's 160 KB runs with 8 planes per pass.
 struct GridShape {
-    int gp, threads, kacc;
+    int gp, threads, kacc, max_sg;
     bool mfma;
     size_t lds_bytes;
 };
@@ -88,6 +89,7 @@ inline GridShape grid_shape(int tuning, int kmax) {
         g.kacc = gridder_kacc(kmax, g.gp);
     }
     if (!g.mfma && g.threads == 64) g.threads = (tuning & kTuneWide) ? 1024 : 512;
+    g.max_sg = g.mfma ? 1 : g.gp;
     g.lds_bytes = gridder_lds(g.gp, g.threads, g.kacc, g.mfma);
     return g;
 }

@@ -94,7 +94,7 @@ __device__ inline void positive_major(double e[3]) {
 }
 
 __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, const RowStat* __restrict__ rows,
-                                               int n_row, int mode, int gp, DevPlan* __restrict__ plan) {
+                                               int n_row, int mode, int gp, int max_sg, DevPlan* __restrict__ plan) {
     __shared__ double red[16][4];
     __shared__ double V_s[9];
     __shared__ uint32_t status_s;
@@ -160,10 +160,11 @@ __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, c
         P.K = 1;
         P.planes = 1;
         P.ng = 1;
-        P.sg = gp;
+        P.sg = min(gp, max_sg);
         P.kp = 1;
         P.parts = 1;
         P.gp = gp;
+        P.max_sg = max_sg;
         P.status = st;
         *plan = P;
         for (int i = 0; i < 9; ++i) V_s[i] = P.V[i];
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(256) void k_plan(double alpha_target, double gamma,
         plan->miller_top = 2 * ((K + 16 + (int)ceil(1.5 * fabs(a_slab))) / 2);
         const int gp = plan->gp;
         if (K <= gp) {
-            plan->sg = gp / K;
+            plan->sg = min(gp / K, plan->max_sg);
             plan->kp = K;
             plan->parts = 1;
             plan->ng = (plan->n_slab + plan->sg - 1) / plan->sg;
@@ -319,8 +320,9 @@ hipError_t launch_prep(toi_ctx* c, const toi_snapshot& s) {
     if (s.n_row > 0)
         hipLaunchKernelGGL(k_row_stats, dim3(s.n_row), dim3(256), 0, c->stream, s.weight, s.flag, s.freq,
                            p.n_chan, p.n_corr, p.corr_mask, c->rows);
-    const int gp = grid_shape(c->tuning, c->kmax).gp;
-    hipLaunchKernelGGL(k_basis, dim3(1), dim3(256), 0, c->stream, s.uvw, c->rows, s.n_row, p.mode, gp, c->plan);
+    const GridShape gs = grid_shape(c->tuning, c->kmax);
+    hipLaunchKernelGGL(k_basis, dim3(1), dim3(256), 0, c->stream, s.uvw, c->rows, s.n_row, p.mode, gs.gp, gs.max_sg,
+                       c->plan);
     if (p.mode == 3) {
         const double cell = p.cell_deg * kPi / 180.0;
         const long total = (long)c->N * c->N;
