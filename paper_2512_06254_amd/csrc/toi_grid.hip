@@ -655,13 +655,31 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
         const float* wa_l = sw + (lane & 7);                // this lane's A cell (lane mod 8, lane / 8)
         const float* wb_l = sw + 8 + (lane >> 3);
         const float* b_l = sB + col;
-        while (pending) {
-            const int q = __ffsll((unsigned long long)pending) - 1;
+        // software-pipelined walk (two operand sets in turn): the next
+        // sample's operands are read from LDS while the current outer product
+        // runs
+        auto take = [&](float& xa, float& xb, float& xc) __attribute__((always_inline)) {
+            const int q = pending ? __ffsll((unsigned long long)pending) - 1 : 0;   // slot 0 past the end
             pending &= pending - 1;
-            const float a = wa_l[q * 16] * wb_l[q * 16];
-            const float b = b_l[q * NCOL];
-            if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, acc, 0, 0, 0);
-            else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(a, b, acc, 0, 0, 0);
+            xa = wa_l[q * 16];
+            xb = wb_l[q * 16];
+            xc = b_l[q * NCOL];
+        };
+        auto outer = [&](float xa, float xb, float xc) __attribute__((always_inline)) {
+            if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(xa * xb, xc, acc, 0, 0, 0);
+            else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(xa * xb, xc, acc, 0, 0, 0);
+        };
+        float a0, b0, c0, a1, b1, c1;
+        take(a0, b0, c0);
+        while (true) {                                      // the reads run unconditionally, so the
+            const bool m1 = pending != 0;                   // LDS counter state is the same on every path
+            take(a1, b1, c1);
+            outer(a0, b0, c0);
+            if (!m1) break;
+            const bool m2 = pending != 0;
+            take(a0, b0, c0);
+            outer(a1, b1, c1);
+            if (!m2) break;
         }
         lds_order();                                        // the walk's reads precede the next staging writes
     }
