@@ -625,31 +625,39 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
         }
         uint64_t pending = __ballot(act);
         if (pending == 0) continue;
-        // staging: this lane's sample (weights by offset from the footprint start; B values)
+        // staging of this lane's sample, written four values at a time
         {
             // weights at the tile's columns / rows i = 0..7 (0 outside the footprint)
-            float wv[16], bv[NCOL];
+            float4* dw = reinterpret_cast<float4*>(sw + lane * 16);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int dx = (tx * kTile + i - ix) & (M - 1), dy = (ty * kTile + i - iy) & (M - 1);
-                wv[i] = dx < 8 ? es_kernel(((float)dx - ox) * 0.25f) : 0.f;
-                wv[8 + i] = dy < 8 ? es_kernel(((float)dy - oy) * 0.25f) : 0.f;
+            for (int h = 0; h < 4; ++h) {
+                float w4[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = (h & 1) * 4 + j;
+                    const int d = h < 2 ? (tx * kTile + i - ix) & (M - 1) : (ty * kTile + i - iy) & (M - 1);
+                    w4[j] = d < 8 ? es_kernel(((float)d - (h < 2 ? ox : oy)) * 0.25f) : 0.f;
+                }
+                dw[h] = make_float4(w4[0], w4[1], w4[2], w4[3]);
             }
             // column c: order k0 + c mod NPL of the group's slab, Re (c < NPL) or Im
+            float4* dbr = reinterpret_cast<float4*>(sB + lane * NCOL);
+            float4* dbi = reinterpret_cast<float4*>(sB + lane * NCOL + NPL);
             float t, tm1;
             cheb_start(ss, k0, t, tm1);
 #pragma unroll
-            for (int k = 0; k < NPL; ++k) {
-                const float tk = k < nk ? t : 0.f;
-                bv[k] = tk * vr;
-                bv[NPL + k] = tk * vi;
-                const float tn = 2.f * ss * t - tm1;
-                tm1 = t;
-                t = tn;
-            }
-            store16(sw + lane * 16, wv);
+            for (int k4 = 0; k4 < NPL / 4; ++k4) {
+                float tr[4];
 #pragma unroll
-            for (int v = 0; v < NCOL / 16; ++v) store16(sB + lane * NCOL + 16 * v, bv + 16 * v);
+                for (int j = 0; j < 4; ++j) {
+                    tr[j] = 4 * k4 + j < nk ? t : 0.f;
+                    const float tn = 2.f * ss * t - tm1;
+                    tm1 = t;
+                    t = tn;
+                }
+                dbr[k4] = make_float4(tr[0] * vr, tr[1] * vr, tr[2] * vr, tr[3] * vr);
+                dbi[k4] = make_float4(tr[0] * vi, tr[1] * vi, tr[2] * vi, tr[3] * vi);
+            }
         }
         lds_order();                                        // staging writes precede the walk's reads
         const float* wa_l = sw + (lane & 7);                // this lane's A cell (lane mod 8, lane / 8)
