@@ -30,11 +30,15 @@
 namespace toi {
 
 // ---------------------------------------------------------------- 1. items
-__global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, const float* __restrict__ weight,
-                                               const uint8_t* __restrict__ flag, const double* __restrict__ freq,
-                                               int n_chan, int n_corr, uint32_t mask, int mode,
+// One wavefront per item; lane l also writes the gridding record of channel
+// c0 + l (FP64 coordinates split into a cell and FP32 offsets once per sample).
+__global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, const float2* __restrict__ vis,
+                                               const float* __restrict__ weight, const uint8_t* __restrict__ flag,
+                                               const double* __restrict__ freq, const int32_t* __restrict__ ant1,
+                                               const int32_t* __restrict__ ant2, const float2* __restrict__ gains,
+                                               int n_ant, int n_chan, int n_corr, uint32_t mask, int mode,
                                                const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
-                                               int n_items, ItemBox* __restrict__ items,
+                                               int n_items, ItemBox* __restrict__ items, SampleRec* __restrict__ recs,
                                                int32_t* __restrict__ bin_count) {
     const int lane = threadIdx.x & 63;
     const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -50,10 +54,41 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
         return;
     }
     const Track tr = row_track(uvw, r, P, M, cell_rad);
+    // gridding record of this lane's sample
+    bool kept = false;
+    if (c < n_chan) {
+        float xr, xi;
+        const float w = sample_value(vis, weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask, xr, xi);
+        SampleRec rec;
+        rec.pk = -1;
+        rec.sp = 0;
+        rec.ox = rec.oy = 4.f;
+        rec.ss = rec.vr = rec.vi = rec.pad_ = 0.f;
+        if (w > 0.f) {
+            kept = true;
+            const double nu = freq[c];
+            if (mode == 3 && P->dr3 > 0.0) {
+                const double r3 = tr.a3 * nu;
+                rec.sp = slab_index(r3, P);
+                rec.ss = (float)((r3 - (P->r3min + (2 * rec.sp + 1) * P->dr3)) / P->dr3);
+            }
+            const double X = 0.5 * M + tr.ax * nu, Y = 0.5 * M + tr.ay * nu;
+            const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
+            rec.pk = ((int)fx0 & (M - 1)) | (((int)fy0 & (M - 1)) << 13);
+            rec.ox = (float)(X - fx0);
+            rec.oy = (float)(Y - fy0);
+            const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
+            rec.vr = xr * gr.x - xi * gr.y;
+            rec.vi = xr * gr.y + xi * gr.x;
+        }
+        float4* dst = reinterpret_cast<float4*>(recs + (size_t)r * n_chan + c);
+        dst[0] = make_float4(__int_as_float(rec.pk), __int_as_float(rec.sp), rec.ox, rec.oy);
+        dst[1] = make_float4(rec.ss, rec.vr, rec.vi, 0.f);
+    }
     // X, Y and r3 are linear in nu along the row: their extremes over the kept
     // channels sit at the extreme kept frequencies
     double nlo = 1e300, nhi = -1e300;
-    if (c < n_chan && sample_kept(weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask)) nlo = nhi = freq[c];
+    if (kept) nlo = nhi = freq[c];
     nlo = wave_min(nlo);
     nhi = wave_max(nhi);
     if (nlo > nhi) {   // no kept sample
@@ -479,53 +514,6 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
 }
 
 // ------------------------------------------------- 3b. tiles, matrix cores
-// Per-lane raw inputs of one sample.  The matrix-core kernel loads them one
-// work item ahead of use, so the loads overlap the previous item's walk.
-struct SampleRaw {
-    float2 v[4];
-    float wt[4];
-    uint32_t fl;   // flag bytes of the four correlations
-    double nu;
-    bool live;
-};
-__device__ inline void load_sample(SampleRaw& s, const float2* __restrict__ vis, const float* __restrict__ weight,
-                                   const uint8_t* __restrict__ flag, const double* __restrict__ freq, int n_chan,
-                                   int n_corr, uint32_t mask, int r, int c, bool live) {
-    s.live = live;
-    s.nu = 0.0;
-    s.fl = 0u;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        s.v[k] = make_float2(0.f, 0.f);
-        s.wt[k] = 0.f;
-    }
-    if (!live) return;
-    const size_t base = ((size_t)r * n_chan + c) * n_corr;
-    s.nu = freq[c];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (k < n_corr && ((mask >> k) & 1u)) {
-            s.v[k] = vis[base + k];
-            s.wt[k] = weight ? weight[base + k] : 1.f;
-            if (flag) s.fl |= (uint32_t)flag[base + k] << (8 * k);
-        }
-    }
-}
-// Same arithmetic, in the same order, as sample_value.
-__device__ inline float raw_value(const SampleRaw& s, float& xr, float& xi) {
-    float w = 0.f;
-    xr = 0.f;
-    xi = 0.f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float wk = ((s.fl >> (8 * k)) & 0xffu) ? 0.f : s.wt[k];
-        w += wk;
-        xr += wk * s.v[k].x;
-        xi += wk * s.v[k].y;
-    }
-    return w;
-}
-
 constexpr int kMfmaWorkgroups = 8192;   // 32 single-wave workgroups per CU
 constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
 
@@ -542,15 +530,14 @@ constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
 // l mod NCOL (B operand); accumulator register r of lane l then holds cell
 // (4 (l / 32) + r mod 4, r / 4) (NCOL = 32) or (4 ((l / 16) mod 2) + r mod 4,
 // 2 (r / 4) + l / 32) (NCOL = 16), column l mod NCOL (hardware output layout).
-// One wavefront per tile.  LDS: staging of the item's 64 samples (kernel
-// weights at the tile's eight columns and eight rows, zero outside the
-// footprint, and the NCOL B values), then the write-out buffer.
+// One wavefront per tile.  The samples come as gridding records written by
+// k_items (cell, offsets, slab, Chebyshev argument, g x); each next item's
+// records are loaded during the current walk.  LDS: staging of the item's 64
+// samples (kernel weights at the tile's eight columns and eight rows, zero
+// outside the footprint, and the NCOL B values), then the write-out buffer.
 template <int NCOL>
 __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
-    const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
-    const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
-    const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_chan, int n_corr,
-    uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
+    const SampleRec* __restrict__ recs, int n_chan, const DevPlan* __restrict__ P, int M, int NT,
     const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
     const int32_t* __restrict__ order, const int32_t* __restrict__ n_active, float2* __restrict__ grid) {
     static_assert(NCOL == 16 || NCOL == 32, "one 16- or 32-column matrix block");
@@ -564,7 +551,6 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     float* sw = lds;                           // [64][16] footprint weights
     float* sB = lds + 64 * 16;                 // [64][NCOL] B values
     const int lane = threadIdx.x;
-    const bool cheb = (mode == 3) && (P->dr3 > 0.0);
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & (NCOL - 1);
     // non-empty bins in decreasing order of work, dealt round-robin over the
@@ -583,46 +569,29 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     const int tx = tile % NT, ty = tile / NT;
     acc_t acc = {};
 
-    int item = list[b0];
-    SampleRaw raw;
-    load_sample(raw, vis, weight, flag, freq, n_chan, n_corr, mask, item / n_chunks,
-                (item % n_chunks) * kItemChans + lane, (item % n_chunks) * kItemChans + lane < n_chan);
+    // gridding records of the first item; each next item's are loaded
+    // during the current walk
+    auto load_rec = [&](int item_, float4& ra, float4& rb) __attribute__((always_inline)) {
+        const int c = (item_ % n_chunks) * kItemChans + lane;
+        if (c < n_chan) {
+            const float4* src = reinterpret_cast<const float4*>(recs + (size_t)(item_ / n_chunks) * n_chan + c);
+            ra = src[0];
+            rb = src[1];
+        } else {
+            ra = make_float4(__int_as_float(-1), 0.f, 4.f, 4.f);
+            rb = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    float4 ra, rb;
+    load_rec(list[b0], ra, rb);
     for (int it = b0; it < b1; ++it) {
-        const int r = item / n_chunks;
-        const Track trk = row_track(uvw, r, P, M, cell_rad);
-        const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
-        int ix = 0, iy = 0, sp = 0;
-        float ss = 0.f, vr = 0.f, vi = 0.f, ox = 4.f, oy = 4.f;
-        bool act = false;
-        {
-            float xr, xi;
-            const float w = raw_value(raw, xr, xi);
-            if (raw.live && w > 0.f) {
-                const double nu = raw.nu;
-                if (cheb) {
-                    const double r3 = trk.a3 * nu;
-                    sp = slab_index(r3, P);
-                    ss = (float)((r3 - (P->r3min + (2 * sp + 1) * P->dr3)) / P->dr3);
-                }
-                const double hM = 0.5 * M;
-                const double X = hM + trk.ax * nu, Y = hM + trk.ay * nu;
-                const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
-                const int jx = (int)fx0, jy = (int)fy0;
-                ox = (float)(X - fx0);
-                oy = (float)(Y - fy0);
-                const int ddx = (jx - tx * kTile) & (M - 1), ddy = (jy - ty * kTile) & (M - 1);
-                act = (sp >= s0 && sp < s1) && (ddx < kTile || ddx >= M - 7) && (ddy < kTile || ddy >= M - 7);
-                ix = jx & (M - 1);
-                iy = jy & (M - 1);
-                vr = xr * gr.x - xi * gr.y;
-                vi = xr * gr.y + xi * gr.x;
-            }
-        }
-        if (it + 1 < b1) {                                  // prefetch the next item's inputs
-            item = list[it + 1];
-            const int cn = (item % n_chunks) * kItemChans + lane;
-            load_sample(raw, vis, weight, flag, freq, n_chan, n_corr, mask, item / n_chunks, cn, cn < n_chan);
-        }
+        const int pk = __float_as_int(ra.x), sp = __float_as_int(ra.y);
+        const int ix = pk & 8191, iy = (pk >> 13) & 8191;
+        const float ox = ra.z, oy = ra.w, ss = rb.x, vr = rb.y, vi = rb.z;
+        const int ddx = (ix - tx * kTile) & (M - 1), ddy = (iy - ty * kTile) & (M - 1);
+        const bool act = pk >= 0 && (sp >= s0 && sp < s1) && (ddx < kTile || ddx >= M - 7) &&
+                         (ddy < kTile || ddy >= M - 7);
+        if (it + 1 < b1) load_rec(list[it + 1], ra, rb);   // prefetch the next item's records
         uint64_t pending = __ballot(act);
         if (pending == 0) continue;
         // staging of this lane's sample, written four values at a time
@@ -727,9 +696,10 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
         hipLaunchKernelGGL(k_scan_clear, dim3(256), dim3(256), 0, c->stream, c->bin_count, n_bins, c->bin_aux,
                            c->row_bits, c->NG_max * words);
         if (n_items > 0)
-            hipLaunchKernelGGL(k_items, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw, s.weight, s.flag,
-                               s.freq, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, NT, cell, n_items,
-                               c->items, c->bin_count);
+            hipLaunchKernelGGL(k_items, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw,
+                               (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2,
+                               (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M,
+                               NT, cell, n_items, c->items, c->recs, c->bin_count);
         hipLaunchKernelGGL(k_scan_local, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, c->bin_off,
                            c->bin_aux);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, n_scan, n_bins, c->bin_cap, c->plan,
@@ -751,10 +721,9 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
 #define TOI_TILE_LAUNCH(KA) hipLaunchKernelGGL((k_grid_tiles<KA>), TOI_TILE_ARGS)
     if (gs.mfma) {   // a fixed grid of single-wave workgroups takes the non-empty bins in turn
         const int mblocks = std::min(n_bins, kMfmaWorkgroups);
-#define TOI_MFMA_ARGS                                                                                         \
-    dim3(mblocks), dim3(64), gs.lds_bytes, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag, s.freq,     \
-        s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, NT, \
-        cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
+#define TOI_MFMA_ARGS                                                                                      \
+    dim3(mblocks), dim3(64), gs.lds_bytes, c->stream, c->recs, p.n_chan, c->plan, M, NT, c->bin_off, c->bin_list, \
+        c->bin_cap, c->bin_order, c->scratch_i, c->grid
         if (gs.gp > 8)
             hipLaunchKernelGGL((k_grid_tiles_mfma<32>), TOI_MFMA_ARGS);
         else

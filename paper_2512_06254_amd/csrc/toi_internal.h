@@ -100,6 +100,15 @@ struct ItemBox {
     int32_t tx0, tx1, ty0, ty1, g0, g1, pad_[2];
 };
 
+// One sample prepared for gridding (written by k_items, read by the
+// matrix-core gridder at every tile the sample's item visits): footprint
+// start ix | iy << 13 (-1: sample not kept), slab, offsets of the sample from
+// the start in (3, 4], Chebyshev argument, value g x.
+struct SampleRec {
+    int32_t pk, sp;
+    float ox, oy, ss, vr, vi, pad_;
+};
+
 // Per-row partial sums of the kept samples (sample prep).
 struct RowStat {
     double cnt;           // kept channels
@@ -133,6 +142,7 @@ struct toi_ctx {
     int NG_max;           // plane-group capacity
     int n_items_max;      // work items capacity (n_row_max * chunks)
     toi::ItemBox* items;  // [n_items_max]
+    toi::SampleRec* recs; // [n_row_max][n_chan] gridding records
     int32_t* bin_count;   // [NG_max][NT*NT]
     int32_t* bin_off;     // [NG_max][NT*NT + 1]
     int32_t* bin_cursor;  // [NG_max][NT*NT]
