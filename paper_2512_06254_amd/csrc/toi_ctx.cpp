@@ -188,6 +188,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
     Alloc allocs[] = {
         {(void**)&c->items, (size_t)c->n_items_max * sizeof(ItemBox)},
         {(void**)&c->recs, std::max<size_t>(1, (size_t)p.n_row_max * p.n_chan) * sizeof(SampleRec)},
+        {(void**)&c->gx, std::max<size_t>(1, (size_t)p.n_row_max * p.n_chan) * sizeof(float2)},
         {(void**)&c->bin_count, NG * NT * NT * sizeof(int32_t)},
         {(void**)&c->bin_off, (NG * NT * NT + 1) * sizeof(int32_t)},
         {(void**)&c->bin_cursor, NG * NT * NT * sizeof(int32_t)},
@@ -249,7 +250,7 @@ toi_status toi_destroy(toi_ctx* c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
     if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
-    void* ptrs[] = {c->items, c->recs, c->bin_order, c->bin_aux, c->bin_count, c->bin_off, c->bin_cursor, c->bin_list, c->tile_bits, c->row_bits,
+    void* ptrs[] = {c->items, c->recs, c->gx, c->bin_order, c->bin_aux, c->bin_count, c->bin_off, c->bin_cursor, c->bin_list, c->tile_bits, c->row_bits,
                     c->adj_tp, c->item_gain, c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
                     c->scratch_d, c->scratch_i, c->det_scores, c->det_boxes, c->batch_desc};
     for (void* q : ptrs)

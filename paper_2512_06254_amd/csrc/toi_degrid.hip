@@ -17,11 +17,15 @@
 //      sum), reduced per antenna in FP64 in a fixed order.
 // The grid and row-pass workspaces are reused, so toi_grid must run again
 // before the next toi_image.
+#include <algorithm>
+
 #include "toi_fft.h"
 #include "toi_grid.h"
 #include "toi_internal.h"
 
 namespace toi {
+
+constexpr int kDegridWorkgroups = 8192;   // persistent single-wave workgroups
 
 __global__ __launch_bounds__(256) void k_zero_f32(float* __restrict__ p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -275,119 +279,164 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict_
     }
 }
 
-// 4-5. Gather degridding (transpose of S4), one wavefront per work item (64
-// channels of a row), walked in channel order like the gridder: lane (i, j)
-// holds the plane gradients G_k of its footprint cell (x = i, y = j mod 8),
-// reloaded from the grid only when the footprint start or the slab moves
-// (Romein, ICS 2012).  Per sample q: grad x_q = sum over the 64 cells of
-// w_q(cell) sum_k T_k(s_q) G_k(cell) -- each lane forms its cell's term with
-// the weights and Chebyshev values staged in LDS, and a DPP reduction over
-// the wavefront sums them; lane q keeps the result.  KACC >= K orders are
-// held in registers.
-template <int KACC>
-__global__ __launch_bounds__(256) void k_degrid(
-    const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
-    const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
-    const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_chan, int n_corr,
-    uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, double cell_rad, int n_items,
-    const float2* __restrict__ gg, float2* __restrict__ grad_vis, double2* __restrict__ item_gain) {
-    __shared__ float stage[4][64 * (16 + KACC)];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int item = blockIdx.x * (blockDim.x >> 6) + wave;
+// 4. Gather degridding on the matrix cores, the transpose of the tile
+// gridder, over the forward's bins and gridding records (toi_grid of the same
+// snapshot).  One wavefront per 8 x 8 tile holds the tile's plane gradients G
+// (64 cells x 32 columns: the group's orders x Re/Im) as B operands of
+// v_mfma_f32_32x32x2f32 (step i covers cells 2i, 2i + 1; lane l holds
+// G[2i + l / 32][l mod 32]).  The samples an item has in the tile are
+// compacted into LDS (weights at the tile's 8 columns and 8 rows, T_k(s)); per
+// batch of 32 of them 32 steps give H = A G, A[q][cell] the weight of sample
+// q at the cell (A from lane q mod 32 for cell 2i + l / 32).  Then
+// grad x_q += sum_k T_k(s_q) (H[q][k, Re] + i H[q][k, Im]): lane l holds
+// column l mod 32 of rows (r mod 4) + 8 (r / 4) + 4 (l / 32) (hardware
+// layout), multiplies by T and a DPP reduction over each 16-lane row sums the
+// orders; the row's last lane adds the result to the sample's gradient
+// (global float atomics: a sample meets 3.5 tiles on average).
+__global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict__ recs, int n_chan,
+                                                     const DevPlan* __restrict__ P, int M, int NT,
+                                                     const int32_t* __restrict__ bin_off,
+                                                     const int32_t* __restrict__ list, int bin_cap,
+                                                     const int32_t* __restrict__ order,
+                                                     const int32_t* __restrict__ n_active,
+                                                     const float2* __restrict__ gg, float* __restrict__ gx) {
+    typedef float v16 __attribute__((ext_vector_type(16)));
+    __shared__ float sw[64 * 16];      // compacted samples: weights at tile columns 0..7, rows 0..7
+    __shared__ float sT[64 * 16];      // T_{k0 + k}(s), zero for k >= nk
+    __shared__ int sidx[64];           // sample index r * n_chan + c
+    const int tiles = NT * NT;
+    const int lane = threadIdx.x;
+    if (P->status & kStatusFatal) return;
+    const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
+    const int col = lane & 31, pl = col & 15, half = lane >> 5;
+    const int n_bins_active = *n_active;
+    for (int ob = blockIdx.x; ob < n_bins_active; ob += gridDim.x) {
+        const int bid = order[ob];
+        const int g = bid / tiles, tile = bid % tiles;
+        if (g >= P->ng) continue;
+        const int b0 = bin_off[(size_t)g * tiles + tile];
+        const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
+        if (b1 <= b0) continue;
+        int s0, s1, k0, k1;
+        group_range(g, P, s0, s1, k0, k1);   // one slab per group
+        const int nk = k1 - k0;
+        const int tx = tile % NT, ty = tile / NT;
+        // the tile's plane gradients as B operands
+        float gb[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            const int cell = 2 * i + half;
+            float v = 0.f;
+            if (pl < nk) {
+                const float2 gv = gg[((size_t)(s0 * P->K + k0 + pl) * M + ty * kTile + (cell >> 3)) * M + tx * kTile +
+                                     (cell & 7)];
+                v = col < 16 ? gv.x : gv.y;
+            }
+            gb[i] = v;
+        }
+        for (int it = b0; it < b1; ++it) {
+            const int item = list[it];
+            const int c = (item % n_chunks) * kItemChans + lane;
+            bool act = false;
+            int sample = 0;
+            float4 ra = make_float4(0.f, 0.f, 4.f, 4.f), rb = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (c < n_chan) {
+                sample = (item / n_chunks) * n_chan + c;
+                const float4* src = reinterpret_cast<const float4*>(recs + sample);
+                ra = src[0];
+                rb = src[1];
+                const int pk = __float_as_int(ra.x), sp = __float_as_int(ra.y);
+                const int ddx = ((pk & 8191) - tx * kTile) & (M - 1), ddy = (((pk >> 13) & 8191) - ty * kTile) & (M - 1);
+                act = pk >= 0 && sp >= s0 && sp < s1 && (ddx < kTile || ddx >= M - 7) && (ddy < kTile || ddy >= M - 7);
+            }
+            const uint64_t m = __ballot(act);
+            if (m == 0) continue;
+            const int n_act = __popcll(m);
+            if (act) {   // compact: slot = number of active lanes below this one
+                const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+                const int pk = __float_as_int(ra.x);
+                const int ix = pk & 8191, iy = (pk >> 13) & 8191;
+                float4* dw = reinterpret_cast<float4*>(sw + slot * 16);
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    float w4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int i = (h & 1) * 4 + j;
+                        const int d = h < 2 ? (tx * kTile + i - ix) & (M - 1) : (ty * kTile + i - iy) & (M - 1);
+                        w4[j] = d < 8 ? es_kernel(((float)d - (h < 2 ? ra.z : ra.w)) * 0.25f) : 0.f;
+                    }
+                    dw[h] = make_float4(w4[0], w4[1], w4[2], w4[3]);
+                }
+                float4* dt = reinterpret_cast<float4*>(sT + slot * 16);
+                float t, tm1;
+                cheb_start(rb.x, k0, t, tm1);
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    float t4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        t4[j] = 4 * k4 + j < nk ? t : 0.f;
+                        const float tn = 2.f * rb.x * t - tm1;
+                        tm1 = t;
+                        t = tn;
+                    }
+                    dt[k4] = make_float4(t4[0], t4[1], t4[2], t4[3]);
+                }
+                sidx[slot] = sample;
+            }
+            lds_order();                                   // staging writes precede the reads below
+            for (int b = 0; b < n_act; b += 32) {
+                const int qa = b + col;                     // this lane's A row (sample slot)
+                const bool oka = qa < n_act;
+                const float* wq = sw + (oka ? qa : 0) * 16;
+                v16 h = {};
+#pragma unroll
+                for (int i = 0; i < 32; ++i) {              // cells 2i + half: column 2 (i mod 4) + half, row i / 4
+                    const float a = oka ? wq[2 * (i & 3) + half] * wq[8 + (i >> 2)] : 0.f;
+                    h = __builtin_amdgcn_mfma_f32_32x32x2f32(a, gb[i], h, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int q = b + (r & 3) + 8 * (r >> 2) + 4 * half;   // sample slot of this register's row
+                    const bool ok = q < n_act;
+                    float v = ok ? h[r] * sT[q * 16 + pl] : 0.f;
+                    v = dpp_add<0x111, 0xf>(v);
+                    v = dpp_add<0x112, 0xf>(v);
+                    v = dpp_add<0x114, 0xf>(v);
+                    v = dpp_add<0x118, 0xf>(v);             // lane 15 of each 16-lane row: the sum over the orders
+                    if (ok && (lane & 15) == 15) unsafeAtomicAdd(gx + 2 * sidx[q] + (col >> 4), v);
+                }
+            }
+            lds_order();                                   // the reads above precede the next staging writes
+        }
+    }
+}
+
+// 5. Visibility gradients and per-item gain partials from grad x (one
+// wavefront per work item): grad V_k = conj(g_row) W_k (1 - F_k) grad x on the
+// selected correlations; item_gain = sum over the item's channels of
+// conj(y) grad x in FP64 (y the pre-gain weighted sum).
+__global__ __launch_bounds__(256) void k_degrid_finish(const float2* __restrict__ vis, const float* __restrict__ weight,
+                                                       const uint8_t* __restrict__ flag, const int32_t* __restrict__ ant1,
+                                                       const int32_t* __restrict__ ant2, const float2* __restrict__ gains,
+                                                       int n_ant, int n_chan, int n_corr, uint32_t mask, int n_items,
+                                                       const float2* __restrict__ gxv, float2* __restrict__ grad_vis,
+                                                       double2* __restrict__ item_gain) {
+    const int lane = threadIdx.x & 63;
+    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (item >= n_items) return;
-    float* sw = stage[wave];         // [64][16]: wx[0..7], wy[0..7]
-    float* sT = sw + 64 * 16;        // [64][KACC]: T_k(s)
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int r = item / n_chunks;
     const int c = (item % n_chunks) * kItemChans + lane;
     const bool live = c < n_chan;
     const size_t base = ((size_t)r * n_chan + (live ? c : 0)) * n_corr;
-    float gxr = 0.f, gxi = 0.f, yr = 0.f, yi = 0.f;
-    float w = 0.f;
-    if (live) w = sample_value(vis, weight, flag, base, n_corr, mask, yr, yi);
-    const bool act = live && w > 0.f && !(P->status & kStatusFatal);
-    int pk = 0, p = 0;
-    float s = 0.f, ox = 4.f, oy = 4.f;
-    if (act) {
-        const Track trk = row_track(uvw, r, P, M, cell_rad);
-        const double nu = freq[c];
-        if (mode == 3 && P->dr3 > 0.0) {
-            const double r3 = trk.a3 * nu;
-            p = slab_index(r3, P);
-            s = (float)((r3 - (P->r3min + (2 * p + 1) * P->dr3)) / P->dr3);
-        }
-        const double X = 0.5 * M + trk.ax * nu, Y = 0.5 * M + trk.ay * nu;
-        const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
-        pk = ((int)fx0 & (M - 1)) | (((int)fy0 & (M - 1)) << 13);   // footprint start, M <= 8192
-        ox = (float)(X - fx0);
-        oy = (float)(Y - fy0);
-    }
-    uint64_t pending = __ballot(act);
-    if (pending) {
-        {
-            float wv[16];
-#pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                wv[d] = es_kernel(((float)d - ox) * 0.25f);
-                wv[8 + d] = es_kernel(((float)d - oy) * 0.25f);
-            }
-            float4* d4 = reinterpret_cast<float4*>(sw + lane * 16);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) d4[v] = make_float4(wv[4 * v], wv[4 * v + 1], wv[4 * v + 2], wv[4 * v + 3]);
-            float tv[KACC];
-            float t = 1.f, tm1 = s;   // T_0, T_{-1} = T_1
-#pragma unroll
-            for (int k = 0; k < KACC; ++k) {
-                tv[k] = t;
-                const float tn = 2.f * s * t - tm1;
-                tm1 = t;
-                t = tn;
-            }
-            float4* t4 = reinterpret_cast<float4*>(sT + lane * KACC);
-#pragma unroll
-            for (int v = 0; v < KACC / 4; ++v) t4[v] = make_float4(tv[4 * v], tv[4 * v + 1], tv[4 * v + 2], tv[4 * v + 3]);
-        }
-        lds_order();                       // staging writes precede the walk's reads
-        const int K = P->K;
-        const size_t MM = (size_t)M * M;
-        const int ax = lane & 7, ay = lane >> 3;
-        int cur_pk = -1, cur_p = -1;
-        float gre[KACC], gim[KACC];
-#pragma unroll
-        for (int k = 0; k < KACC; ++k) { gre[k] = 0.f; gim[k] = 0.f; }
-        while (pending) {
-            const int q = __ffsll((unsigned long long)pending) - 1;
-            pending &= pending - 1;
-            const int qpk = __builtin_amdgcn_readlane(pk, q), qp = __builtin_amdgcn_readlane(p, q);
-            const int qx = qpk & 8191, qy = qpk >> 13;
-            const int dx = (ax - qx) & 7, dy = (ay - qy) & 7;
-            if (qpk != cur_pk || qp != cur_p) {     // wave-uniform: reload this lane's cell
-                const int cx = (qx + dx) & (M - 1), cy = (qy + dy) & (M - 1);
-                const float2* src = gg + (size_t)qp * K * MM + (size_t)cy * M + cx;
-#pragma unroll
-                for (int k = 0; k < KACC; ++k) {
-                    const float2 v = k < K ? src[k * MM] : make_float2(0.f, 0.f);
-                    gre[k] = v.x;
-                    gim[k] = v.y;
-                }
-                cur_pk = qpk;
-                cur_p = qp;
-            }
-            const float wq = sw[q * 16 + dx] * sw[q * 16 + 8 + dy];
-            const float4* tq = reinterpret_cast<const float4*>(sT + q * KACC);
-            float hr = 0.f, hi = 0.f;
-#pragma unroll
-            for (int v = 0; v < KACC / 4; ++v) {
-                const float4 t4 = tq[v];
-                hr += t4.x * gre[4 * v] + t4.y * gre[4 * v + 1] + t4.z * gre[4 * v + 2] + t4.w * gre[4 * v + 3];
-                hi += t4.x * gim[4 * v] + t4.y * gim[4 * v + 1] + t4.z * gim[4 * v + 2] + t4.w * gim[4 * v + 3];
-            }
-            const float Hr = wave_total(wq * hr), Hi = wave_total(wq * hi);
-            if (lane == q) {
-                gxr = Hr;
-                gxi = Hi;
-            }
-        }
+    float yr = 0.f, yi = 0.f, gxr = 0.f, gxi = 0.f;
+    if (live) {
+        (void)sample_value(vis, weight, flag, base, n_corr, mask, yr, yi);
+        const float2 g = gxv[(size_t)r * n_chan + c];
+        gxr = g.x;
+        gxi = g.y;
     }
     // visibility gradients: conj(g_row) W_k (1 - F_k) grad x on the selected correlations
     const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
@@ -473,22 +522,18 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
     }
     const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;
     const int n_items = s.n_row * n_chunks;
-#define TOI_DEGRID(KA)                                                                                       \
-    hipLaunchKernelGGL((k_degrid<KA>), dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw,                \
-                       (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2, (const float2*)s.gains,   \
-                       p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M, cell, n_items, c->grid,     \
-                       grad_vis, grad_gains ? c->item_gain : nullptr)
     if (n_items > 0) {
-        if (c->kmax <= 4)
-            TOI_DEGRID(4);
-        else if (c->kmax <= 8)
-            TOI_DEGRID(8);
-        else if (c->kmax <= 16)
-            TOI_DEGRID(16);
-        else
-            TOI_DEGRID(32);
+        const int NT = c->NT;
+        const size_t n_samp = (size_t)s.n_row * p.n_chan;
+        hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, reinterpret_cast<float*>(c->gx),
+                           2 * n_samp);
+        hipLaunchKernelGGL(k_degrid_tiles, dim3(std::min(c->NG_max * NT * NT, kDegridWorkgroups)), dim3(64), 0,
+                           c->stream, c->recs, p.n_chan, c->plan, M, NT, c->bin_off, c->bin_list, c->bin_cap,
+                           c->bin_order, c->scratch_i, c->grid, reinterpret_cast<float*>(c->gx));
+        hipLaunchKernelGGL(k_degrid_finish, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, (const float2*)s.vis,
+                           s.weight, s.flag, s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr,
+                           p.corr_mask, n_items, c->gx, grad_vis, grad_gains ? c->item_gain : nullptr);
     }
-#undef TOI_DEGRID
     if (grad_gains)
         hipLaunchKernelGGL(k_gain_grad, dim3(p.n_ant), dim3(256), 0, c->stream, c->item_gain, n_items, n_chunks,
                            s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, grad_gains);

@@ -37,7 +37,7 @@ struct DevPlan {
     int32_t kp;           // Chebyshev orders per group when K > gp
     int32_t parts;        // groups per slab when K > gp (1 otherwise)
     int32_t gp;           // planes per group (LDS pass of the gridder)
-    int32_t max_sg;       // at most this many slabs share a group (1: matrix-core gridder)
+    int32_t max_sg;       // at most this many slabs share a group (1: the gridders and the adjoint rely on it)
     int32_t pad2_[2];
 };
 
@@ -89,7 +89,7 @@ inline GridShape grid_shape(int tuning, int kmax) {
         g.kacc = gridder_kacc(kmax, g.gp);
     }
     if (!g.mfma && g.threads == 64) g.threads = (tuning & kTuneWide) ? 1024 : 512;
-    g.max_sg = g.mfma ? 1 : g.gp;
+    g.max_sg = 1;   // one slab per plane group (the adjoint gather relies on it)
     g.lds_bytes = gridder_lds(g.gp, g.threads, g.kacc, g.mfma);
     return g;
 }
@@ -143,6 +143,7 @@ struct toi_ctx {
     int n_items_max;      // work items capacity (n_row_max * chunks)
     toi::ItemBox* items;  // [n_items_max]
     toi::SampleRec* recs; // [n_row_max][n_chan] gridding records
+    float2* gx;           // [n_row_max][n_chan] adjoint: gradient of each sample's value
     int32_t* bin_count;   // [NG_max][NT*NT]
     int32_t* bin_off;     // [NG_max][NT*NT + 1]
     int32_t* bin_cursor;  // [NG_max][NT*NT]
