@@ -489,11 +489,11 @@ __global__ __launch_bounds__(256) void k_gain_grad(const double2* __restrict__ i
     if (threadIdx.x == 0) grad_gains[a] = make_float2((float)sr, (float)si);
 }
 
-template <int M, int E>
+template <int M, int E, int EC>   // row-pass and column-pass radices
 static void launch_adj_ffts(toi_ctx* c) {
     constexpr int B = (M >= 8192) ? 2 : 4;
     const float cell = (float)(c->p.cell_deg * kPi / 180.0);
-    hipLaunchKernelGGL((k_adj_cols<M, E>), dim3(M / 2), dim3(M / E), 0, c->stream, c->adj_tp, c->hbuf, c->twiddle,
+    hipLaunchKernelGGL((k_adj_cols<M, EC>), dim3(M / 2), dim3(M / EC), 0, c->stream, c->adj_tp, c->hbuf, c->twiddle,
                        c->corr, c->plan, cell, c->p.mode);
     const int nbands = M / B;
     hipLaunchKernelGGL((k_adj_rows<M, E, B>), dim3(nbands * c->P_cap), dim3(M / E), 0, c->stream, c->hbuf, c->grid,
@@ -510,14 +510,14 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
     hipLaunchKernelGGL(k_reproject_adj, dim3((N + kRaTile - 1) / kRaTile, (N + kRaTile - 1) / kRaTile), dim3(256), 0,
                        c->stream, grad_image, c->adj_tp, c->plan, N, cell);
     switch (M) {
-        case 64: launch_adj_ffts<64, 8>(c); break;
-        case 128: launch_adj_ffts<128, 8>(c); break;
-        case 256: launch_adj_ffts<256, 16>(c); break;
-        case 512: launch_adj_ffts<512, 16>(c); break;
-        case 1024: launch_adj_ffts<1024, 16>(c); break;
-        case 2048: launch_adj_ffts<2048, 16>(c); break;
-        case 4096: launch_adj_ffts<4096, 16>(c); break;
-        case 8192: launch_adj_ffts<8192, 32>(c); break;
+        case 64: launch_adj_ffts<64, 8, 8>(c); break;
+        case 128: launch_adj_ffts<128, 8, 8>(c); break;
+        case 256: launch_adj_ffts<256, 16, 16>(c); break;
+        case 512: launch_adj_ffts<512, 16, 16>(c); break;
+        case 1024: launch_adj_ffts<1024, 16, 16>(c); break;
+        case 2048: launch_adj_ffts<2048, 16, 16>(c); break;
+        case 4096: launch_adj_ffts<4096, 16, 16>(c); break;
+        case 8192: launch_adj_ffts<8192, 32, 32>(c); break;
         default: return hipErrorInvalidValue;
     }
     const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;

@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src
     for (int i = ty; i < 32; i += 8) dst[(size_t)(bx + i) * N + by + tx] = tile[tx][i];
 }
 
-template <int M, int E>
+template <int M, int E, int EC>   // row-pass and column-pass radices
 static hipError_t launch_fft_passes(toi_ctx* c) {
     constexpr int B = (M >= 8192) ? 2 : 4;
     const int nbands = M / B;
@@ -245,7 +245,7 @@ static hipError_t launch_fft_passes(toi_ctx* c) {
     const float cell = (float)(c->p.cell_deg * kPi / 180.0);
     StageTimer timer(c, TOI_STAGE_FFT_COLS);
     const int words = (c->NT + 31) / 32;
-    hipLaunchKernelGGL((k_fft_cols<M, E>), dim3(M / 2), dim3(M / E), c->NG_max * words * sizeof(uint32_t),
+    hipLaunchKernelGGL((k_fft_cols<M, EC>), dim3(M / 2), dim3(M / EC), c->NG_max * words * sizeof(uint32_t),
                        c->stream, c->hbuf, c->tplane_t, c->twiddle, c->corr, c->plan, cell, c->p.mode, c->row_bits,
                        c->NG_max);
     return hipGetLastError();
@@ -254,14 +254,14 @@ static hipError_t launch_fft_passes(toi_ctx* c) {
 hipError_t launch_image(toi_ctx* c, float* image_out, float* tplane_out) {
     hipError_t e;
     switch (c->M) {
-        case 64: e = launch_fft_passes<64, 8>(c); break;
-        case 128: e = launch_fft_passes<128, 8>(c); break;
-        case 256: e = launch_fft_passes<256, 16>(c); break;
-        case 512: e = launch_fft_passes<512, 16>(c); break;
-        case 1024: e = launch_fft_passes<1024, 16>(c); break;
-        case 2048: e = launch_fft_passes<2048, 16>(c); break;
-        case 4096: e = launch_fft_passes<4096, 16>(c); break;
-        case 8192: e = launch_fft_passes<8192, 32>(c); break;
+        case 64: e = launch_fft_passes<64, 8, 8>(c); break;
+        case 128: e = launch_fft_passes<128, 8, 8>(c); break;
+        case 256: e = launch_fft_passes<256, 16, 16>(c); break;
+        case 512: e = launch_fft_passes<512, 16, 16>(c); break;
+        case 1024: e = launch_fft_passes<1024, 16, 16>(c); break;
+        case 2048: e = launch_fft_passes<2048, 16, 16>(c); break;
+        case 4096: e = launch_fft_passes<4096, 16, 8>(c); break;
+        case 8192: e = launch_fft_passes<8192, 32, 32>(c); break;
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
