@@ -166,8 +166,13 @@ __device__ inline int block_exclusive_scan(int v, int& total) {
 }
 
 __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__ count, int n_bins,
+                                                     const DevPlan* __restrict__ P, int tiles,
                                                      int32_t* __restrict__ off, int32_t* __restrict__ aux) {
     __shared__ int32_t hist[32];
+    if (blockIdx.x * kScanBlock >= P->ng * tiles) {   // bins of unused plane groups hold no items
+        if (threadIdx.x == 0) aux[64 + blockIdx.x] = 0;
+        return;
+    }
     if (threadIdx.x < 32) hist[threadIdx.x] = 0;
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
     int c[kScanPer], sum = 0;
@@ -217,8 +222,10 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
                                                      int32_t* __restrict__ off, int32_t* __restrict__ cursor,
                                                      int32_t* __restrict__ order, int32_t* __restrict__ aux,
                                                      uint32_t* __restrict__ tile_bits,
-                                                     uint32_t* __restrict__ row_bits) {
+                                                     uint32_t* __restrict__ row_bits,
+                                                     const DevPlan* __restrict__ P) {
     __shared__ int32_t hist[32], start[32];
+    if (blockIdx.x * kScanBlock >= P->ng * NT * NT) return;   // unused plane groups: never read
     if (threadIdx.x < 32) hist[threadIdx.x] = 0;
     __syncthreads();
     const int add = aux[64 + blockIdx.x];
@@ -700,12 +707,13 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
                                (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2,
                                (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M,
                                NT, cell, n_items, c->items, c->recs, c->bin_count);
-        hipLaunchKernelGGL(k_scan_local, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, c->bin_off,
-                           c->bin_aux);
+        hipLaunchKernelGGL(k_scan_local, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, c->plan,
+                           NT * NT, c->bin_off, c->bin_aux);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, n_scan, n_bins, c->bin_cap, c->plan,
                            c->bin_aux, c->bin_off, c->scratch_i);
         hipLaunchKernelGGL(k_scan_apply, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, NT,
-                           c->bin_off, c->bin_cursor, c->bin_order, c->bin_aux, c->tile_bits, c->row_bits);
+                           c->bin_off, c->bin_cursor, c->bin_order, c->bin_aux, c->tile_bits, c->row_bits,
+                           c->plan);
         if (n_items > 0)
             hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, c->items, n_items, NT,
                                c->bin_cap, c->bin_cursor, c->bin_list);
