@@ -21,6 +21,9 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-munsafe-fp-atomics",
+    # matrix-core accumulators in ordinary VGPRs: a loop-carried accumulator
+    # otherwise moves between VGPRs and AGPRs around every inner loop
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-warning-option",

@@ -195,6 +195,8 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
         {(void**)&c->bin_list, (size_t)c->bin_cap * sizeof(int32_t)},
         {(void**)&c->bin_order, NG * NT * NT * sizeof(int32_t)},
         {(void**)&c->bin_aux, (64 + (NG * NT * NT + kScanBlock - 1) / kScanBlock) * sizeof(int32_t)},
+        {(void**)&c->units, (size_t)kSplitSlots * sizeof(int4)},
+        {(void**)&c->split_part, (size_t)kSplitSlots * kPartFloats * sizeof(float)},
         {(void**)&c->tile_bits, NG * NT * words * sizeof(uint32_t)},
         {(void**)&c->row_bits, NG * words * sizeof(uint32_t)},
         {(void**)&c->grid, P * M * M * sizeof(float2)},
@@ -250,7 +252,8 @@ toi_status toi_destroy(toi_ctx* c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
     if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
-    void* ptrs[] = {c->items, c->recs, c->gx, c->bin_order, c->bin_aux, c->bin_count, c->bin_off, c->bin_cursor, c->bin_list, c->tile_bits, c->row_bits,
+    void* ptrs[] = {c->items, c->recs, c->gx, c->bin_order, c->bin_aux, c->units, c->split_part,
+                    c->bin_count, c->bin_off, c->bin_cursor, c->bin_list, c->tile_bits, c->row_bits,
                     c->adj_tp, c->item_gain, c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
                     c->scratch_d, c->scratch_i, c->det_scores, c->det_boxes, c->batch_desc};
     for (void* q : ptrs)

@@ -25,7 +25,6 @@
 
 namespace toi {
 
-constexpr int kDegridWorkgroups = 8192;   // persistent single-wave workgroups
 
 __global__ __launch_bounds__(256) void k_zero_f32(float* __restrict__ p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -298,7 +297,8 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                                                      const int32_t* __restrict__ bin_off,
                                                      const int32_t* __restrict__ list, int bin_cap,
                                                      const int32_t* __restrict__ order,
-                                                     const int32_t* __restrict__ n_active,
+                                                     const int32_t* __restrict__ cnt,
+                                                     const int4* __restrict__ units,
                                                      const float2* __restrict__ gg, float* __restrict__ gx) {
     typedef float v16 __attribute__((ext_vector_type(16)));
     __shared__ float sw[64 * 16];      // compacted samples: weights at tile columns 0..7, rows 0..7
@@ -309,13 +309,16 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
     if (P->status & kStatusFatal) return;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & 31, pl = col & 15, half = lane >> 5;
-    const int n_bins_active = *n_active;
-    for (int ob = blockIdx.x; ob < n_bins_active; ob += gridDim.x) {
-        const int bid = order[ob];
+    // the forward's work units (heavy bins split), heaviest first; normally
+    // one per workgroup, handed out by the dispatcher as waves finish
+    const int n_units = work_unit_count(cnt);
+    for (int ob = blockIdx.x; ob < n_units; ob += gridDim.x) {
+        const WorkUnit un = work_unit(ob, units, order, cnt);
+        const int bid = un.bin;
         const int g = bid / tiles, tile = bid % tiles;
         if (g >= P->ng) continue;
-        const int b0 = bin_off[(size_t)g * tiles + tile];
-        const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
+        int b0, b1;
+        work_unit_items(un, bin_off, bin_cap, b0, b1);
         if (b1 <= b0) continue;
         int s0, s1, k0, k1;
         group_range(g, P, s0, s1, k0, k1);   // one slab per group
@@ -356,18 +359,12 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                 const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
                 const int pk = __float_as_int(ra.x);
                 const int ix = pk & 8191, iy = (pk >> 13) & 8191;
+                float wxy[16];
+                tile_axis_weights(tx * kTile, ix, ra.z, M, wxy);
+                tile_axis_weights(ty * kTile, iy, ra.w, M, wxy + 8);
                 float4* dw = reinterpret_cast<float4*>(sw + slot * 16);
 #pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    float w4[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int i = (h & 1) * 4 + j;
-                        const int d = h < 2 ? (tx * kTile + i - ix) & (M - 1) : (ty * kTile + i - iy) & (M - 1);
-                        w4[j] = d < 8 ? es_kernel(((float)d - (h < 2 ? ra.z : ra.w)) * 0.25f) : 0.f;
-                    }
-                    dw[h] = make_float4(w4[0], w4[1], w4[2], w4[3]);
-                }
+                for (int h = 0; h < 4; ++h) dw[h] = make_float4(wxy[4 * h], wxy[4 * h + 1], wxy[4 * h + 2], wxy[4 * h + 3]);
                 float4* dt = reinterpret_cast<float4*>(sT + slot * 16);
                 float t, tm1;
                 cheb_start(rb.x, k0, t, tm1);
@@ -527,9 +524,10 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
         const size_t n_samp = (size_t)s.n_row * p.n_chan;
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, reinterpret_cast<float*>(c->gx),
                            2 * n_samp);
-        hipLaunchKernelGGL(k_degrid_tiles, dim3(std::min(c->NG_max * NT * NT, kDegridWorkgroups)), dim3(64), 0,
+        const int blocks = unit_workgroups(n_items, c->NG_max * NT * NT);
+        hipLaunchKernelGGL(k_degrid_tiles, dim3(blocks), dim3(64), 0,
                            c->stream, c->recs, p.n_chan, c->plan, M, NT, c->bin_off, c->bin_list, c->bin_cap,
-                           c->bin_order, c->scratch_i, c->grid, reinterpret_cast<float*>(c->gx));
+                           c->bin_order, c->scratch_i, c->units, c->grid, reinterpret_cast<float*>(c->gx));
         hipLaunchKernelGGL(k_degrid_finish, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, (const float2*)s.vis,
                            s.weight, s.flag, s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr,
                            p.corr_mask, n_items, c->gx, grad_vis, grad_gains ? c->item_gain : nullptr);

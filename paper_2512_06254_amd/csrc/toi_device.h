@@ -107,8 +107,25 @@ __device__ inline int xcd_block_id(int bid, int nblk) {
 // hardware square root and base-2 exponential (about 1 ulp each).
 __device__ inline float es_kernel(float z) {
     constexpr float beta_log2e = 18.4f * 1.4426950408889634f;
-    const float a = fmaxf(1.0f - z * z, 0.0f);
-    return __builtin_amdgcn_exp2f(beta_log2e * (__builtin_amdgcn_sqrtf(a) - 1.0f));
+    const float a = fmaxf(__builtin_fmaf(-z, z, 1.0f), 0.0f);
+    return __builtin_amdgcn_exp2f(__builtin_fmaf(beta_log2e, __builtin_amdgcn_sqrtf(a), -beta_log2e));
+}
+
+// Kernel weights of one footprint axis at the eight cells c0 + i (i = 0..7)
+// of an aligned 8-cell tile: footprint start s (cell index), offset o of the
+// sample from s in (3, 4], grid side M (a power of two).  Cell c lies at
+// footprint position d = (c - s) mod M and gets psi((d - o) / 4) for d < 8, 0
+// otherwise.  Computed for all eight cells without branches (the kernel is
+// evaluated everywhere, then masked).
+__device__ inline void tile_axis_weights(int c0, int s, float o, int M, float w[8]) {
+    int b = (c0 - s) & (M - 1);
+    if (b >= (M >> 1)) b -= M;                      // footprint position of cell c0, signed
+    const float z0 = ((float)b - o) * 0.25f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float e = es_kernel(z0 + 0.25f * (float)i);
+        w[i] = (unsigned)(b + i) < 8u ? e : 0.f;
+    }
 }
 
 }  // namespace toi

@@ -100,6 +100,36 @@ __device__ inline void group_range(int g, const DevPlan* __restrict__ P, int& s0
     }
 }
 
+// Work unit ob of the matrix-core tile passes (toi_grid, toi_degrid).  The
+// first cnt[1] units come from the bins listed unit by unit (the heaviest
+// cnt[2] non-empty bins, kUnitItems items per unit); the rest are the other
+// non-empty bins, whole, in their launch order.  Item range [b0, b1) of the
+// bin's list; parts > 1 marks a split bin whose part 0 is unit slot0.
+struct WorkUnit {
+    int bin, part, parts, slot0;
+};
+__device__ inline int work_unit_count(const int32_t* __restrict__ cnt) { return cnt[0] - cnt[2] + cnt[1]; }
+__device__ inline WorkUnit work_unit(int ob, const int4* __restrict__ units, const int32_t* __restrict__ order,
+                                     const int32_t* __restrict__ cnt) {
+    const int n_split = cnt[1];
+    if (ob < n_split) {
+        const int4 u = units[ob];
+        return WorkUnit{u.x, u.y, u.z, u.w};
+    }
+    return WorkUnit{order[cnt[2] + ob - n_split], 0, 1, -1};
+}
+__device__ inline void work_unit_items(const WorkUnit& u, const int32_t* __restrict__ bin_off, int bin_cap, int& b0,
+                                       int& b1) {
+    const int e = min(bin_off[u.bin + 1], bin_cap);
+    b0 = bin_off[u.bin];
+    if (u.parts > 1) {
+        b0 += u.part * kUnitItems;
+        b1 = min(b0 + kUnitItems, e);
+    } else {
+        b1 = e;
+    }
+}
+
 // Chebyshev recurrence T_{k+1} = 2 s T_k - T_{k-1} started at order k0:
 // returns t = T_{k0}(s) and tm1 = T_{k0-1}(s) (T_{-1} = T_1).
 __device__ inline void cheb_start(float s, int k0, float& t, float& tm1) {

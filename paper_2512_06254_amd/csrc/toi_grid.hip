@@ -1,20 +1,23 @@
 // S4: gridding of the Chebyshev moment planes M_{p,k} (Section 3.4) with an
 // exponential-of-semicircle kernel of support 8 on a periodic 2N x 2N grid.
 //
-// Tile-owner design, no global float atomics:
+// Tile-owner design, no float atomics on the grid:
 //  1. Work items are runs of kItemChans channels of one row.  A row's samples
 //     lie on a radial track (b = uvw nu / c), so an item's 8 x 8 footprints
-//     cover a small box; k_items computes the box and the slabs it touches and
-//     counts the item into every (plane group, 32 x 32 tile) bin it overlaps.
+//     cover a small box; k_items computes the box and the slabs it touches,
+//     counts the item into every (plane group, 8 x 8 tile) bin it overlaps and
+//     writes each sample's gridding record (cell, offsets, slab, value).
 //  2. k_scan_local / k_scan_top / k_scan_apply turn the counts into list
-//     offsets, a heaviest-first launch order and occupancy bit masks;
+//     offsets, a heaviest-first launch order and occupancy bit masks; k_units
+//     splits the heaviest bins into work units of at most kUnitItems items;
 //     k_bin_fill writes the item lists.
-//  3. k_grid_tiles: one workgroup per (group, tile) accumulates the tile's
-//     planes in LDS and writes it to HBM once.  Inside a workgroup each
-//     wavefront walks one item at a time: lane (i, j) owns the cells with
-//     x = i, y = j (mod 8), exactly one of which lies in every footprint, and
-//     keeps that cell's plane values in registers until the track moves it
-//     (Romein, ICS 2012), then adds them to LDS.
+//  3. k_grid_tiles_mfma (default): one wavefront per work unit keeps the whole
+//     tile in matrix-core accumulators and writes it to HBM once (the units of
+//     a split bin add their partial tiles in a fixed order first).
+//     k_grid_tiles (vector ALU): one workgroup per bin accumulates the tile's
+//     planes in LDS; each wavefront walks one item at a time with lane (i, j)
+//     owning the cells x = i, y = j (mod 8) of the footprints (Romein, ICS
+//     2012).
 // Tiles without samples are never written; the FFT passes read the
 // occupancy masks and treat them as zero.
 //
@@ -274,6 +277,51 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
     }
 }
 
+// Work units of the matrix-core passes (one workgroup): the bins of buckets
+// kUnitShift and up (at least kUnitItems items; the first entries of the launch
+// order) are listed unit by unit, ceil(count / kUnitItems) units each, as long
+// as the units fit in kSplitSlots; from the first bin that does not fit on,
+// bins run whole.  cnt[1] = units listed, cnt[2] = bins they cover.
+__global__ __launch_bounds__(1024) void k_units(const int32_t* __restrict__ count, const int32_t* __restrict__ order,
+                                                const int32_t* __restrict__ aux, int4* __restrict__ units,
+                                                int32_t* __restrict__ cnt) {
+    __shared__ int cut_i, cut_p;
+    int n_big = 0;
+    for (int k = kUnitShift; k < 32; ++k) n_big += aux[k];
+    int carry = 0, n_fit = n_big;
+    for (int i0 = 0; i0 < n_big; i0 += 1024) {
+        const int i = i0 + (int)threadIdx.x;
+        int bin = 0, u = 0;
+        if (i < n_big) {
+            bin = order[i];
+            u = (count[bin] + kUnitItems - 1) / kUnitItems;
+        }
+        int total;
+        const int p0 = carry + block_exclusive_scan(u, total);   // barriers inside
+        if (threadIdx.x == 0) cut_i = INT_MAX;
+        __syncthreads();
+        const bool over = i < n_big && p0 + u > kSplitSlots;
+        if (over) atomicMin(&cut_i, i);
+        __syncthreads();
+        const int cut = cut_i;
+        if (i == cut) cut_p = p0;
+        if (i < n_big && i < cut) {
+            for (int p = 0; p < u; ++p) units[p0 + p] = make_int4(bin, p, u, p0);
+        }
+        __syncthreads();
+        if (cut != INT_MAX) {   // the rest runs whole
+            n_fit = cut;
+            carry = cut_p;
+            break;
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        cnt[1] = carry;
+        cnt[2] = n_fit;
+    }
+}
+
 // ---------------------------------------------------------------- 2b. fill
 __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ items, int n_items, int NT,
                                                   int bin_cap, int32_t* __restrict__ cursor,
@@ -521,7 +569,6 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
 }
 
 // ------------------------------------------------- 3b. tiles, matrix cores
-constexpr int kMfmaWorkgroups = 8192;   // 32 single-wave workgroups per CU
 constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
 
 // Matrix-core gridder.  Tiles are 8 x 8 cells, one v_mfma block: the tile's
@@ -546,7 +593,8 @@ template <int NCOL>
 __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     const SampleRec* __restrict__ recs, int n_chan, const DevPlan* __restrict__ P, int M, int NT,
     const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
-    const int32_t* __restrict__ order, const int32_t* __restrict__ n_active, float2* __restrict__ grid) {
+    const int32_t* __restrict__ order, const int32_t* __restrict__ cnt, const int4* __restrict__ units,
+    float* __restrict__ split_part, float2* __restrict__ grid) {
     static_assert(NCOL == 16 || NCOL == 32, "one 16- or 32-column matrix block");
     static_assert(kTile == 8, "a tile is one 64-row matrix block");
     constexpr int NREG = NCOL;                 // accumulator registers per lane (64 x NCOL / 64)
@@ -560,16 +608,17 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     const int lane = threadIdx.x;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & (NCOL - 1);
-    // non-empty bins in decreasing order of work, dealt round-robin over the
-    // workgroups (the dispatcher spreads consecutive workgroups over the XCDs)
-    const int n_bins_active = *n_active;
-    for (int ob = blockIdx.x; ob < n_bins_active; ob += gridDim.x) {
-    const int bid = order[ob];
+    // work units (heavy bins split) in decreasing order of work; normally one
+    // per workgroup, handed out by the dispatcher as waves finish
+    const int n_units = work_unit_count(cnt);
+    for (int ob = blockIdx.x; ob < n_units; ob += gridDim.x) {
+    const WorkUnit un = work_unit(ob, units, order, cnt);
+    const int bid = un.bin;
     const int g = bid / tiles, tile = bid % tiles;
     if (g >= P->ng) continue;
-    const int b0 = bin_off[(size_t)g * tiles + tile];
-    const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
-    if (b1 <= b0) continue;
+    int b0, b1;
+    work_unit_items(un, bin_off, bin_cap, b0, b1);
+    if (b1 <= b0 && un.parts == 1) continue;   // every unit of a split bin reports in
     int s0, s1, k0, k1;
     group_range(g, P, s0, s1, k0, k1);         // one slab per group (max_sg = 1)
     const int nk = k1 - k0;                    // <= gp <= NPL planes
@@ -590,7 +639,7 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
         }
     };
     float4 ra, rb;
-    load_rec(list[b0], ra, rb);
+    if (b0 < b1) load_rec(list[b0], ra, rb);
     for (int it = b0; it < b1; ++it) {
         const int pk = __float_as_int(ra.x), sp = __float_as_int(ra.y);
         const int ix = pk & 8191, iy = (pk >> 13) & 8191;
@@ -604,18 +653,12 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
         // staging of this lane's sample, written four values at a time
         {
             // weights at the tile's columns / rows i = 0..7 (0 outside the footprint)
+            float wxy[16];
+            tile_axis_weights(tx * kTile, ix, ox, M, wxy);
+            tile_axis_weights(ty * kTile, iy, oy, M, wxy + 8);
             float4* dw = reinterpret_cast<float4*>(sw + lane * 16);
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                float w4[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int i = (h & 1) * 4 + j;
-                    const int d = h < 2 ? (tx * kTile + i - ix) & (M - 1) : (ty * kTile + i - iy) & (M - 1);
-                    w4[j] = d < 8 ? es_kernel(((float)d - (h < 2 ? ox : oy)) * 0.25f) : 0.f;
-                }
-                dw[h] = make_float4(w4[0], w4[1], w4[2], w4[3]);
-            }
+            for (int h = 0; h < 4; ++h) dw[h] = make_float4(wxy[4 * h], wxy[4 * h + 1], wxy[4 * h + 2], wxy[4 * h + 3]);
             // column c: order k0 + c mod NPL of the group's slab, Re (c < NPL) or Im
             float4* dbr = reinterpret_cast<float4*>(sB + lane * NCOL);
             float4* dbi = reinterpret_cast<float4*>(sB + lane * NCOL + NPL);
@@ -678,14 +721,53 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
         wo[(cy * kTile + cx) * (NCOL + 1) + col] = acc[rg];
     }
     lds_order();
-    for (int i = threadIdx.x; i < nk * 64; i += blockDim.x) {
-        const int pl = i / 64, cell = i % 64;
-        const int ly = cell / kTile, lx = cell % kTile;
-        const int pg = s0 * P->K + k0 + pl;    // global plane index
-        const float* e = wo + cell * (NCOL + 1);
-        grid[((size_t)pg * M + ty * kTile + ly) * M + tx * kTile + lx] = make_float2(e[pl], e[NPL + pl]);
+    if (un.parts > 1) {   // a split bin's partial tile [plane][cell], added up by k_split_sum
+        float2* part = reinterpret_cast<float2*>(split_part + (size_t)ob * kPartFloats);
+        for (int i = threadIdx.x; i < nk * 64; i += blockDim.x) {
+            const float* e = wo + (i % 64) * (NCOL + 1);
+            part[i] = make_float2(e[i / 64], e[NPL + i / 64]);
+        }
+    } else {
+        for (int i = threadIdx.x; i < nk * 64; i += blockDim.x) {
+            const int pl = i / 64, cell = i % 64;
+            const int ly = cell / kTile, lx = cell % kTile;
+            const int pg = s0 * P->K + k0 + pl;    // global plane index
+            const float* e = wo + cell * (NCOL + 1);
+            grid[((size_t)pg * M + ty * kTile + ly) * M + tx * kTile + lx] = make_float2(e[pl], e[NPL + pl]);
+        }
     }
     lds_order();                               // the write-out reads precede the next tile's staging writes
+    }
+}
+
+// Tiles of split bins: the partial tiles of a bin's units (consecutive unit
+// slots from part 0) added in part order, written to the grid.  One workgroup
+// per split bin at a time.
+constexpr int kSplitSumWorkgroups = 1024;
+__global__ __launch_bounds__(256) void k_split_sum(const DevPlan* __restrict__ P, int M, int NT,
+                                                   const int4* __restrict__ units, const int32_t* __restrict__ cnt,
+                                                   const float* __restrict__ split_part, float2* __restrict__ grid) {
+    if (P->status & kStatusFatal) return;
+    const int n_split = cnt[1], tiles = NT * NT;
+    for (int ob = blockIdx.x; ob < n_split; ob += gridDim.x) {
+        const int4 u = units[ob];
+        if (u.z <= 1 || u.y != 0) continue;   // whole bins and parts after the first
+        const int g = u.x / tiles, tile = u.x % tiles;
+        if (g >= P->ng) continue;
+        int s0, s1, k0, k1;
+        group_range(g, P, s0, s1, k0, k1);
+        const int nk = k1 - k0, tx = tile % NT, ty = tile / NT;
+        for (int i = threadIdx.x; i < nk * 64; i += blockDim.x) {
+            float2 v = make_float2(0.f, 0.f);
+            for (int p = 0; p < u.z; ++p) {
+                const float2 a = reinterpret_cast<const float2*>(split_part + (size_t)(ob + p) * kPartFloats)[i];
+                v.x += a.x;
+                v.y += a.y;
+            }
+            const int pl = i / 64, cell = i % 64;
+            const int pg = s0 * P->K + k0 + pl;
+            grid[((size_t)pg * M + ty * kTile + cell / kTile) * M + tx * kTile + cell % kTile] = v;
+        }
     }
 }
 
@@ -714,6 +796,8 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
         hipLaunchKernelGGL(k_scan_apply, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, NT,
                            c->bin_off, c->bin_cursor, c->bin_order, c->bin_aux, c->tile_bits, c->row_bits,
                            c->plan);
+        hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->bin_count, c->bin_order, c->bin_aux,
+                           c->units, c->scratch_i);
         if (n_items > 0)
             hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, c->items, n_items, NT,
                                c->bin_cap, c->bin_cursor, c->bin_list);
@@ -728,15 +812,17 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
         c->plan, M, NT, cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
 #define TOI_TILE_LAUNCH(KA) hipLaunchKernelGGL((k_grid_tiles<KA>), TOI_TILE_ARGS)
     if (gs.mfma) {   // a fixed grid of single-wave workgroups takes the non-empty bins in turn
-        const int mblocks = std::min(n_bins, kMfmaWorkgroups);
+        const int mblocks = unit_workgroups(n_items, n_bins);
 #define TOI_MFMA_ARGS                                                                                      \
     dim3(mblocks), dim3(64), gs.lds_bytes, c->stream, c->recs, p.n_chan, c->plan, M, NT, c->bin_off, c->bin_list, \
-        c->bin_cap, c->bin_order, c->scratch_i, c->grid
+        c->bin_cap, c->bin_order, c->scratch_i, c->units, c->split_part, c->grid
         if (gs.gp > 8)
             hipLaunchKernelGGL((k_grid_tiles_mfma<32>), TOI_MFMA_ARGS);
         else
             hipLaunchKernelGGL((k_grid_tiles_mfma<16>), TOI_MFMA_ARGS);
 #undef TOI_MFMA_ARGS
+        hipLaunchKernelGGL(k_split_sum, dim3(kSplitSumWorkgroups), dim3(256), 0, c->stream, c->plan, M, NT, c->units,
+                           c->scratch_i, c->split_part, c->grid);
     } else if (gs.kacc <= 1) {
         TOI_TILE_LAUNCH(1);
     } else if (gs.kacc <= 4) {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -47,6 +48,14 @@ constexpr int kTile = 8, kTileShift = 3;
 constexpr int kItemChans = 64;
 constexpr int kGroupPlanes = 16;   // largest plane group held in LDS
 constexpr int kScanBlock = 4096;   // bins per workgroup of the bin scan
+// Work units of the matrix-core tile passes: a bin of more than kUnitItems
+// items is split into units of at most kUnitItems items (bins of bucket
+// kUnitShift and above are listed unit by unit); the units of one bin add
+// their partial tiles in a fixed order.  At most kSplitSlots listed units per
+// snapshot (bins past that run whole).
+constexpr int kUnitShift = 6, kUnitItems = 1 << kUnitShift;
+constexpr int kSplitSlots = 16384;
+constexpr int kPartFloats = 64 * 32;   // one partial tile: 64 cells x up to 16 complex planes
 
 // Gridder variant chosen by the autotuner (toi_tune / toi_set_tuning):
 // bit 0: matrix-core accumulation (v_mfma; one slab per plane group), else the
@@ -148,8 +157,11 @@ struct toi_ctx {
     int32_t* bin_off;     // [NG_max][NT*NT + 1]
     int32_t* bin_cursor;  // [NG_max][NT*NT]
     int32_t* bin_list;    // [bin capacity]
-    int32_t* bin_order;   // [NG_max][NT*NT] non-empty bins, heaviest first (count in scratch_i[0])
+    int32_t* bin_order;   // [NG_max][NT*NT] non-empty bins, heaviest first (count in scratch_i[0];
+                          // scratch_i[1]: units of split bins, scratch_i[2]: bins listed as units)
     int32_t* bin_aux;     // [32] bucket sizes, [32] bucket cursors, then one total per scan block
+    int4* units;          // [kSplitSlots] listed work units {bin, part, parts, index of part 0}
+    float* split_part;    // [kSplitSlots][kPartFloats] partial tiles of split bins ([plane][cell] complex)
     int bin_cap;
     uint32_t* tile_bits;  // [NG_max][NT][NT/32]  nonempty tiles of each tile row
     uint32_t* row_bits;   // [NG_max][NT/32]      nonempty tile rows
@@ -206,6 +218,15 @@ struct StageTimer {
     StageTimer(toi_ctx* ctx, int stage);
     ~StageTimer();
 };
+
+// Single-wave workgroups launched for the matrix-core tile passes: about one
+// per expected work unit (a bin holds some 12 items, an item meets some 5
+// tiles), so the hardware dispatcher hands the units out as waves finish;
+// each workgroup loops if there are more units.
+inline int unit_workgroups(int n_items, int n_bins) {
+    const long want = std::max<long>(8192, n_items / 2);
+    return (int)std::min<long>(std::min<long>(want, 1 << 20), (long)n_bins + kSplitSlots);
+}
 
 // host-side tables (toi_ctx.cpp)
 void es_correction_table(int N, int M, double* out);   // (-1)^a / psi(a)

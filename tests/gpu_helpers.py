@@ -7,6 +7,34 @@ from oracle import toi as O
 
 IMAGE_TOL = 1e-4        # max |delta| <= 1e-4 of the image peak (FP32 vs the FP64 oracle)
 
+# A compact array seen on a small grid: many work items share each 8 x 8 tile,
+# so the heaviest bins are split into several work units.
+DENSE = dict(n_ant=32, diameter_m=300.0, sigma_h_m=20.0, n_chan=128, n_pix=64, cell_arcsec=60.0)
+
+
+def items_per_bin(wl, snap_index=0):
+    """Work items (runs of 64 channels of one row) counted into every 8 x 8
+    tile their footprints overlap, all channels counted as kept (host-side
+    estimate of the gridder's bins, from the oracle's basis)."""
+    enu = S.antenna_enu(wl)
+    uvw = S.snapshot_uvw(wl, snap_index, enu)
+    freq = S.channel_freqs(wl)
+    b = (uvw[:, None, :] * (freq[None, :, None] / O.C_LIGHT)).reshape(-1, 3)
+    V = O.snapshot_basis(b).V
+    M = 2 * wl.n_pix
+    r = uvw @ V.T
+    ix = np.ceil(M / 2 - r[:, 0:1] * freq[None, :] / O.C_LIGHT * M * wl.cell_rad - 4).astype(int)
+    iy = np.ceil(M / 2 + r[:, 1:2] * freq[None, :] / O.C_LIGHT * M * wl.cell_rad - 4).astype(int)
+    NT = M // 8
+    cnt = np.zeros((NT, NT), int)
+    for row in range(ix.shape[0]):
+        for c0 in range(0, wl.n_chan, 64):
+            xs, ys = ix[row, c0:c0 + 64], iy[row, c0:c0 + 64]
+            for ty in range(ys.min() >> 3, ((ys.max() + 7) >> 3) + 1):
+                for tx in range(xs.min() >> 3, ((xs.max() + 7) >> 3) + 1):
+                    cnt[ty % NT, tx % NT] += 1
+    return cnt
+
 
 def run_gpu(snap, n_pix, cell_deg, *, mode=3, n_slab=0, cheb_k=0, max_planes=0, tile=32, n_ant=0,
             corr_mask=0):

@@ -7,13 +7,17 @@ import synth_inputs as S
 from oracle import adjoint as A
 from oracle import toi as O
 
+from gpu_helpers import DENSE, items_per_bin
+
 pytestmark = pytest.mark.gpu
 
 
-def _setup(n_slab=1, K=8, flags=True, gains=True, n_pix=64, seed=0):
-    wl = S.scaled(S.WORKLOADS["adjoint"], n_ant=8, n_chan=40, n_pix=n_pix, n_steady=4, cell_arcsec=60.0,
-                  diameter_m=2000.0, sigma_h_m=40.0, flag_frac_max=0.3 if flags else 0.0, with_gains=gains,
-                  seed=seed)
+def _setup(n_slab=1, K=8, flags=True, gains=True, n_pix=64, seed=0, dense=False):
+    shape = dict(n_ant=8, n_chan=40, n_pix=n_pix, cell_arcsec=60.0, diameter_m=2000.0, sigma_h_m=40.0)
+    if dense:
+        shape.update(DENSE)
+    wl = S.scaled(S.WORKLOADS["adjoint"], n_steady=4, flag_frac_max=0.3 if flags else 0.0, with_gains=gains,
+                  seed=seed, **shape)
     snap = S.make_snapshot(wl, 0)
     return wl, snap
 
@@ -25,11 +29,13 @@ def _imager(wl, snap, n_slab, K):
                     n_ant=0 if snap.get("gains") is None else wl.n_ant, max_planes=32)
 
 
-@pytest.mark.parametrize("n_slab,K", [(1, 8), (2, 4), (1, 16)])
-def test_adjoint_matches_oracle(n_slab, K):
+@pytest.mark.parametrize("n_slab,K,dense", [(1, 8, False), (2, 4, False), (1, 16, False), (1, 16, True)])
+def test_adjoint_matches_oracle(n_slab, K, dense):
     import torch
     from paper_2512_06254_amd import toi as T
-    wl, snap = _setup()
+    wl, snap = _setup(dense=dense)
+    if dense:   # heavy bins: the gather runs over the forward's split work units
+        assert items_per_bin(wl).max() > 2 * 64
     op = A.SnapshotOperator(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=n_slab, K=K)
     rng = np.random.default_rng(3)
     y = rng.normal(size=(wl.n_pix, wl.n_pix))

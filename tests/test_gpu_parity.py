@@ -8,7 +8,7 @@ import synth_inputs as S
 from oracle import fitrig as F
 from oracle import toi as O
 
-from gpu_helpers import IMAGE_TOL, check_snapshot, max_rel_err, run_gpu
+from gpu_helpers import DENSE, IMAGE_TOL, check_snapshot, items_per_bin, max_rel_err, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -131,5 +131,25 @@ def test_every_gridder_variant_matches_oracle(ns, k):
         img, tp = im.image(tplane=True)
         e = max_rel_err(tp.cpu().numpy(), ref.tplane)
         print(f"[variant {v} ({ns},{k})] t-plane err {e:.3e}", flush=True)
+        assert e <= IMAGE_TOL
+    im.close()
+
+
+def test_dense_bins_split_into_work_units():
+    # bins of up to ~190 items: the matrix-core gridder splits them into
+    # units of 64 items whose partial tiles are added in a fixed order
+    from paper_2512_06254_amd import toi as T
+    wl = S.scaled(S.WORKLOADS["tiny"], **DENSE)
+    assert items_per_bin(wl).max() > 2 * 64
+    snap = S.make_snapshot(wl, 0)
+    ref = O.image_snapshot(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=16)
+    im = T.Imager(wl.n_pix, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=1, cheb_k=16)
+    d = T.to_device(snap)
+    for v in (1, 0, 1):   # matrix cores, vector ALU (whole bins), matrix cores again (unit counters reset)
+        im.set_tuning(v)
+        im.grid(d)
+        img, tp = im.image(tplane=True)
+        e = max_rel_err(tp.cpu().numpy(), ref.tplane)
+        print(f"[dense bins, variant {v}] t-plane err {e:.3e}", flush=True)
         assert e <= IMAGE_TOL
     im.close()
