@@ -588,7 +588,9 @@ constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
 // k_items (cell, offsets, slab, Chebyshev argument, g x); each next item's
 // records are loaded during the current walk.  LDS: staging of the item's 64
 // samples (kernel weights at the tile's eight columns and eight rows, zero
-// outside the footprint, and the NCOL B values), then the write-out buffer.
+// outside the footprint, the NPL Chebyshev values and g x; B = T_k Re/Im(g x)
+// is formed in the walk, which keeps the staging at 8.5 KB per wave), then the
+// write-out buffer.
 template <int NCOL>
 __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     const SampleRec* __restrict__ recs, int n_chan, const DevPlan* __restrict__ P, int M, int NT,
@@ -603,8 +605,9 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     extern __shared__ float lds[];
     const int tiles = NT * NT;
     if (P->status & kStatusFatal) return;
-    float* sw = lds;                           // [64][16] footprint weights
-    float* sB = lds + 64 * 16;                 // [64][NCOL] B values
+    float* sw = lds;                           // [64][16] kernel weights at the tile's columns, rows
+    float* sT = lds + 64 * 16;                 // [64][NPL] T_{k0 + k}(s), 0 for k >= nk
+    float* sV = sT + 64 * NPL;                 // [64][2] Re, Im of g x
     const int lane = threadIdx.x;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & (NCOL - 1);
@@ -659,9 +662,8 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
             float4* dw = reinterpret_cast<float4*>(sw + lane * 16);
 #pragma unroll
             for (int h = 0; h < 4; ++h) dw[h] = make_float4(wxy[4 * h], wxy[4 * h + 1], wxy[4 * h + 2], wxy[4 * h + 3]);
-            // column c: order k0 + c mod NPL of the group's slab, Re (c < NPL) or Im
-            float4* dbr = reinterpret_cast<float4*>(sB + lane * NCOL);
-            float4* dbi = reinterpret_cast<float4*>(sB + lane * NCOL + NPL);
+            // Chebyshev values T_{k0 + k}(s) of the group's orders, and g x
+            float4* dt = reinterpret_cast<float4*>(sT + lane * NPL);
             float t, tm1;
             cheb_start(ss, k0, t, tm1);
 #pragma unroll
@@ -674,38 +676,43 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
                     tm1 = t;
                     t = tn;
                 }
-                dbr[k4] = make_float4(tr[0] * vr, tr[1] * vr, tr[2] * vr, tr[3] * vr);
-                dbi[k4] = make_float4(tr[0] * vi, tr[1] * vi, tr[2] * vi, tr[3] * vi);
+                dt[k4] = make_float4(tr[0], tr[1], tr[2], tr[3]);
             }
+            reinterpret_cast<float2*>(sV)[lane] = make_float2(vr, vi);
         }
         lds_order();                                        // staging writes precede the walk's reads
-        const float* wa_l = sw + (lane & 7);                // this lane's A cell (lane mod 8, lane / 8)
+        // this lane's operands: A = weight of cell (lane mod 8, lane / 8);
+        // B = column c = lane mod NCOL: order k0 + c mod NPL, Re (c < NPL) or Im
+        const float* wa_l = sw + (lane & 7);
         const float* wb_l = sw + 8 + (lane >> 3);
-        const float* b_l = sB + col;
+        const float* t_l = sT + (col % NPL);
+        const float* v_l = sV + (col / NPL);
         // software-pipelined walk (two operand sets in turn): the next
         // sample's operands are read from LDS while the current outer product
         // runs
-        auto take = [&](float& xa, float& xb, float& xc) __attribute__((always_inline)) {
+        struct Ops { float wa, wb, t, v; };
+        auto take = [&](Ops& o) __attribute__((always_inline)) {
             const int q = pending ? __ffsll((unsigned long long)pending) - 1 : 0;   // slot 0 past the end
             pending &= pending - 1;
-            xa = wa_l[q * 16];
-            xb = wb_l[q * 16];
-            xc = b_l[q * NCOL];
+            o.wa = wa_l[q * 16];
+            o.wb = wb_l[q * 16];
+            o.t = t_l[q * NPL];
+            o.v = v_l[q * 2];
         };
-        auto outer = [&](float xa, float xb, float xc) __attribute__((always_inline)) {
-            if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(xa * xb, xc, acc, 0, 0, 0);
-            else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(xa * xb, xc, acc, 0, 0, 0);
+        auto outer = [&](const Ops& o) __attribute__((always_inline)) {
+            if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(o.wa * o.wb, o.t * o.v, acc, 0, 0, 0);
+            else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(o.wa * o.wb, o.t * o.v, acc, 0, 0, 0);
         };
-        float a0, b0, c0, a1, b1, c1;
-        take(a0, b0, c0);
+        Ops o0, o1;
+        take(o0);
         while (true) {                                      // the reads run unconditionally, so the
             const bool m1 = pending != 0;                   // LDS counter state is the same on every path
-            take(a1, b1, c1);
-            outer(a0, b0, c0);
+            take(o1);
+            outer(o0);
             if (!m1) break;
             const bool m2 = pending != 0;
-            take(a0, b0, c0);
-            outer(a1, b1, c1);
+            take(o0);
+            outer(o1);
             if (!m2) break;
         }
         lds_order();                                        // the walk's reads precede the next staging writes

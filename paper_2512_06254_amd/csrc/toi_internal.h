@@ -80,8 +80,8 @@ inline int gridder_kacc(int kmax, int gp) {
     return k <= 1 ? 1 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
 }
 inline size_t gridder_lds(int gp, int threads, int kacc, bool mfma) {
-    if (mfma) {   // staging [64][16 + 2 gp], then reused as the write-out buffer [64][2 gp + 1]
-        const size_t stage = (size_t)64 * (16 + 2 * gp), wout = (size_t)64 * (2 * gp + 1);
+    if (mfma) {   // staging [64][16 + gp + 2], then reused as the write-out buffer [64][2 gp + 1]
+        const size_t stage = (size_t)64 * (16 + gp + 2), wout = (size_t)64 * (2 * gp + 1);
         return (stage > wout ? stage : wout) * sizeof(float);
     }
     (void)kacc;
