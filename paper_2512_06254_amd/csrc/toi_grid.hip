@@ -586,13 +586,13 @@ constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
 // 2 (r / 4) + l / 32) (NCOL = 16), column l mod NCOL (hardware output layout).
 // One wavefront per tile.  The samples come as gridding records written by
 // k_items (cell, offsets, slab, Chebyshev argument, g x); each next item's
-// records are loaded during the current walk.  LDS: staging of the item's 64
-// samples (kernel weights at the tile's eight columns and eight rows, zero
-// outside the footprint, the NPL Chebyshev values and g x; B = T_k Re/Im(g x)
-// is formed in the walk, which keeps the staging at 8.5 KB per wave), then the
-// write-out buffer.
+// records are loaded during the current walk.  LDS: staging of the item's
+// active samples, compacted (kernel weights at the tile's eight columns and
+// eight rows, zero outside the footprint, the NPL Chebyshev values and g x; B =
+// T_k Re/Im(g x) is formed in the walk, which keeps the staging at 8.5 KB per
+// wave), then the write-out buffer.
 template <int NCOL>
-__global__ __launch_bounds__(64) void k_grid_tiles_mfma(
+__global__ __launch_bounds__(64, 5) void k_grid_tiles_mfma(
     const SampleRec* __restrict__ recs, int n_chan, const DevPlan* __restrict__ P, int M, int NT,
     const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
     const int32_t* __restrict__ order, const int32_t* __restrict__ cnt, const int4* __restrict__ units,
@@ -605,9 +605,15 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
     extern __shared__ float lds[];
     const int tiles = NT * NT;
     if (P->status & kStatusFatal) return;
-    float* sw = lds;                           // [64][16] kernel weights at the tile's columns, rows
-    float* sT = lds + 64 * 16;                 // [64][NPL] T_{k0 + k}(s), 0 for k >= nk
-    float* sV = sT + 64 * NPL;                 // [64][2] Re, Im of g x
+    // staging rows of 64 sample slots (the item's active samples, compacted);
+    // four consecutive slots are one 16-byte read.  Rows that different lanes
+    // of one read access (x weights, Chebyshev values) are padded to 68
+    // floats so that they fall in different banks.
+    // (A read of slots 64 .. 67 of a 64-float row lands in the next region.)
+    float* sx = lds;                           // 8 rows x 68: kernel weight at tile column i
+    float* sy = sx + 8 * 68;                   // 8 rows x 64: kernel weight at tile row i
+    float* sV = sy + 8 * 64;                   // 2 rows x 64: Re, Im of g x
+    float* sT = sV + 2 * 64;                   // NPL rows x 68: T_{k0 + k}(s), 0 for k >= nk
     const int lane = threadIdx.x;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & (NCOL - 1);
@@ -651,69 +657,72 @@ __global__ __launch_bounds__(64) void k_grid_tiles_mfma(
         const bool act = pk >= 0 && (sp >= s0 && sp < s1) && (ddx < kTile || ddx >= M - 7) &&
                          (ddy < kTile || ddy >= M - 7);
         if (it + 1 < b1) load_rec(list[it + 1], ra, rb);   // prefetch the next item's records
-        uint64_t pending = __ballot(act);
-        if (pending == 0) continue;
-        // staging of this lane's sample, written four values at a time
-        {
+        const uint64_t amask = __ballot(act);
+        if (amask == 0) continue;
+        // the active samples take slots 0 .. n_act - 1; the walk takes four
+        // slots at a time, so up to three inactive lanes fill the slots up to
+        // n4 with zeros
+        const int n_act = __popcll(amask), n4 = (n_act + 3) & ~3;
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(amask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)amask, 0));
+        const int q = act ? below : n_act + (lane - below);
+        if (q < n4) {
             // weights at the tile's columns / rows i = 0..7 (0 outside the footprint)
             float wxy[16];
             tile_axis_weights(tx * kTile, ix, ox, M, wxy);
             tile_axis_weights(ty * kTile, iy, oy, M, wxy + 8);
-            float4* dw = reinterpret_cast<float4*>(sw + lane * 16);
 #pragma unroll
-            for (int h = 0; h < 4; ++h) dw[h] = make_float4(wxy[4 * h], wxy[4 * h + 1], wxy[4 * h + 2], wxy[4 * h + 3]);
+            for (int r = 0; r < 8; ++r) {
+                sx[r * 68 + q] = act ? wxy[r] : 0.f;
+                sy[r * 64 + q] = act ? wxy[8 + r] : 0.f;
+            }
             // Chebyshev values T_{k0 + k}(s) of the group's orders, and g x
-            float4* dt = reinterpret_cast<float4*>(sT + lane * NPL);
             float t, tm1;
             cheb_start(ss, k0, t, tm1);
 #pragma unroll
-            for (int k4 = 0; k4 < NPL / 4; ++k4) {
-                float tr[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    tr[j] = 4 * k4 + j < nk ? t : 0.f;
-                    const float tn = 2.f * ss * t - tm1;
-                    tm1 = t;
-                    t = tn;
-                }
-                dt[k4] = make_float4(tr[0], tr[1], tr[2], tr[3]);
+            for (int k = 0; k < NPL; ++k) {
+                sT[k * 68 + q] = act && k < nk ? t : 0.f;
+                const float tn = 2.f * ss * t - tm1;
+                tm1 = t;
+                t = tn;
             }
-            reinterpret_cast<float2*>(sV)[lane] = make_float2(vr, vi);
+            sV[q] = act ? vr : 0.f;
+            sV[64 + q] = act ? vi : 0.f;
         }
         lds_order();                                        // staging writes precede the walk's reads
         // this lane's operands: A = weight of cell (lane mod 8, lane / 8);
         // B = column c = lane mod NCOL: order k0 + c mod NPL, Re (c < NPL) or Im
-        const float* wa_l = sw + (lane & 7);
-        const float* wb_l = sw + 8 + (lane >> 3);
-        const float* t_l = sT + (col % NPL);
-        const float* v_l = sV + (col / NPL);
-        // software-pipelined walk (two operand sets in turn): the next
-        // sample's operands are read from LDS while the current outer product
-        // runs
-        struct Ops { float wa, wb, t, v; };
-        auto take = [&](Ops& o) __attribute__((always_inline)) {
-            const int q = pending ? __ffsll((unsigned long long)pending) - 1 : 0;   // slot 0 past the end
-            pending &= pending - 1;
-            o.wa = wa_l[q * 16];
-            o.wb = wb_l[q * 16];
-            o.t = t_l[q * NPL];
-            o.v = v_l[q * 2];
+        const float* pa = sx + (lane & 7) * 68;
+        const float* pb = sy + (lane >> 3) * 64;
+        const float* pt = sT + (col % NPL) * 68;
+        const float* pv = sV + (col / NPL) * 64;
+        struct Ops { float4 a, b, t, v; };
+        auto rd4 = [&](Ops& o, int q) __attribute__((always_inline)) {   // slots q .. q + 3 (q <= 64)
+            o.a = *reinterpret_cast<const float4*>(pa + q);
+            o.b = *reinterpret_cast<const float4*>(pb + q);
+            o.t = *reinterpret_cast<const float4*>(pt + q);
+            o.v = *reinterpret_cast<const float4*>(pv + q);
         };
-        auto outer = [&](const Ops& o) __attribute__((always_inline)) {
-            if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(o.wa * o.wb, o.t * o.v, acc, 0, 0, 0);
-            else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(o.wa * o.wb, o.t * o.v, acc, 0, 0, 0);
+        auto outer = [&](float a, float b) __attribute__((always_inline)) {
+            if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, acc, 0, 0, 0);
+            else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(a, b, acc, 0, 0, 0);
         };
+        auto four = [&](const Ops& o) __attribute__((always_inline)) {
+            outer(o.a.x * o.b.x, o.t.x * o.v.x);
+            outer(o.a.y * o.b.y, o.t.y * o.v.y);
+            outer(o.a.z * o.b.z, o.t.z * o.v.z);
+            outer(o.a.w * o.b.w, o.t.w * o.v.w);
+        };
+        // two operand sets in turn: the next four samples are read while the
+        // current four outer products run (the slots read past n4 are unused)
         Ops o0, o1;
-        take(o0);
-        while (true) {                                      // the reads run unconditionally, so the
-            const bool m1 = pending != 0;                   // LDS counter state is the same on every path
-            take(o1);
-            outer(o0);
-            if (!m1) break;
-            const bool m2 = pending != 0;
-            take(o0);
-            outer(o1);
-            if (!m2) break;
+        rd4(o0, 0);
+        for (int qq = 0;;) {
+            rd4(o1, qq + 4);
+            four(o0);
+            if ((qq += 4) >= n4) break;
+            rd4(o0, qq + 4);
+            four(o1);
+            if ((qq += 4) >= n4) break;
         }
         lds_order();                                        // the walk's reads precede the next staging writes
     }

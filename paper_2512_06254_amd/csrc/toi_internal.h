@@ -80,8 +80,8 @@ inline int gridder_kacc(int kmax, int gp) {
     return k <= 1 ? 1 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
 }
 inline size_t gridder_lds(int gp, int threads, int kacc, bool mfma) {
-    if (mfma) {   // staging [64][16 + gp + 2], then reused as the write-out buffer [64][2 gp + 1]
-        const size_t stage = (size_t)64 * (16 + gp + 2), wout = (size_t)64 * (2 * gp + 1);
+    if (mfma) {   // staging rows (8 x 68, 8 x 64, 2 x 64, gp x 68), then the write-out buffer [64][2 gp + 1]
+        const size_t stage = (size_t)8 * 68 + 8 * 64 + 2 * 64 + (size_t)gp * 68, wout = (size_t)64 * (2 * gp + 1);
         return (stage > wout ? stage : wout) * sizeof(float);
     }
     (void)kacc;
