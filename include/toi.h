@@ -179,8 +179,9 @@ toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* w
                          int32_t* n_slab, int32_t* cheb_k, uint32_t* status);
 
 /* Measurement support.  Stages timed with HIP events on the context's stream:
- * TOI_STAGE_PREP (sample statistics, basis, plan), TOI_STAGE_CLEAR (grid
- * clear), TOI_STAGE_GRID (gridding), TOI_STAGE_FFT_ROWS, TOI_STAGE_FFT_COLS
+ * TOI_STAGE_PREP (sample statistics, basis, plan), TOI_STAGE_BIN (work
+ * items, gridding records, bin scan, work units and lists), TOI_STAGE_GRID
+ * (gridding), TOI_STAGE_FFT_ROWS, TOI_STAGE_FFT_COLS
  * (column FFT + correction + combination), TOI_STAGE_REPROJECT,
  * TOI_STAGE_TLISI, TOI_STAGE_DEGRID (adjoint), TOI_STAGE_BATCH (one whole
  * toi_image_batch graph launch; its kernels are not timed individually).  toi_profile_enable(ctx, 1)
@@ -189,7 +190,7 @@ toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* w
  * duration in milliseconds and the number of timed launches (host arrays of
  * TOI_NSTAGE entries, each nullable). */
 #define TOI_STAGE_PREP 0
-#define TOI_STAGE_CLEAR 1
+#define TOI_STAGE_BIN 1
 #define TOI_STAGE_GRID 2
 #define TOI_STAGE_FFT_ROWS 3
 #define TOI_STAGE_FFT_COLS 4

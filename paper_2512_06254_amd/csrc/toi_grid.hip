@@ -571,15 +571,21 @@ __global__ __launch_bounds__(1024) void k_grid_tiles(
 // ------------------------------------------------- 3b. tiles, matrix cores
 constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
 
-// Matrix-core gridder.  Tiles are 8 x 8 cells, one v_mfma block: the tile's
-// 64 cells are the rows, the group's planes (order, slab) x {Re, Im} the
-// columns.  The contribution of one sample to the tile is the outer product
-// of its kernel weights at the 64 cells (zero outside its footprint) and the
-// values T_k(s) Re(g x), T_k(s) Im(g x) of the planes of its slab (zero for
-// the group's other planes).  One v_mfma_f32_32x32x1f32 (NCOL = 32: two
-// 32 x 32 blocks) or v_mfma_f32_16x16x1f32 (NCOL = 16: four 16 x 16 blocks)
-// per sample and tile adds it to accumulators that hold the whole tile in
-// registers: no LDS accumulation, no atomics, nothing to flush.  Lane l
+// Matrix-core gridder.  Tiles are 8 x 8 cells: the tile's 64 cells are the
+// rows, the group's planes (order, slab) x {Re, Im} the columns.  The
+// contribution of one sample to the tile is the outer product of its kernel
+// weights at the 64 cells (zero outside its footprint) and the values
+// T_k(s) Re(g x), T_k(s) Im(g x) of the planes of its slab (zero for the
+// group's other planes); the tile is the product A B of the weights A (64
+// cells x samples) and the values B (samples x NCOL).  NCOL = 32 (16
+// planes): v_mfma_f32_32x32x16_bf16 on two 32-row halves, 16 samples per
+// instruction, each operand split as x = hi + lo in bf16 and A B formed as
+// Ah Bh + Ah Bl + Al Bh (products exact, the dropped Al Bl and the splits
+// about 2^-17 relative), accumulated in FP32; the bf16 matrix cores run
+// beside the vector ALU, where FP32 matrix instructions would share it.
+// NCOL = 16 (8 planes): one v_mfma_f32_16x16x1f32 (four 16 x 16 blocks) per
+// sample.  The accumulators hold the whole tile in registers: no LDS
+// accumulation, no atomics, nothing to flush.  Lane l
 // supplies the weight of cell (l mod 8, l / 8) (A operand) and column
 // l mod NCOL (B operand); accumulator register r of lane l then holds cell
 // (4 (l / 32) + r mod 4, r / 4) (NCOL = 32) or (4 ((l / 16) mod 2) + r mod 4,
@@ -592,7 +598,7 @@ constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
 // T_k Re/Im(g x) is formed in the walk, which keeps the staging at 8.5 KB per
 // wave), then the write-out buffer.
 template <int NCOL>
-__global__ __launch_bounds__(64, 5) void k_grid_tiles_mfma(
+__global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
     const SampleRec* __restrict__ recs, int n_chan, const DevPlan* __restrict__ P, int M, int NT,
     const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
     const int32_t* __restrict__ order, const int32_t* __restrict__ cnt, const int4* __restrict__ units,
@@ -601,7 +607,22 @@ __global__ __launch_bounds__(64, 5) void k_grid_tiles_mfma(
     static_assert(kTile == 8, "a tile is one 64-row matrix block");
     constexpr int NREG = NCOL;                 // accumulator registers per lane (64 x NCOL / 64)
     constexpr int NPL = NCOL / 2;              // planes per block
+    constexpr int kQuad = NCOL == 32 ? 16 : 4; // samples per step of the walk
     typedef float acc_t __attribute__((ext_vector_type(NREG)));
+    typedef float f32x16 __attribute__((ext_vector_type(16)));
+    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+    auto ld8 = [](const float* p, float* o) __attribute__((always_inline)) {
+        const float4 u = reinterpret_cast<const float4*>(p)[0], w = reinterpret_cast<const float4*>(p)[1];
+        o[0] = u.x; o[1] = u.y; o[2] = u.z; o[3] = u.w; o[4] = w.x; o[5] = w.y; o[6] = w.z; o[7] = w.w;
+    };
+    auto split_bf16 = [](const float* x, bf16x8& hi, bf16x8& lo) __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const __bf16 h = (__bf16)x[e];
+            hi[e] = h;
+            lo[e] = (__bf16)(x[e] - (float)h);
+        }
+    };
     extern __shared__ float lds[];
     const int tiles = NT * NT;
     if (P->status & kStatusFatal) return;
@@ -633,9 +654,10 @@ __global__ __launch_bounds__(64, 5) void k_grid_tiles_mfma(
     const int nk = k1 - k0;                    // <= gp <= NPL planes
     const int tx = tile % NT, ty = tile / NT;
     acc_t acc = {};
+    f32x16 acc_lo = {}, acc_hi = {};            // NCOL = 32: cells 0..31, 32..63
 
-    // gridding records of the first item; each next item's are loaded
-    // during the current walk
+    // gridding records, loaded two items ahead (a walk is shorter than the
+    // latency of HBM)
     auto load_rec = [&](int item_, float4& ra, float4& rb) __attribute__((always_inline)) {
         const int c = (item_ % n_chunks) * kItemChans + lane;
         if (c < n_chan) {
@@ -647,8 +669,9 @@ __global__ __launch_bounds__(64, 5) void k_grid_tiles_mfma(
             rb = make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
-    float4 ra, rb;
+    float4 ra, rb, ra2, rb2;
     if (b0 < b1) load_rec(list[b0], ra, rb);
+    if (b0 + 1 < b1) load_rec(list[b0 + 1], ra2, rb2);
     for (int it = b0; it < b1; ++it) {
         const int pk = __float_as_int(ra.x), sp = __float_as_int(ra.y);
         const int ix = pk & 8191, iy = (pk >> 13) & 8191;
@@ -656,13 +679,14 @@ __global__ __launch_bounds__(64, 5) void k_grid_tiles_mfma(
         const int ddx = (ix - tx * kTile) & (M - 1), ddy = (iy - ty * kTile) & (M - 1);
         const bool act = pk >= 0 && (sp >= s0 && sp < s1) && (ddx < kTile || ddx >= M - 7) &&
                          (ddy < kTile || ddy >= M - 7);
-        if (it + 1 < b1) load_rec(list[it + 1], ra, rb);   // prefetch the next item's records
+        ra = ra2;
+        rb = rb2;
+        if (it + 2 < b1) load_rec(list[it + 2], ra2, rb2);   // the records two items ahead
         const uint64_t amask = __ballot(act);
         if (amask == 0) continue;
-        // the active samples take slots 0 .. n_act - 1; the walk takes four
-        // slots at a time, so up to three inactive lanes fill the slots up to
-        // n4 with zeros
-        const int n_act = __popcll(amask), n4 = (n_act + 3) & ~3;
+        // the active samples take slots 0 .. n_act - 1; the walk takes kQuad
+        // slots at a time, so inactive lanes fill the slots up to n4 with zeros
+        const int n_act = __popcll(amask), n4 = (n_act + kQuad - 1) & ~(kQuad - 1);
         const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(amask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)amask, 0));
         const int q = act ? below : n_act + (lane - below);
         if (q < n4) {
@@ -691,40 +715,84 @@ __global__ __launch_bounds__(64, 5) void k_grid_tiles_mfma(
         lds_order();                                        // staging writes precede the walk's reads
         // this lane's operands: A = weight of cell (lane mod 8, lane / 8);
         // B = column c = lane mod NCOL: order k0 + c mod NPL, Re (c < NPL) or Im
-        const float* pa = sx + (lane & 7) * 68;
-        const float* pb = sy + (lane >> 3) * 64;
-        const float* pt = sT + (col % NPL) * 68;
-        const float* pv = sV + (col / NPL) * 64;
-        struct Ops { float4 a, b, t, v; };
-        auto rd4 = [&](Ops& o, int q) __attribute__((always_inline)) {   // slots q .. q + 3 (q <= 64)
-            o.a = *reinterpret_cast<const float4*>(pa + q);
-            o.b = *reinterpret_cast<const float4*>(pb + q);
-            o.t = *reinterpret_cast<const float4*>(pt + q);
-            o.v = *reinterpret_cast<const float4*>(pv + q);
-        };
-        auto outer = [&](float a, float b) __attribute__((always_inline)) {
-            if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, acc, 0, 0, 0);
-            else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(a, b, acc, 0, 0, 0);
-        };
-        auto four = [&](const Ops& o) __attribute__((always_inline)) {
-            outer(o.a.x * o.b.x, o.t.x * o.v.x);
-            outer(o.a.y * o.b.y, o.t.y * o.v.y);
-            outer(o.a.z * o.b.z, o.t.z * o.v.z);
-            outer(o.a.w * o.b.w, o.t.w * o.v.w);
-        };
-        // two operand sets in turn: the next four samples are read while the
-        // current four outer products run (the slots read past n4 are unused)
-        Ops o0, o1;
-        rd4(o0, 0);
-        for (int qq = 0;;) {
-            rd4(o1, qq + 4);
-            four(o0);
-            if ((qq += 4) >= n4) break;
-            rd4(o0, qq + 4);
-            four(o1);
-            if ((qq += 4) >= n4) break;
+        if constexpr (NCOL == 32) {
+            // bf16 matrix cores, 16 samples per instruction: x = hi + lo in
+            // bf16, and A B = Ah Bh + Ah Bl + Al Bh (about 2^-17 relative).
+            // Lane l: rows (cells) l mod 32 and 32 + l mod 32 of A, column
+            // l mod 32 of B, samples 8 (l / 32) .. + 7 of the group.
+            const int h = lane >> 5, c = lane & 31;
+            const float* px = sx + (c & 7) * 68 + 8 * h;
+            const float* py = sy + (c >> 3) * 64 + 8 * h;
+            const float* pt = sT + (c & 15) * 68 + 8 * h;
+            const float* pv = sV + (c >> 4) * 64 + 8 * h;
+            for (int q0 = 0; q0 < n4; q0 += 16) {
+                float x[8], y0[8], y1[8], t[8], v[8];
+                ld8(px + q0, x);
+                ld8(py + q0, y0);
+                ld8(py + 4 * 64 + q0, y1);
+                ld8(pt + q0, t);
+                ld8(pv + q0, v);
+                float a0[8], a1[8], b[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    a0[e] = x[e] * y0[e];
+                    a1[e] = x[e] * y1[e];
+                    b[e] = t[e] * v[e];
+                }
+                bf16x8 a0h, a0l, a1h, a1l, bh, bl;
+                split_bf16(a0, a0h, a0l);
+                split_bf16(a1, a1h, a1l);
+                split_bf16(b, bh, bl);
+                acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, bh, acc_lo, 0, 0, 0);
+                acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, bh, acc_hi, 0, 0, 0);
+                acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, bl, acc_lo, 0, 0, 0);
+                acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, bl, acc_hi, 0, 0, 0);
+                acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, bh, acc_lo, 0, 0, 0);
+                acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, bh, acc_hi, 0, 0, 0);
+            }
+        } else {
+            const float* pa = sx + (lane & 7) * 68;
+            const float* pb = sy + (lane >> 3) * 64;
+            const float* pt = sT + (col % NPL) * 68;
+            const float* pv = sV + (col / NPL) * 64;
+            struct Ops { float4 a, b, t, v; };
+            auto rd4 = [&](Ops& o, int q) __attribute__((always_inline)) {   // slots q .. q + 3 (q <= 64)
+                o.a = *reinterpret_cast<const float4*>(pa + q);
+                o.b = *reinterpret_cast<const float4*>(pb + q);
+                o.t = *reinterpret_cast<const float4*>(pt + q);
+                o.v = *reinterpret_cast<const float4*>(pv + q);
+            };
+            auto outer = [&](float a, float b) __attribute__((always_inline)) {
+                if constexpr (NCOL == 32) acc = __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, acc, 0, 0, 0);
+                else acc = __builtin_amdgcn_mfma_f32_16x16x1f32(a, b, acc, 0, 0, 0);
+            };
+            auto four = [&](const Ops& o) __attribute__((always_inline)) {
+                outer(o.a.x * o.b.x, o.t.x * o.v.x);
+                outer(o.a.y * o.b.y, o.t.y * o.v.y);
+                outer(o.a.z * o.b.z, o.t.z * o.v.z);
+                outer(o.a.w * o.b.w, o.t.w * o.v.w);
+            };
+            // two operand sets in turn: the next four samples are read while the
+            // current four outer products run (the slots read past n4 are unused)
+            Ops o0, o1;
+            rd4(o0, 0);
+            for (int qq = 0;;) {
+                rd4(o1, qq + 4);
+                four(o0);
+                if ((qq += 4) >= n4) break;
+                rd4(o0, qq + 4);
+                four(o1);
+                if ((qq += 4) >= n4) break;
+            }
         }
         lds_order();                                        // the walk's reads precede the next staging writes
+    }
+    if constexpr (NCOL == 32) {   // the 32 x 32 blocks in the layout of the two-block instruction
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            acc[r] = acc_lo[r];
+            acc[16 + r] = acc_hi[r];
+        }
     }
     // write-out: accumulators -> LDS [cell][NCOL + 1] -> planes of the group in HBM
     float* wo = lds;
@@ -795,7 +863,7 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
     const int n_items = s.n_row * n_chunks;
     const int n_bins = c->NG_max * NT * NT;
     {
-        StageTimer timer(c, TOI_STAGE_CLEAR);   // binning
+        StageTimer timer(c, TOI_STAGE_BIN);
         const int words = (NT + 31) / 32;
         const int n_scan = (n_bins + kScanBlock - 1) / kScanBlock;
         hipLaunchKernelGGL(k_scan_clear, dim3(256), dim3(256), 0, c->stream, c->bin_count, n_bins, c->bin_aux,

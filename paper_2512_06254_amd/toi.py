@@ -76,7 +76,7 @@ _SIGS = {
 
 TUNE_VARIANTS = 8
 
-STAGES = ("prep", "clear", "grid", "fft_rows", "fft_cols", "reproject", "tlisi", "degrid", "batch", "detect")
+STAGES = ("prep", "bin", "grid", "fft_rows", "fft_cols", "reproject", "tlisi", "degrid", "batch", "detect")
 
 
 def lib():
