@@ -282,11 +282,13 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict_
 // gridder, over the forward's bins and gridding records (toi_grid of the same
 // snapshot).  One wavefront per 8 x 8 tile holds the tile's plane gradients G
 // (64 cells x 32 columns: the group's orders x Re/Im) as B operands of
-// v_mfma_f32_32x32x2f32 (step i covers cells 2i, 2i + 1; lane l holds
-// G[2i + l / 32][l mod 32]).  The samples an item has in the tile are
-// compacted into LDS (weights at the tile's 8 columns and 8 rows, T_k(s)); per
-// batch of 32 of them 32 steps give H = A G, A[q][cell] the weight of sample
-// q at the cell (A from lane q mod 32 for cell 2i + l / 32).  Then
+// v_mfma_f32_32x32x16_bf16, split as G = Gh + Gl in bf16 (chunk c covers
+// cells 16 c .. 16 c + 15; lane l holds G[16 c + 8 (l / 32) + e][l mod 32],
+// e = 0..7).  The samples an item has in the tile are compacted into LDS
+// (weights at the tile's 8 columns and 8 rows, T_k(s)); per batch of 32 of
+// them H = A G = sum over the chunks of Ah Gh + Ah Gl + Al Gh, A[q][cell] the
+// weight of sample q at the cell (from lane q mod 32, split the same way;
+// the bf16 matrix cores run beside the vector ALU).  Then
 // grad x_q += sum_k T_k(s_q) (H[q][k, Re] + i H[q][k, Im]): lane l holds
 // column l mod 32 of rows (r mod 4) + 8 (r / 4) + 4 (l / 32) (hardware
 // layout), multiplies by T and a DPP reduction over each 16-lane row sums the
@@ -301,6 +303,15 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                                                      const int4* __restrict__ units,
                                                      const float2* __restrict__ gg, float* __restrict__ gx) {
     typedef float v16 __attribute__((ext_vector_type(16)));
+    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+    auto split_bf16 = [](const float* x, bf16x8& hi, bf16x8& lo) __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const __bf16 t = (__bf16)x[e];
+            hi[e] = t;
+            lo[e] = (__bf16)(x[e] - (float)t);
+        }
+    };
     __shared__ float sw[64 * 16];      // compacted samples: weights at tile columns 0..7, rows 0..7
     __shared__ float sT[64 * 16];      // T_{k0 + k}(s), zero for k >= nk
     __shared__ int sidx[64];           // sample index r * n_chan + c
@@ -324,18 +335,23 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
         group_range(g, P, s0, s1, k0, k1);   // one slab per group
         const int nk = k1 - k0;
         const int tx = tile % NT, ty = tile / NT;
-        // the tile's plane gradients as B operands
-        float gb[32];
+        // the tile's plane gradients as B operands, split into bf16 hi + lo:
+        // chunk c covers cells 16 c .. 16 c + 15, lane l elements e = 0..7 are
+        // cells 16 c + 8 (l / 32) + e, i.e. tile row 2 c + l / 32, column e
+        bf16x8 gh[4], gl[4];
 #pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            const int cell = 2 * i + half;
-            float v = 0.f;
-            if (pl < nk) {
-                const float2 gv = gg[((size_t)(s0 * P->K + k0 + pl) * M + ty * kTile + (cell >> 3)) * M + tx * kTile +
-                                     (cell & 7)];
-                v = col < 16 ? gv.x : gv.y;
+        for (int c4 = 0; c4 < 4; ++c4) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                v[e] = 0.f;
+                if (pl < nk) {
+                    const float2 gv = gg[((size_t)(s0 * P->K + k0 + pl) * M + ty * kTile + 2 * c4 + half) * M +
+                                         tx * kTile + e];
+                    v[e] = col < 16 ? gv.x : gv.y;
+                }
             }
-            gb[i] = v;
+            split_bf16(v, gh[c4], gl[c4]);
         }
         for (int it = b0; it < b1; ++it) {
             const int item = list[it];
@@ -386,12 +402,22 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
             for (int b = 0; b < n_act; b += 32) {
                 const int qa = b + col;                     // this lane's A row (sample slot)
                 const bool oka = qa < n_act;
-                const float* wq = sw + (oka ? qa : 0) * 16;
+                const float4* wq = reinterpret_cast<const float4*>(sw + (oka ? qa : 0) * 16);
+                const float4 x0 = wq[0], x1 = wq[1], y0 = wq[2], y1 = wq[3];
+                const float wx[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+                const float wy[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
                 v16 h = {};
 #pragma unroll
-                for (int i = 0; i < 32; ++i) {              // cells 2i + half: column 2 (i mod 4) + half, row i / 4
-                    const float a = oka ? wq[2 * (i & 3) + half] * wq[8 + (i >> 2)] : 0.f;
-                    h = __builtin_amdgcn_mfma_f32_32x32x2f32(a, gb[i], h, 0, 0, 0);
+                for (int c4 = 0; c4 < 4; ++c4) {            // A[q][cell] = w_x(column e) w_y(row 2 c + half)
+                    float a[8];
+                    const float wr = oka ? wy[2 * c4 + half] : 0.f;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) a[e] = wx[e] * wr;
+                    bf16x8 ah, al;
+                    split_bf16(a, ah, al);
+                    h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, gh[c4], h, 0, 0, 0);
+                    h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, gl[c4], h, 0, 0, 0);
+                    h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, gh[c4], h, 0, 0, 0);
                 }
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
