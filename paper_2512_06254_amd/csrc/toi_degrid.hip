@@ -116,7 +116,7 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
     constexpr int T = M / E;
-    __shared__ float2 lds[M];
+    __shared__ float2 lds[fft_lds_size<M, E>()];
     __shared__ float2 tw_s[M];
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
     if (plan->status & kStatusFatal) return;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict_
     constexpr int KEEP = E / 2;
     constexpr int T = M / E;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
-    __shared__ float2 lds[M];
+    __shared__ float2 lds[fft_lds_size<M, E>()];
     __shared__ float2 tw_s[M];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
     const int plane = id / nbands, band = id % nbands;

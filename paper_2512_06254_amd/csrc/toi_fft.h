@@ -104,7 +104,20 @@ __device__ inline void fft_stage_regs(float2* v, const float2* tw) {
     }
 }
 
-template <int M, int E, int NS>
+// Exchange buffer of the stages: M values, with PAD one pad slot after every
+// E (index i at i + i / E), so that the stride-E writes of a stage fall in
+// different banks (the padded addresses cost registers, which the row pass,
+// holding four rows, does not have).
+template <int M, int E, bool PAD = true>
+__host__ __device__ constexpr int fft_lds_size() {
+    return PAD ? M + M / E : M;
+}
+template <int E, bool PAD>
+__device__ inline int fft_pad(int i) {
+    return PAD ? i + i / E : i;
+}
+
+template <int M, int E, int NS, bool PAD = true>
 __device__ inline void fft_stages(float2* v, float2* lds, const float2* tw) {
     constexpr int T = M / E;
     constexpr int R = fft_radix_at(M, E, NS);
@@ -117,16 +130,16 @@ __device__ inline void fft_stages(float2* v, float2* lds, const float2* tw) {
             const int j = threadIdx.x + b * T;
             const int base = (j / NS) * NS * R + (j & (NS - 1));
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[base + r * NS] = v[b * R + r];
+            for (int r = 0; r < R; ++r) lds[fft_pad<E, PAD>(base + r * NS)] = v[b * R + r];
         }
         __syncthreads();
 #pragma unroll
         for (int b = 0; b < E / R2; ++b) {
             const int j = threadIdx.x + b * T;
 #pragma unroll
-            for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[j + r * (M / R2)];
+            for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[fft_pad<E, PAD>(j + r * (M / R2))];
         }
-        fft_stages<M, E, NS * R>(v, lds, tw);
+        fft_stages<M, E, NS * R, PAD>(v, lds, tw);
     }
 }
 

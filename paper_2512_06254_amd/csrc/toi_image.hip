@@ -16,6 +16,8 @@
 
 namespace toi {
 
+constexpr bool kRowPad = false;   // padded exchanges spill the row pass's registers
+
 template <int M, int E, int B>
 __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict__ grid, float2* __restrict__ hbuf,
                                                     const float2* __restrict__ tw,
@@ -25,7 +27,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict_
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
-    __shared__ float2 lds[M];
+    __shared__ float2 lds[fft_lds_size<M, E, kRowPad>()];
     __shared__ float2 tw_s[M];
     __shared__ uint32_t tb[WORDS];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict_
         const int y = band * B + rb;
         float2 v[E];
         fft_load_masked<M, E>(v, grid + ((size_t)plane * M + y) * M, occupied);
-        fft_stages<M, E, 1>(v, lds, tw_s);
+        fft_stages<M, E, 1, kRowPad>(v, lds, tw_s);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) keep[rb][q] = v[fft_kept_slot<E>(q)];
         __syncthreads();
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict_
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
-    __shared__ float2 lds[M];
+    __shared__ float2 lds[fft_lds_size<M, E>()];
     __shared__ float2 tw_s[M];
     extern __shared__ uint32_t rb_s[];                 // [ng][WORDS] nonempty tile rows per group
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
