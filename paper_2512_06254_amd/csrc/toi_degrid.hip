@@ -117,10 +117,10 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
     constexpr int KEEP = E / 2;
     constexpr int T = M / E;
     __shared__ float2 lds[fft_lds_size<M, E>()];
-    __shared__ float2 tw_s[M];
+    __shared__ float2 tw_s[FftTw<M, E>::size()];
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
     if (plan->status & kStatusFatal) return;
-    load_twiddles<M>(tw_s, tw);
+    load_twiddles<M, E>(tw_s, tw);
     const int K = plan->K, ns = plan->n_slab;
     int j2[KEEP];
     float y[KEEP];
@@ -240,14 +240,14 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict_
     constexpr int T = M / E;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[fft_lds_size<M, E>()];
-    __shared__ float2 tw_s[M];
+    __shared__ float2 tw_s[FftTw<M, E>::size()];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
     const int plane = id / nbands, band = id % nbands;
     if ((plan->status & kStatusFatal) || plane >= plan->planes) return;
     const int g = group_of_plane(plane, plan);
     const int ty = (band * B) / kTile;
     if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) return;
-    load_twiddles<M>(tw_s, tw);
+    load_twiddles<M, E>(tw_s, tw);
     float2 in[B][KEEP];
 #pragma unroll
     for (int q = 0; q < KEEP; ++q) {

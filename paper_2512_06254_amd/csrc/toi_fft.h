@@ -75,17 +75,37 @@ __host__ __device__ constexpr int fft_radix_at(int M, int E, int NS) {
     return NS == 1 ? fft_first_radix(M, E) : E;
 }
 
-// e^{+2 pi i n / M} from the full-period table tw[n] (n < M), which the
-// kernels keep in LDS.
-template <int M>
-__device__ inline float2 twiddle(const float2* tw, int n) {
-    return tw[n & (M - 1)];
-}
+// Twiddles in LDS, one table per stage after the first: the stage with
+// stride NS (radix E) multiplies element r of the butterfly of k = j mod NS by
+// e^{+2 pi i r k / (NS E)}, kept at k (E - 1) + r - 1.  Consecutive lanes then
+// read addresses E - 1 values apart, which spreads them over the banks (a
+// single M-entry table read at r k M / (NS E) puts up to 16 lanes in one
+// bank).  The tables hold about M entries in total, built from the
+// full-period table tw[n] = e^{+2 pi i n / M} in HBM.
+template <int M, int E>
+struct FftTw {
+    static constexpr int R1 = fft_first_radix(M, E);
+    static constexpr int off(int NS) {   // start of the table of the stage with stride NS (> 1)
+        int o = 0;
+        for (int ns = R1; ns < NS; ns *= E) o += ns * (E - 1);
+        return o;
+    }
+    static constexpr int size() { return off(M); }
+};
 
-// Copy the twiddle table into LDS (all threads; ends with a barrier).
-template <int M>
+// Build the stage tables in LDS (all threads; ends with a barrier).
+template <int M, int E>
 __device__ inline void load_twiddles(float2* tw_s, const float2* __restrict__ tw) {
-    for (int i = threadIdx.x; i < M; i += blockDim.x) tw_s[i] = tw[i];
+    using TW = FftTw<M, E>;
+    for (int i = threadIdx.x; i < TW::size(); i += blockDim.x) {
+        int ns = TW::R1, o = 0;
+        while (i >= o + ns * (E - 1)) {
+            o += ns * (E - 1);
+            ns *= E;
+        }
+        const int k = (i - o) / (E - 1), r = (i - o) % (E - 1) + 1;
+        tw_s[i] = tw[(r * k * (M / (ns * E))) & (M - 1)];
+    }
     __syncthreads();
 }
 
@@ -94,52 +114,74 @@ __device__ inline void fft_stage_regs(float2* v, const float2* tw) {
     constexpr int T = M / E;
 #pragma unroll
     for (int b = 0; b < E / R; ++b) {
-        if (NS > 1) {
+        if constexpr (NS > 1) {
+            static_assert(R == E, "every stage after the first has radix E");
             const int j = threadIdx.x + b * T;
-            const int k = j & (NS - 1);
+            const float2* w = tw + FftTw<M, E>::off(NS) + (j & (NS - 1)) * (E - 1) - 1;
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], twiddle<M>(tw, r * k * (M / (NS * R))));
+            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r]);
         }
         Dft<R>::run(v + b * R);
     }
 }
 
-// Exchange buffer of the stages: M values, with PAD one pad slot after every
-// E (index i at i + i / E), so that the stride-E writes of a stage fall in
-// different banks (the padded addresses cost registers, which the row pass,
-// holding four rows, does not have).
-template <int M, int E, bool PAD = true>
+// Exchange buffer of the stages: M values with one pad slot after every E
+// (index i at i + i / E), so that the stride-E writes of a stage fall in
+// different banks.  Where a stage's offsets r NS (r M / R2 for the reads) are
+// multiples of E, or the base is and r NS < E, the padded address is the
+// padded base plus a compile-time offset.
+template <int M, int E>
 __host__ __device__ constexpr int fft_lds_size() {
-    return PAD ? M + M / E : M;
+    return M + M / E;
 }
-template <int E, bool PAD>
+template <int E>
 __device__ inline int fft_pad(int i) {
-    return PAD ? i + i / E : i;
+    return i + i / E;
+}
+template <int E>
+__host__ __device__ constexpr int fft_pad_off(int d) {   // padded offset d (a multiple of E, or below E)
+    return d + d / E;
 }
 
-template <int M, int E, int NS, bool PAD = true>
+template <int M, int E, int NS>
 __device__ inline void fft_stages(float2* v, float2* lds, const float2* tw) {
     constexpr int T = M / E;
     constexpr int R = fft_radix_at(M, E, NS);
     fft_stage_regs<M, E, R, NS>(v, tw);
     if constexpr (NS * R < M) {
         constexpr int R2 = fft_radix_at(M, E, NS * R);
+        // the base of a write is a multiple of E when NS = 1 and R = E, and the
+        // offsets r NS are multiples of E when NS >= E; otherwise pad each
+        constexpr bool split_w = (NS >= E && NS % E == 0) || (NS == 1 && R == E);
+        constexpr bool split_r = (M / R2) % E == 0;
         __syncthreads();
 #pragma unroll
         for (int b = 0; b < E / R; ++b) {
             const int j = threadIdx.x + b * T;
             const int base = (j / NS) * NS * R + (j & (NS - 1));
+            if constexpr (split_w) {
+                float2* dst = lds + fft_pad<E>(base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[fft_pad<E, PAD>(base + r * NS)] = v[b * R + r];
+                for (int r = 0; r < R; ++r) dst[fft_pad_off<E>(r * NS)] = v[b * R + r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[fft_pad<E>(base + r * NS)] = v[b * R + r];
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int b = 0; b < E / R2; ++b) {
             const int j = threadIdx.x + b * T;
+            if constexpr (split_r) {
+                const float2* src = lds + fft_pad<E>(j);
 #pragma unroll
-            for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[fft_pad<E, PAD>(j + r * (M / R2))];
+                for (int r = 0; r < R2; ++r) v[b * R2 + r] = src[fft_pad_off<E>(r * (M / R2))];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[fft_pad<E>(j + r * (M / R2))];
+            }
         }
-        fft_stages<M, E, NS * R, PAD>(v, lds, tw);
+        fft_stages<M, E, NS * R>(v, lds, tw);
     }
 }
 

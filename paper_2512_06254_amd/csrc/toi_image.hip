@@ -16,8 +16,6 @@
 
 namespace toi {
 
-constexpr bool kRowPad = false;   // padded exchanges spill the row pass's registers
-
 template <int M, int E, int B>
 __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict__ grid, float2* __restrict__ hbuf,
                                                     const float2* __restrict__ tw,
@@ -27,8 +25,8 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict_
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
-    __shared__ float2 lds[fft_lds_size<M, E, kRowPad>()];
-    __shared__ float2 tw_s[M];
+    __shared__ float2 lds[fft_lds_size<M, E>()];
+    __shared__ float2 tw_s[FftTw<M, E>::size()];
     __shared__ uint32_t tb[WORDS];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
     const int plane = id / nbands, band = id % nbands;
@@ -37,7 +35,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict_
     const int ty = (band * B) / kTile;
     if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) return;   // empty tile row
     if (threadIdx.x < WORDS) tb[threadIdx.x] = tile_bits[((size_t)g * NT + ty) * WORDS + threadIdx.x];
-    load_twiddles<M>(tw_s, tw);
+    load_twiddles<M, E>(tw_s, tw);
     auto occupied = [&](int x) { return (tb[x >> (kTileShift + 5)] >> ((x >> kTileShift) & 31)) & 1u; };
     float2 keep[B][KEEP];
 #pragma unroll
@@ -45,7 +43,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict_
         const int y = band * B + rb;
         float2 v[E];
         fft_load_masked<M, E>(v, grid + ((size_t)plane * M + y) * M, occupied);
-        fft_stages<M, E, 1, kRowPad>(v, lds, tw_s);
+        fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) keep[rb][q] = v[fft_kept_slot<E>(q)];
         __syncthreads();
@@ -80,7 +78,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict_
     constexpr int KEEP = E / 2;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[fft_lds_size<M, E>()];
-    __shared__ float2 tw_s[M];
+    __shared__ float2 tw_s[FftTw<M, E>::size()];
     extern __shared__ uint32_t rb_s[];                 // [ng][WORDS] nonempty tile rows per group
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
     int j2[KEEP];
@@ -88,7 +86,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict_
     for (int q = 0; q < KEEP; ++q) j2[q] = fft_kept_index<M, E>(q);
     float* out = tplane_t + (size_t)j1 * N;
     for (int i = threadIdx.x; i < ng_cap * WORDS; i += blockDim.x) rb_s[i] = row_bits[i];
-    load_twiddles<M>(tw_s, tw);
+    load_twiddles<M, E>(tw_s, tw);
     if (plan->status & kStatusFatal) {
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) out[j2[q]] = 0.f;
