@@ -262,17 +262,20 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
     const int words = (NT + 31) / 32;
     const int row0 = (blockIdx.x * kScanBlock + NT - 1) / NT;
     const int row1 = min(n_bins, (blockIdx.x + 1) * kScanBlock + NT - 1) / NT;   // rows [row0, row1)
-    for (int w = row0 * words + (int)threadIdx.x; w < row1 * words; w += blockDim.x) {
+    // one word per half-wavefront: each lane tests one tile, a ballot packs them
+    const int hw = (int)(threadIdx.x >> 5), hl = (int)(threadIdx.x & 31);
+    for (int w = row0 * words + hw; w < row1 * words; w += blockDim.x >> 5) {
         const int row = w / words, wd = w % words;
-        const int32_t* cr = count + (size_t)row * NT + wd * 32;
-        const int nb = min(32, NT - wd * 32);
-        uint32_t bits = 0;
-        for (int i = 0; i < nb; ++i)
-            if (cr[i] > 0) bits |= 1u << i;
-        tile_bits[w] = bits;
-        if (bits) {
-            const int g = row / NT, ty = row % NT;
-            atomicOr(&row_bits[g * words + (ty >> 5)], 1u << (ty & 31));
+        const int i = wd * 32 + hl;
+        const bool nz = i < NT && count[(size_t)row * NT + i] > 0;
+        const uint64_t m = __ballot(nz);
+        const uint32_t bits = (threadIdx.x & 32) ? (uint32_t)(m >> 32) : (uint32_t)m;
+        if (hl == 0) {
+            tile_bits[w] = bits;
+            if (bits) {
+                const int g = row / NT, ty = row % NT;
+                atomicOr(&row_bits[g * words + (ty >> 5)], 1u << (ty & 31));
+            }
         }
     }
 }
