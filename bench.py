@@ -200,6 +200,50 @@ def batched_leg(n_batch, reps, device):
             "kept_sample_fraction": [round(k, 3) for k in kept]}
 
 
+def ingest_leg(n_snap, reps, device):
+    """Host-resident MeerKAT-shaped snapshots (page-locked) imaged with toi_ingest: the
+    H2D copy of each snapshot overlaps the imaging of the previous one.  Reports the
+    end-to-end ms/snapshot including H2D, the copy alone and the device-resident path."""
+    import torch
+
+    import synth_inputs as S
+    from paper_2512_06254_amd import toi as T
+    wl = S.WORKLOADS["meerkat"]
+    n_slab, K = wl.forced_planes
+    dev = make_pool(wl, 2, device)
+    host = []
+    for d in dev:
+        host.append({k: (None if v is None else v.to("cpu").pin_memory()) for k, v in d.items()})
+    snaps = [host[i % 2] for i in range(n_snap)]
+    N, TT = wl.n_pix, wl.n_pix // 32
+    im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K, tile=32)
+    imgs = torch.zeros((n_snap, N, N), dtype=torch.float32, device=device)
+    tls = torch.zeros((n_snap - 2, TT, TT), dtype=torch.float32, device=device)
+    im.ingest(snaps[:2], imgs[:2])              # staging allocation and warm-up
+    torch.cuda.synchronize()
+    ms_ingest = time_events(lambda: im.ingest(snaps, imgs, tls), reps) / n_snap
+    h2d_bytes = sum(v.numel() * v.element_size() for v in host[0].values() if v is not None)
+    dst = {k: torch.empty_like(v, device=device) for k, v in host[0].items() if v is not None}
+    ms_copy = time_events(lambda: [dst[k].copy_(v, non_blocking=True) for k, v in host[0].items() if v is not None],
+                          reps)
+
+    def resident():
+        for i in range(n_snap):
+            im.grid(dev[i % 2])
+            im.image(out=imgs[i])
+            if i >= 2:
+                im.tlisi(imgs[i - 2], imgs[i - 1], imgs[i], out=tls[i - 2])
+
+    resident()
+    ms_res = time_events(resident, reps) / n_snap
+    im.close()
+    return {"workload": "meerkat, host-resident page-locked snapshots", "snapshots_per_call": n_snap,
+            "ms_per_snapshot_end_to_end": round(ms_ingest, 4), "ms_h2d_copy_per_snapshot": round(ms_copy, 4),
+            "h2d_bytes_per_snapshot": h2d_bytes, "h2d_GBps": round(h2d_bytes / (ms_copy * 1e-3) / 1e9, 1),
+            "ms_per_snapshot_device_resident": round(ms_res, 4),
+            "ms_if_serial": round(ms_copy + ms_res, 4)}
+
+
 def adjoint_leg(reps, device):
     """Forward image and the hand-written adjoint (vis + gain gradients) on the 1024-channel workload."""
     import torch
@@ -250,6 +294,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="snapshots per batched graph launch (0 = skip)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--ingest", type=int, default=8, help="host-resident snapshots per toi_ingest call (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -358,6 +403,9 @@ def main():
     if args.batch > 0:
         log(f"[bench] batched leg: {args.batch} uneven snapshots per graph launch")
         out["batched"] = batched_leg(args.batch, 2, device)
+    if args.ingest > 0:
+        log(f"[bench] ingest leg: {args.ingest} host-resident snapshots per call")
+        out["ingest"] = ingest_leg(args.ingest, 2, device)
     if not args.no_adjoint:
         log("[bench] adjoint leg")
         out["adjoint"] = adjoint_leg(max(3, args.steps // 4), device)

@@ -156,6 +156,24 @@ toi_status fitrig_detect(toi_ctx* ctx, const float* window, int32_t t,
 toi_status toi_image_batch(toi_ctx* ctx, const toi_snapshot* snaps, int32_t n,
                            float* images_out, float* tlisi_out);
 
+/* Streaming ingest (the paper's host pipeline, Section 4: data read and
+ * copied to the device while the GPU images): host_snaps holds n snapshot
+ * descriptors whose arrays are HOST pointers, in the layouts above.  For each
+ * snapshot the library copies the arrays into one of two device staging
+ * slots on an internal copy stream (default priority) and images the slot on
+ * the context's stream: the copy of snapshot i + 1 overlaps the imaging of
+ * snapshot i, and a slot is refilled once the gridding that read it has
+ * finished.  Page-locked host memory (hipHostMalloc, a pinned torch tensor)
+ * makes the copies asynchronous DMA; pageable memory works, without overlap.
+ * images_out (device f32[n][N][N]) and tlisi_out (device f32[n - 2][T][T],
+ * nullable) as in toi_image_batch.  The staging (2 x the largest snapshot's
+ * arrays) is allocated on the first call and kept by the context.
+ * Asynchronous on the context's stream; the host arrays must stay valid and
+ * unchanged until the stream has passed the call's work.  Errors as for
+ * toi_image_batch. */
+toi_status toi_ingest(toi_ctx* ctx, const toi_snapshot* host_snaps, int32_t n,
+                      float* images_out, float* tlisi_out);
+
 /* Autotuning of the gridder (batched use): the variants differ in the
  * accumulation unit (bit 0: matrix cores -- one v_mfma outer product per
  * sample and 8 x 8 grid tile, accumulators in registers; else vector ALU with

@@ -247,6 +247,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
 toi_status toi_destroy(toi_ctx* c) {
     if (!c) return TOI_OK;
     (void)hipStreamSynchronize(c->stream);
+    ingest_release(c);
     for (auto& e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

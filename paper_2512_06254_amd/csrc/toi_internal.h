@@ -192,6 +192,9 @@ struct toi_ctx {
     int batch_n;
     hipStream_t cap_stream;   // internal stream the batch is captured on (default priority)
     void* batch_desc;
+
+    // streaming ingest (toi_ingest.cpp): device staging slots and the copy stream
+    struct toi_ingest_state* ingest;
 };
 
 namespace toi {
@@ -227,6 +230,9 @@ inline int unit_workgroups(int n_items, int n_bins) {
     const long want = std::max<long>(8192, n_items / 2);
     return (int)std::min<long>(std::min<long>(want, 1 << 20), (long)n_bins + kSplitSlots);
 }
+
+// streaming ingest state (toi_ingest.cpp), released by toi_destroy
+void ingest_release(toi_ctx* ctx);
 
 // host-side tables (toi_ctx.cpp)
 void es_correction_table(int N, int M, double* out);   // (-1)^a / psi(a)

@@ -61,6 +61,8 @@ _SIGS = {
                                      ctypes.c_int32, ctypes.c_void_p]),
     "toi_image_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Snapshot), ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "toi_ingest": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Snapshot), ctypes.c_int32,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
     "toi_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -118,6 +120,26 @@ def snapshot_struct(snap: dict, device=None) -> Snapshot:
             continue
         if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
             raise TypeError(f"snapshot[{k!r}] must be a contiguous {dt} CUDA tensor")
+    return Snapshot(uvw=_ptr(snap["uvw"]), vis=_ptr(snap["vis"]), flag=_ptr(snap.get("flag")),
+                    weight=_ptr(snap.get("weight")), freq=_ptr(snap["freq"]),
+                    ant1=_ptr(snap.get("ant1")), ant2=_ptr(snap.get("ant2")),
+                    gains=_ptr(snap.get("gains")), n_row=int(snap["uvw"].shape[0]))
+
+
+def host_snapshot_struct(snap: dict) -> Snapshot:
+    """Descriptor of a snapshot whose arrays are torch tensors in host memory
+    (page-locked for asynchronous copies: ``pin_memory()``)."""
+    import torch
+    kinds = {"uvw": torch.float64, "vis": torch.complex64, "freq": torch.float64, "flag": torch.uint8,
+             "weight": torch.float32, "ant1": torch.int32, "ant2": torch.int32, "gains": torch.complex64}
+    for k, dt in kinds.items():
+        t = snap.get(k)
+        if t is None:
+            if k in ("uvw", "vis", "freq") and snap["uvw"].shape[0] > 0:
+                raise ValueError(f"snapshot is missing {k}")
+            continue
+        if not isinstance(t, torch.Tensor) or t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"snapshot[{k!r}] must be a contiguous {dt} host tensor")
     return Snapshot(uvw=_ptr(snap["uvw"]), vis=_ptr(snap["vis"]), flag=_ptr(snap.get("flag")),
                     weight=_ptr(snap.get("weight")), freq=_ptr(snap["freq"]),
                     ant1=_ptr(snap.get("ant1")), ant2=_ptr(snap.get("ant2")),
@@ -211,6 +233,13 @@ class Imager:
         _check(lib().toi_image_batch(self.ctx, arr, len(snaps), _ptr(images_out), _ptr(tlisi_out)),
                self.ctx)
 
+    def ingest(self, host_snaps, images_out, tlisi_out=None):
+        """Image snapshots held in host memory, copies overlapped with the imaging."""
+        arr = (Snapshot * len(host_snaps))(*[host_snapshot_struct(s) for s in host_snaps])
+        self._keep_ingest = (arr, host_snaps)
+        self._sync_stream()
+        _check(lib().toi_ingest(self.ctx, arr, len(host_snaps), _ptr(images_out), _ptr(tlisi_out)), self.ctx)
+
     def profile(self, enable: bool = True):
         """Start (clearing the totals) or stop per-stage HIP-event timing."""
         _check(lib().toi_profile_enable(self.ctx, 1 if enable else 0), self.ctx)
@@ -256,6 +285,22 @@ def to_device(snap: dict, device="cuda") -> dict:
     for k in ("uvw", "vis", "flag", "weight", "freq", "ant1", "ant2", "gains"):
         v = snap.get(k)
         out[k] = None if v is None else torch.from_numpy(np.ascontiguousarray(v)).to(device)
+    return out
+
+
+def to_host(snap: dict, pinned: bool = True) -> dict:
+    """A host snapshot (numpy arrays) as torch host tensors for ``Imager.ingest``,
+    page-locked unless ``pinned`` is False."""
+    import numpy as np
+    import torch
+    out = {}
+    for k in ("uvw", "vis", "flag", "weight", "freq", "ant1", "ant2", "gains"):
+        v = snap.get(k)
+        if v is None:
+            out[k] = None
+            continue
+        t = torch.from_numpy(np.ascontiguousarray(v))
+        out[k] = t.pin_memory() if pinned else t.clone()
     return out
 
 
