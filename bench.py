@@ -244,6 +244,41 @@ def ingest_leg(n_snap, reps, device):
             "ms_if_serial": round(ms_copy + ms_res, 4)}
 
 
+def many_slab_leg(n_snap, reps, device):
+    """The AA2-like many-slab regime (17 slabs x K = 16 = 272 planes, 2048^2 images):
+    ms/snapshot of the plain path and its stages."""
+    import torch
+
+    import synth_inputs as S
+    from paper_2512_06254_amd import toi as T
+    wl = S.WORKLOADS["aa2"]
+    n_slab, K = wl.forced_planes
+    pool = make_pool(wl, 2, device)
+    N, TT = wl.n_pix, wl.n_pix // 32
+    im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K, tile=32,
+                  max_planes=n_slab * K)
+    imgs = torch.zeros((n_snap, N, N), dtype=torch.float32, device=device)
+
+    def run():
+        for i in range(n_snap):
+            im.grid(pool[i % 2])
+            im.image(out=imgs[i])
+            if i >= 2:
+                im.tlisi(imgs[i - 2], imgs[i - 1], imgs[i])
+
+    run()
+    ms = time_events(run, reps) / n_snap
+    im.profile(True)
+    run()
+    prof = im.profile_read()
+    im.profile(False)
+    info = im.plan_info()
+    im.close()
+    return {"workload": "aa2", "baselines": wl.n_row, "channels": wl.n_chan, "correlations": wl.n_corr,
+            "image": f"{N}x{N}", "planes": f"{info['n_slab']} slabs x K={info['K']}", "ms_per_snapshot": round(ms, 4),
+            "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]}}
+
+
 def adjoint_leg(reps, device):
     """Forward image and the hand-written adjoint (vis + gain gradients) on the 1024-channel workload."""
     import torch
@@ -295,6 +330,7 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="snapshots per batched graph launch (0 = skip)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--ingest", type=int, default=8, help="host-resident snapshots per toi_ingest call (0 = skip)")
+    ap.add_argument("--many-slab", type=int, default=4, help="AA2-like 272-plane snapshots timed (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -406,6 +442,9 @@ def main():
     if args.ingest > 0:
         log(f"[bench] ingest leg: {args.ingest} host-resident snapshots per call")
         out["ingest"] = ingest_leg(args.ingest, 2, device)
+    if args.many_slab > 0:
+        log(f"[bench] many-slab leg (AA2-like, 272 planes): {args.many_slab} snapshots")
+        out["many_slab"] = many_slab_leg(args.many_slab, 2, device)
     if not args.no_adjoint:
         log("[bench] adjoint leg")
         out["adjoint"] = adjoint_leg(max(3, args.steps // 4), device)

@@ -93,9 +93,9 @@ def _ch_width(lo_hz, hi_hz, n):
     return (hi_hz - lo_hz) / n
 
 
-# The five workloads: a tiny plain imager, the MeerKAT-shaped single batch,
-# the batched uneven-flag stream, the differentiable imager and the full
-# FIP-TOI run.
+# The workloads: a tiny plain imager, the MeerKAT-shaped single batch, the
+# batched uneven-flag stream, the differentiable imager, an AA2-like
+# many-slab array and the full FIP-TOI run.
 WORKLOADS = {
     "tiny": Workload(
         name="tiny", n_ant=16, diameter_m=1000.0, sigma_h_m=2.0,
@@ -121,6 +121,18 @@ WORKLOADS = {
         n_pix=2048, cell_arcsec=1.5, n_steady=200, flux_law="powerlaw",
         flux_lo=1e-3, flux_hi=1.0, noise_sigma=0.2, n_snap=20,
         forced_planes=(1, 16), seed=3, with_gains=True),
+    # SKA AA2 (MID)-like non-coplanar array (the many-slab regime of the
+    # paper's Chebyshev table: Phi_max ~ 164 gives 17 slabs of K = 16, 272
+    # planes): 65 antennas (2080 baselines) in a 4 km disk (every baseline
+    # inside the uv extent of the 5.3" cells) with 31.1 m rms heights, which
+    # set Phi_max; 128 channels of 1 MHz from 1.2 GHz, a 3 degree field on
+    # 2048^2 pixels, phase centre at declination 0.
+    "aa2": Workload(
+        name="aa2", n_ant=65, diameter_m=4000.0, sigma_h_m=31.1,
+        n_chan=128, freq0_hz=1.2e9, dfreq_hz=1e6, n_corr=4,
+        n_pix=2048, cell_arcsec=3.0 * 3600.0 / 2048, n_steady=16, flux_law="uniform",
+        flux_lo=0.1, flux_hi=1.0, noise_sigma=0.2, n_snap=8,
+        forced_planes=(17, 16), seed=5, dec_deg=0.0),
     "full": Workload(
         name="full", n_ant=64, diameter_m=8000.0, sigma_h_m=5.0,
         n_chan=4096, freq0_hz=856e6, dfreq_hz=_ch_width(856e6, 1712e6, 4096), n_corr=4,

@@ -153,3 +153,19 @@ def test_dense_bins_split_into_work_units():
         print(f"[dense bins, variant {v}] t-plane err {e:.3e}", flush=True)
         assert e <= IMAGE_TOL
     im.close()
+
+
+def test_many_slab_aa2_like_forced_272_planes():
+    # the many-slab regime: 17 slabs x K = 16 = 272 planes (17 plane groups);
+    # the AA2-like array's cells on a 128^2 image
+    wl = S.scaled(S.WORKLOADS["aa2"], n_ant=12, n_chan=32, n_pix=128, n_steady=4)
+    res, *_ = check_snapshot(S.make_snapshot(wl, 0), wl.n_pix, wl.cell_deg, mode=3, n_slab=17, cheb_k=16,
+                             label="aa2 17x16")
+    assert res.plan.planes == 272
+
+
+def test_many_slab_aa2_like_automatic_plan():
+    # heights raised so that the 128^2 field still needs several slabs
+    wl = S.scaled(S.WORKLOADS["aa2"], n_ant=16, n_chan=32, n_pix=128, n_steady=4, sigma_h_m=400.0)
+    res, *_ = check_snapshot(S.make_snapshot(wl, 0), wl.n_pix, wl.cell_deg, mode=3, label="aa2 auto")
+    assert res.plan.n_slab > 1
