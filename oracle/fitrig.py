@@ -18,8 +18,9 @@ pair; per tile the SSIM form of Wang et al. (IEEE TIP 13, 2004) with
 ``tLISI = clamp((1 + S) / 2, 0, 1)`` (1 everywhere when ``L = 0``).
 
 Detection runs over a sliding window of the 16 newest tLISI maps (the
-streaming reading): per tile the DFT power of the mean-removed window at
-f = 1..8, harmonic sums over h in {1, 2, 4, 8} harmonics normalised by sqrt(h),
+streaming reading) or over the whole run's cube of L maps (the paper's
+after-the-run statistic): per tile the DFT power of the mean-removed series at
+f = 1..L/2, harmonic sums over h in {1, 2, 4, 8} harmonics normalised by sqrt(h),
 the non-periodic sum of (1 - tLISI), z-scores over all tiles with the
 population standard deviation, thresholds 5 (periodic) or 4 (non-periodic),
 8-connected components of the flagged tiles and one box per component.
@@ -62,7 +63,8 @@ def tlisi(img_tm2, img_tm1, img_t, tile=32):
 
 
 def periodic_score(series):
-    """max over fundamental f and harmonic count h of (sum_{j<=h, jf<=8} P_{jf}) / sqrt(h)."""
+    """max over fundamental f and harmonic count h of (sum_{j<=h, jf<=n/2} P_{jf}) / sqrt(h),
+    P the DFT power of the mean-removed series of length n."""
     x = np.asarray(series, dtype=np.float64)
     n = x.size
     d = x - x.mean()
@@ -109,7 +111,7 @@ def components8(mask):
 
 
 def window_scores(window):
-    """(periodic z, non-periodic z) maps of a (16, ty, tx) window of tLISI maps."""
+    """(periodic z, non-periodic z) maps of an (L, ty, tx) window or cube of tLISI maps."""
     w = np.asarray(window, dtype=np.float64)
     ny, nx = w.shape[1:]
     per = np.empty((ny, nx))
@@ -121,7 +123,8 @@ def window_scores(window):
 
 
 def detect(window, t, tile=32, z_periodic=5.0, z_nonperiodic=4.0):
-    """Candidate boxes (t, x0, y0, x1, y1) in pixels of one window ending at snapshot t."""
+    """Candidate boxes (t, x0, y0, x1, y1) in pixels of one window (or the whole
+    cube) of tLISI maps ending at snapshot t."""
     zp, zn = window_scores(window)
     mask = (zp > z_periodic) | (zn > z_nonperiodic)
     boxes = []

@@ -77,6 +77,26 @@ def test_periodic_score_closed_form():
     assert fitrig.periodic_score(y) == pytest.approx(2 * (A * 8) ** 2 / math.sqrt(2), rel=1e-12)
 
 
+def test_periodic_score_closed_form_whole_run_length():
+    # the whole-cube statistic: a series of any length L (here 150, not a power
+    # of two); a cosine of integer frequency f0 has P_f0 = (A L / 2)^2 and no
+    # other power, so the best score is h = 1 at f0 unless f0's harmonics add
+    A, L = 0.2, 150
+    tau = np.arange(L)
+    x = 0.9 + A * np.cos(2 * math.pi * 7 * tau / L + 0.4)
+    assert fitrig.periodic_score(x) == pytest.approx((A * L / 2) ** 2, rel=1e-10)
+    # fundamental 5 with harmonics 10, 15, 20: h = 4 collects 4 (A L / 2)^2 / 2
+    y = 0.9 + A * sum(np.cos(2 * math.pi * 5 * j * tau / L) for j in (1, 2, 3, 4))
+    assert fitrig.periodic_score(y) == pytest.approx(4 * (A * L / 2) ** 2 / 2, rel=1e-10)
+    # brute-force DFT power of a random series equals numpy's FFT
+    r = np.random.default_rng(8).random(L)
+    d = r - r.mean()
+    P = np.abs(np.fft.rfft(d)) ** 2
+    best = max(sum(P[j * f] for j in range(1, h + 1) if j * f <= L // 2) / math.sqrt(h)
+               for f in range(1, L // 2 + 1) for h in (1, 2, 4, 8))
+    assert fitrig.periodic_score(r) == pytest.approx(best, rel=1e-9)
+
+
 def test_components_match_scipy_label():
     rng = np.random.default_rng(4)
     for _ in range(20):
