@@ -279,6 +279,30 @@ def many_slab_leg(n_snap, reps, device):
             "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]}}
 
 
+def detect_cube_leg(n_maps, T, reps, device):
+    """Whole-run detection (fitrig_detect_cube) over a synthetic tLISI cube of n_maps maps of
+    T x T tiles (the full run's 4096^2 images with 32-pixel tiles: T = 128), with planted
+    on/off tiles of period 12; ms per cube and the boxes found."""
+    import torch
+
+    from paper_2512_06254_amd import toi as T_
+    gen = torch.Generator(device=device).manual_seed(11)
+    cube = 1.0 - (torch.randn((n_maps, T, T), generator=gen, device=device) * 0.02).abs()
+    tau = torch.arange(n_maps, device=device)
+    onoff = torch.where((tau % 12) < 6, 0.55, 0.95)
+    for (y, x) in [(10, 20), (11, 21), (70, 90)]:
+        cube[:, y, x] = onoff
+    im = T_.Imager(T * 32, 0.001, 1, 1, 1, mode=2, tile=32)
+    boxes, n = im.detect_cube(cube, n_maps - 1)
+    torch.cuda.synchronize()
+    ms = time_events(lambda: im.detect_cube(cube, n_maps - 1), reps)
+    found = int(n.item())
+    out = {"maps": n_maps, "tiles": f"{T}x{T}", "ms_per_cube": round(ms, 3), "boxes_found": found,
+           "boxes": [list(map(int, b)) for b in boxes[:min(found, 8)].cpu().tolist()]}
+    im.close()
+    return out
+
+
 def adjoint_leg(reps, device):
     """Forward image and the hand-written adjoint (vis + gain gradients) on the 1024-channel workload."""
     import torch
@@ -331,6 +355,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--ingest", type=int, default=8, help="host-resident snapshots per toi_ingest call (0 = skip)")
     ap.add_argument("--many-slab", type=int, default=4, help="AA2-like 272-plane snapshots timed (0 = skip)")
+    ap.add_argument("--detect-cube", type=int, default=1500, help="maps of the whole-run detection cube (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -445,6 +470,9 @@ def main():
     if args.many_slab > 0:
         log(f"[bench] many-slab leg (AA2-like, 272 planes): {args.many_slab} snapshots")
         out["many_slab"] = many_slab_leg(args.many_slab, 2, device)
+    if args.detect_cube > 0:
+        log(f"[bench] whole-run detection leg: {args.detect_cube} tLISI maps of 128 x 128 tiles")
+        out["detect_cube"] = detect_cube_leg(args.detect_cube, 128, 3, device)
     if not args.no_adjoint:
         log("[bench] adjoint leg")
         out["adjoint"] = adjoint_leg(max(3, args.steps // 4), device)

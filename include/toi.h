@@ -145,6 +145,20 @@ toi_status fitrig_tlisi(toi_ctx* ctx, const float* img_tm2, const float* img_tm1
 toi_status fitrig_detect(toi_ctx* ctx, const float* window, int32_t t,
                          int32_t* boxes_out, int32_t max_boxes, int32_t* n_boxes_out);
 
+/* FITrig detection over the whole run (Section 2: the Fourier transform of
+ * the tLISI cube along time, harmonic summing, significance, connected
+ * tiles): as fitrig_detect, with the window replaced by the cube of all
+ * n_maps tLISI maps, f32[n_maps][N/tile][N/tile] oldest first (device): per
+ * tile the DFT power of the mean-removed series at f = 1 .. n_maps / 2
+ * (FP64), harmonic sums over h in {1, 2, 4, 8} divided by sqrt(h), maximum
+ * over f and h; the non-periodic score sum(1 - tLISI); then the same
+ * z-scores, thresholds, components and boxes, with t written into each box.
+ * TOI_EINVAL unless 2 <= n_maps <= 5460 (the series and its powers are held in
+ * 64 KB of LDS); TOI_EUNSUPPORTED as for
+ * fitrig_detect. */
+toi_status fitrig_detect_cube(toi_ctx* ctx, const float* cube, int32_t n_maps, int32_t t,
+                              int32_t* boxes_out, int32_t max_boxes, int32_t* n_boxes_out);
+
 /* Several snapshots in one call (uneven sample counts allowed): for each i,
  * toi_grid(snaps[i]) + toi_image(images_out + i*N*N), and for i >= 2 the
  * tLISI map of (i-2, i-1, i) into tlisi_out + (i-2)*(N/tile)^2 (nullable);

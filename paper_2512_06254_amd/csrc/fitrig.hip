@@ -136,15 +136,17 @@ __global__ __launch_bounds__(1024) void k_detect(const float* __restrict__ windo
     double* sp = scores;                       // periodic
     double* snp = scores + n;                  // non-periodic
     double s1p = 0, s2p = 0, s1n = 0, s2n = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double x[kWindow];
-        double np = 0.0;
-        for (int t = 0; t < kWindow; ++t) {
-            x[t] = (double)window[(size_t)t * n + i];
-            np += 1.0 - x[t];
+    if (window) {                              // else the scores are in place (whole-cube detection)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            double x[kWindow];
+            double np = 0.0;
+            for (int t = 0; t < kWindow; ++t) {
+                x[t] = (double)window[(size_t)t * n + i];
+                np += 1.0 - x[t];
+            }
+            sp[i] = periodic_score16(x);
+            snp[i] = np;
         }
-        sp[i] = periodic_score16(x);
-        snp[i] = np;
     }
     __syncthreads();
     // population mean / std in a fixed order: per-thread strided partial sums, then a tree
@@ -228,6 +230,77 @@ __global__ __launch_bounds__(1024) void k_detect(const float* __restrict__ windo
         }
     }
     if (threadIdx.x == 0) *n_boxes = nc;
+}
+
+// Whole-cube scores (the after-the-run statistic over all L maps): one
+// wavefront per tile stages the tile's series x_0..x_{L-1} in LDS (FP64) and
+// its mean; lane l evaluates the DFT power of the mean-removed series at
+// f = 1 + l, 65 + l, ... <= L/2 by Goertzel's recurrence
+// s_t = d_t + 2 cos(2 pi f / L) s_{t-1} - s_{t-2}, |X_f|^2 = s_{L-1}^2 +
+// s_{L-2}^2 - 2 cos(2 pi f / L) s_{L-1} s_{L-2} (Goertzel, 1958), all in FP64;
+// the powers go to LDS, and the lanes take the maximum over f and
+// h in {1, 2, 4, 8} of the harmonic sum / sqrt(h).  Also the non-periodic
+// sum(1 - x).  LDS: 8 L + 8 (L / 2 + 1) bytes.
+__global__ __launch_bounds__(64) void k_cube_scores(const float* __restrict__ cube, int L, int n_tiles,
+                                                    double* __restrict__ scores) {
+    extern __shared__ double sd[];
+    double* x = sd;                            // [L]
+    double* P = sd + L;                        // [L / 2 + 1]
+    const int i = blockIdx.x, lane = threadIdx.x;
+    double sum = 0.0;
+    for (int t = lane; t < L; t += 64) {
+        const double v = (double)cube[(size_t)t * n_tiles + i];
+        x[t] = v;
+        sum += v;
+    }
+    sum = wave_sum(sum);
+    const double mean = sum / L;
+    double np = 0.0;
+    for (int t = lane; t < L; t += 64) np += 1.0 - x[t];
+    np = wave_sum(np);
+    lds_order();
+    const int F = L / 2;
+    for (int f = 1 + lane; f <= F; f += 64) {
+        double sn, cs;
+        sincospi(2.0 * f / L, &sn, &cs);
+        const double c2 = 2.0 * cs;
+        double s1 = 0.0, s2 = 0.0;
+        for (int t = 0; t < L; ++t) {
+            const double s0 = (x[t] - mean) + c2 * s1 - s2;
+            s2 = s1;
+            s1 = s0;
+        }
+        P[f] = s1 * s1 + s2 * s2 - c2 * s1 * s2;
+    }
+    lds_order();
+    double best = -1e300;
+    for (int f = 1 + lane; f <= F; f += 64) {
+        double acc = 0.0;
+        int j = 1;
+        for (int h = 1; h <= 8; h *= 2) {      // h = 1, 2, 4, 8 harmonics
+            for (; j <= h; ++j)
+                if (j * f <= F) acc += P[j * f];
+            best = fmax(best, acc / sqrt((double)h));
+        }
+    }
+    best = wave_max(best);
+    if (lane == 0) {
+        scores[i] = best;
+        scores[n_tiles + i] = np;
+    }
+}
+
+hipError_t launch_detect_cube(toi_ctx* c, const float* cube, int L, int t, int32_t* boxes, int max_boxes,
+                              int32_t* n_boxes) {
+    const int T = c->T;
+    const size_t lds = 2 * (size_t)T * T * sizeof(int32_t);
+    const size_t slds = (size_t)(L + L / 2 + 1) * sizeof(double);
+    if (lds > 128 * 1024 || slds > 64 * 1024) return hipErrorNotSupported;
+    StageTimer timer(c, TOI_STAGE_DETECT);
+    hipLaunchKernelGGL(k_cube_scores, dim3(T * T), dim3(64), slds, c->stream, cube, L, T * T, c->det_scores);
+    hipLaunchKernelGGL(k_detect, dim3(1), dim3(1024), lds, c->stream, nullptr, T, c->p.tile, t, c->det_scores,
+                       c->det_boxes, boxes, max_boxes, n_boxes);
+    return hipGetLastError();
 }
 
 hipError_t launch_detect(toi_ctx* c, const float* window, int t, int32_t* boxes, int max_boxes, int32_t* n_boxes) {

@@ -322,6 +322,16 @@ toi_status fitrig_detect(toi_ctx* c, const float* window, int32_t t, int32_t* bo
     return hip_check(c, launch_detect(c, window, t, boxes, max_boxes, n_boxes), "fitrig_detect");
 }
 
+toi_status fitrig_detect_cube(toi_ctx* c, const float* cube, int32_t n_maps, int32_t t, int32_t* boxes,
+                              int32_t max_boxes, int32_t* n_boxes) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "fitrig_detect_cube: ctx is NULL");
+    if (!cube || !n_boxes || (max_boxes > 0 && !boxes) || max_boxes < 0)
+        return fail(c, TOI_EINVAL, "fitrig_detect_cube: NULL cube/boxes/count or max_boxes < 0");
+    if (n_maps < 2 || n_maps > 5460)
+        return fail(c, TOI_EINVAL, "fitrig_detect_cube: n_maps must be in [2, 5460]");
+    return hip_check(c, launch_detect_cube(c, cube, n_maps, t, boxes, max_boxes, n_boxes), "fitrig_detect_cube");
+}
+
 toi_status toi_plan_info(toi_ctx* c, double V_out[9], double* omega, double* wsum, int32_t* n_slab,
                          int32_t* cheb_k, uint32_t* status) {
     if (!c) return fail(nullptr, TOI_EINVAL, "toi_plan_info: ctx is NULL");

@@ -212,6 +212,8 @@ hipError_t launch_degrid(toi_ctx* ctx, const float* grad_image, const toi_snapsh
 hipError_t launch_tlisi(toi_ctx* ctx, const float* a, const float* b, const float* c, float* out);
 hipError_t launch_detect(toi_ctx* ctx, const float* window, int t, int32_t* boxes, int max_boxes,
                          int32_t* n_boxes);
+hipError_t launch_detect_cube(toi_ctx* ctx, const float* cube, int L, int t, int32_t* boxes, int max_boxes,
+                              int32_t* n_boxes);
 
 // RAII stage timer: records a start/stop event pair on the context's stream
 // when profiling is enabled (toi_ctx.cpp).

@@ -59,6 +59,8 @@ _SIGS = {
     "fitrig_tlisi": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
     "fitrig_detect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_int32, ctypes.c_void_p]),
+    "fitrig_detect_cube": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "toi_image_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Snapshot), ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "toi_ingest": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Snapshot), ctypes.c_int32,
@@ -224,6 +226,17 @@ class Imager:
         self._sync_stream()
         _check(lib().fitrig_detect(self.ctx, _ptr(window.contiguous()), t_index, _ptr(boxes), max_boxes,
                                    _ptr(n)), self.ctx)
+        return boxes, n
+
+    def detect_cube(self, cube, t_index: int, max_boxes: int = 256):
+        """Whole-run detection over a (n_maps, T, T) tLISI cube on the device."""
+        t = self.torch
+        boxes = t.zeros((max_boxes, 5), dtype=t.int32, device=self.device)
+        n = t.zeros((1,), dtype=t.int32, device=self.device)
+        c = cube.contiguous()
+        self._sync_stream()
+        _check(lib().fitrig_detect_cube(self.ctx, _ptr(c), int(c.shape[0]), t_index, _ptr(boxes), max_boxes,
+                                        _ptr(n)), self.ctx)
         return boxes, n
 
     def image_batch(self, snaps, images_out, tlisi_out=None):
