@@ -297,8 +297,24 @@ def detect_cube_leg(n_maps, T, reps, device):
     torch.cuda.synchronize()
     ms = time_events(lambda: im.detect_cube(cube, n_maps - 1), reps)
     found = int(n.item())
+    # then the pair and the full-resolution position of each candidate, in a
+    # synthetic 4096^2 difference with a source in each box
+    bx = boxes[:found]
+    k = im.strongest_map(cube, bx)
+    N = T * 32
+    a = torch.randn((N, N), generator=gen, device=device) * 0.01
+    b = a + torch.randn((N, N), generator=gen, device=device) * 0.01
+    yy, xx = torch.meshgrid(torch.arange(N, device=device), torch.arange(N, device=device), indexing="ij")
+    for row in bx.cpu().tolist():
+        cx, cy = (row[1] + row[3]) / 2 + 0.3, (row[2] + row[4]) / 2 - 0.2
+        b += 0.5 * torch.exp(-0.5 * ((xx - cx) ** 2 + (yy - cy) ** 2) / 1.5 ** 2)
+    pos = im.localise(a, b, bx, 135.0, -40.0)
+    ms_loc = time_events(lambda: im.localise(a, b, bx, 135.0, -40.0), reps)
     out = {"maps": n_maps, "tiles": f"{T}x{T}", "ms_per_cube": round(ms, 3), "boxes_found": found,
-           "boxes": [list(map(int, b)) for b in boxes[:min(found, 8)].cpu().tolist()]}
+           "boxes": [list(map(int, r)) for r in bx[:8].cpu().tolist()],
+           "strongest_map": k[:8].cpu().tolist(),
+           "localise_ms": round(ms_loc, 3), "positions_j1_j2": [[round(p[1], 3), round(p[2], 3)]
+                                                                for p in pos[:8].cpu().tolist()]}
     im.close()
     return out
 

@@ -159,6 +159,35 @@ toi_status fitrig_detect(toi_ctx* ctx, const float* window, int32_t t,
 toi_status fitrig_detect_cube(toi_ctx* ctx, const float* cube, int32_t n_maps, int32_t t,
                               int32_t* boxes_out, int32_t max_boxes, int32_t* n_boxes_out);
 
+/* Full-resolution localisation (Sections 2 and 6) of each candidate box
+ * (boxes: device i32[n_boxes][5] as written by fitrig_detect, pixels,
+ * inclusive) in the difference image img_b - img_a of two time-adjacent
+ * snapshots (device f32[N][N]): subtract the box's lower median, sigma =
+ * 1.4826 x the lower median of |D - median|, source pixels with
+ * s (D - median) > 5 sigma where s is the sign at the pixel of largest
+ * |D - median| (first in row-major order on ties), the 8-connected component
+ * of source pixels containing that pixel, and, with morph != 0, the
+ * Gaussian-like check (>= 3 pixels, intensity-weighted second-moment axis
+ * ratio <= 3, brightest pixel within 1.5 pixels of the centroid).  out
+ * (device f64[n_boxes][8]): valid (0/1), centroid j1, j2 (0-based pixels,
+ * intensity-weighted), RA and Dec in degrees (inverse SIN projection about
+ * ra0/dec0 with l = -cell (j1 - N/2), m = cell (j2 - N/2)), the peak
+ * s (D - median), sigma, and the component's pixel count (-1 for a box
+ * outside the image or above 65536 pixels).  The steps' parameters are
+ * documented readings. */
+toi_status fitrig_localise(toi_ctx* ctx, const float* img_a, const float* img_b, const int32_t* boxes,
+                           int32_t n_boxes, double ra0_deg, double dec0_deg, int32_t morph, double* out);
+
+/* The adjacent pair holding a candidate's strongest change (Section 5.2: the
+ * pair is found by analysing the tLISI cube): for each box, the index k of
+ * the tLISI map of cube (device f32[n_maps][N/tile][N/tile], oldest first)
+ * whose sum over the box's tiles is smallest (FP64, the first k on ties);
+ * map k compares the differences (I_{k+1} - I_k) and (I_{k+2} - I_{k+1}) of
+ * the images it was made from, and the newer difference is the one to
+ * localise.  k_out: device i32[n_boxes]. */
+toi_status fitrig_strongest_map(toi_ctx* ctx, const float* cube, int32_t n_maps, const int32_t* boxes,
+                                int32_t n_boxes, int32_t* k_out);
+
 /* Several snapshots in one call (uneven sample counts allowed): for each i,
  * toi_grid(snaps[i]) + toi_image(images_out + i*N*N), and for i >= 2 the
  * tLISI map of (i-2, i-1, i) into tlisi_out + (i-2)*(N/tile)^2 (nullable);

@@ -290,6 +290,253 @@ __global__ __launch_bounds__(64) void k_cube_scores(const float* __restrict__ cu
     }
 }
 
+// ---------------------------------------------------------------- localisation
+// Full-resolution localisation of a candidate box in the difference image
+// D = img_b - img_a (Sections 2 and 6), one workgroup per box:
+//  - background med = the lower median of the box's n values, element
+//    (n - 1) / 2, and MAD = the lower median of |D - med|, both by an exact
+//    4-pass radix selection (8 bits per pass) on order-preserving keys of the
+//    FP32 values; sigma = 1.4826 MAD;
+//  - the brightest pixel p*: largest |D - med|, the first in row-major order
+//    on ties (one 64-bit maximum of (|r| bits, inverted index)); s = its sign;
+//  - source pixels s (D - med) > 5 sigma (FP64) as LDS flags; the component of
+//    8-connected source pixels reached from p*, grown by sweeps until none
+//    changes;
+//  - FP64 intensity-weighted centroid and second moments (fixed-order sums),
+//    the Gaussian-like check (>= 3 pixels, axis ratio <= 3, p* within 1.5
+//    pixels of the centroid), and RA/Dec of the centroid by the inverse SIN
+//    projection about (ra0, dec0) with l = -cell (xc - N/2), m = cell (yc - N/2).
+// out[8]: valid, xc, yc, ra (deg), dec (deg), s (D - med) at p*, sigma,
+// component pixels (-1: box outside the image or above kLocMaxPixels).
+constexpr int kLocMaxPixels = 65536;
+constexpr int kLocThreads = 256;
+
+__device__ inline uint32_t float_key(float v) {   // order-preserving
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float key_float(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+// k-th smallest key(i), i < n (every thread of the block; ends with a barrier)
+template <typename KeyFn>
+__device__ uint32_t block_select(int n, int k, KeyFn key, uint32_t* hist, int* sel) {
+    uint32_t prefix = 0, mask = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t u = key(i);
+            if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0, b = 0;
+            for (; b < 255; ++b) {
+                if (acc + (int)hist[b] > k) break;
+                acc += (int)hist[b];
+            }
+            sel[0] = b;
+            sel[1] = k - acc;
+        }
+        __syncthreads();
+        prefix |= (uint32_t)sel[0] << shift;
+        mask |= 255u << shift;
+        k = sel[1];
+        __syncthreads();
+    }
+    return prefix;
+}
+
+__device__ inline unsigned long long block_max_u64(unsigned long long v, unsigned long long* red) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long m = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = red[i] > m ? red[i] : m;
+    __syncthreads();
+    return m;
+}
+
+__global__ __launch_bounds__(kLocThreads) void k_localise(const float* __restrict__ img_a,
+                                                          const float* __restrict__ img_b,
+                                                          const int32_t* __restrict__ boxes, int N,
+                                                          double cell_rad, double ra0, double dec0, int morph,
+                                                          double* __restrict__ out) {
+    __shared__ uint8_t flag[kLocMaxPixels];   // bit 0: source pixel, bit 1: reached from p*
+    __shared__ uint32_t hist[256];
+    __shared__ int sel[2];
+    __shared__ double red[kLocThreads / 64];
+    __shared__ unsigned long long redu[kLocThreads / 64];
+    __shared__ int changed;
+    const int32_t* bx = boxes + 5 * blockIdx.x;
+    double* o = out + 8 * blockIdx.x;
+    const int x0 = bx[1], y0 = bx[2], x1 = bx[3], y1 = bx[4];
+    const int w = x1 - x0 + 1, h = y1 - y0 + 1;
+    if (x0 < 0 || y0 < 0 || x1 >= N || y1 >= N || w <= 0 || h <= 0 || (long)w * h > kLocMaxPixels) {
+        if (threadIdx.x == 0) {
+            for (int j = 0; j < 8; ++j) o[j] = 0.0;
+            o[7] = -1.0;
+        }
+        return;
+    }
+    const int n = w * h;
+    auto D = [&](int i) { const size_t q = (size_t)(y0 + i / w) * N + x0 + i % w; return img_b[q] - img_a[q]; };
+    const float med = key_float(block_select(n, (n - 1) / 2, [&](int i) { return float_key(D(i)); }, hist, sel));
+    const float mad = key_float(block_select(n, (n - 1) / 2, [&](int i) { return float_key(fabsf(D(i) - med)); },
+                                             hist, sel));
+    const double sigma = 1.4826 * (double)mad;
+    unsigned long long best = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const unsigned long long kk = ((unsigned long long)__float_as_uint(fabsf(D(i) - med)) << 32) |
+                                      (unsigned long long)(0xffffffffu - (uint32_t)i);
+        best = kk > best ? kk : best;
+    }
+    best = block_max_u64(best, redu);
+    const int ip = (int)(0xffffffffu - (uint32_t)(best & 0xffffffffull));
+    const float rp = D(ip) - med;
+    const double sg = rp >= 0.f ? 1.0 : -1.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const bool src = sg * (double)(D(i) - med) > 5.0 * sigma;
+        flag[i] = (src ? 1 : 0) | ((src && i == ip) ? 2 : 0);
+    }
+    __syncthreads();
+    for (;;) {                                   // grow the component of p*
+        if (threadIdx.x == 0) changed = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            if (flag[i] != 1) continue;          // source pixel not reached yet
+            const int yy = i / w, xx = i % w;
+            bool near = false;
+            for (int dy = -1; dy <= 1 && !near; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int y2 = yy + dy, x2 = xx + dx;
+                    if (y2 >= 0 && y2 < h && x2 >= 0 && x2 < w && (flag[y2 * w + x2] & 2)) {
+                        near = true;
+                        break;
+                    }
+                }
+            if (near) {
+                flag[i] = 3;
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        if (!changed) break;
+        __syncthreads();
+    }
+    double sW = 0, sX = 0, sY = 0, cnt = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (flag[i] == 3) {
+            const double wt = sg * (double)(D(i) - med);
+            sW += wt;
+            sX += wt * (x0 + i % w);
+            sY += wt * (y0 + i / w);
+            cnt += 1.0;
+        }
+    sW = block_sum(sW, red);
+    sX = block_sum(sX, red);
+    sY = block_sum(sY, red);
+    cnt = block_sum(cnt, red);
+    if (cnt == 0.0) {
+        if (threadIdx.x == 0) {
+            o[0] = 0.0; o[1] = o[2] = o[3] = o[4] = __builtin_nan("");
+            o[5] = sg * (double)rp; o[6] = sigma; o[7] = 0.0;
+        }
+        return;
+    }
+    const double xc = sX / sW, yc = sY / sW;
+    double cxx = 0, cyy = 0, cxy = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (flag[i] == 3) {
+            const double wt = sg * (double)(D(i) - med);
+            const double dx = x0 + i % w - xc, dy = y0 + i / w - yc;
+            cxx += wt * dx * dx;
+            cyy += wt * dy * dy;
+            cxy += wt * dx * dy;
+        }
+    cxx = block_sum(cxx, red) / sW;
+    cyy = block_sum(cyy, red) / sW;
+    cxy = block_sum(cxy, red) / sW;
+    if (threadIdx.x == 0) {
+        const double tr = cxx + cyy, det = cxx * cyy - cxy * cxy;
+        const double disc = sqrt(fmax(0.0, tr * tr / 4.0 - det));
+        const double l1 = tr / 2.0 + disc, l2 = tr / 2.0 - disc;
+        const double px = x0 + ip % w, py = y0 + ip / w;
+        const bool ok = cnt >= 3.0 && l2 > 0.0 && sqrt(l1 / l2) <= 3.0 && hypot(px - xc, py - yc) <= 1.5;
+        const double l = -cell_rad * (xc - N / 2), m = cell_rad * (yc - N / 2);
+        const double nn = sqrt(fmax(0.0, 1.0 - l * l - m * m));
+        const double dec = asin(m * cos(dec0) + nn * sin(dec0));
+        double ra = ra0 + atan2(l, nn * cos(dec0) - m * sin(dec0));
+        ra = fmod(ra * (180.0 / kPi), 360.0);
+        if (ra < 0.0) ra += 360.0;
+        o[0] = (ok || !morph) ? 1.0 : 0.0;
+        o[1] = xc;
+        o[2] = yc;
+        o[3] = ra;
+        o[4] = dec * (180.0 / kPi);
+        o[5] = sg * (double)rp;
+        o[6] = sigma;
+        o[7] = cnt;
+    }
+}
+
+// Index of the tLISI map (cube[k], oldest first) with the smallest sum over
+// each box's tiles (the first on ties): one workgroup per box, maps strided
+// over the threads (each thread's maps ascending), FP64 sums over the tiles in
+// row-major order; the minimum sum, then the smallest index holding it.
+__global__ __launch_bounds__(256) void k_strongest_map(const float* __restrict__ cube, int n_maps, int T, int tile,
+                                                       const int32_t* __restrict__ boxes,
+                                                       int32_t* __restrict__ k_out) {
+    __shared__ double red[4];
+    __shared__ int redi[4];
+    const int32_t* bx = boxes + 5 * blockIdx.x;
+    const int tx0 = max(0, bx[1] / tile), ty0 = max(0, bx[2] / tile);
+    const int tx1 = min(T - 1, bx[3] / tile), ty1 = min(T - 1, bx[4] / tile);
+    double best = 1e300;
+    int first = INT_MAX;
+    for (int k = threadIdx.x; k < n_maps; k += blockDim.x) {
+        double sm = 0.0;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) sm += (double)cube[((size_t)k * T + ty) * T + tx];
+        if (sm < best) {
+            best = sm;
+            first = k;
+        }
+    }
+    const double m = block_min(best, red);
+    int cand = best == m ? first : INT_MAX;
+    for (int o = 32; o > 0; o >>= 1) cand = min(cand, __shfl_xor(cand, o, 64));
+    if ((threadIdx.x & 63) == 0) redi[threadIdx.x >> 6] = cand;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = redi[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = min(r, redi[w]);
+        k_out[blockIdx.x] = r;
+    }
+}
+
+hipError_t launch_localise(toi_ctx* c, const float* a, const float* b, const int32_t* boxes, int n_boxes,
+                           double ra0_deg, double dec0_deg, int morph, double* out) {
+    if (n_boxes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_localise, dim3(n_boxes), dim3(kLocThreads), 0, c->stream, a, b, boxes, c->N,
+                       c->p.cell_deg * kPi / 180.0, ra0_deg * kPi / 180.0, dec0_deg * kPi / 180.0, morph, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_strongest_map(toi_ctx* c, const float* cube, int n_maps, const int32_t* boxes, int n_boxes,
+                                int32_t* k_out) {
+    if (n_boxes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_strongest_map, dim3(n_boxes), dim3(256), 0, c->stream, cube, n_maps, c->T, c->p.tile,
+                       boxes, k_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_detect_cube(toi_ctx* c, const float* cube, int L, int t, int32_t* boxes, int max_boxes,
                               int32_t* n_boxes) {
     const int T = c->T;

@@ -322,6 +322,23 @@ toi_status fitrig_detect(toi_ctx* c, const float* window, int32_t t, int32_t* bo
     return hip_check(c, launch_detect(c, window, t, boxes, max_boxes, n_boxes), "fitrig_detect");
 }
 
+toi_status fitrig_localise(toi_ctx* c, const float* img_a, const float* img_b, const int32_t* boxes,
+                           int32_t n_boxes, double ra0_deg, double dec0_deg, int32_t morph, double* out) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "fitrig_localise: ctx is NULL");
+    if (n_boxes < 0 || (n_boxes > 0 && (!img_a || !img_b || !boxes || !out)))
+        return fail(c, TOI_EINVAL, "fitrig_localise: NULL image/boxes/output or n_boxes < 0");
+    return hip_check(c, launch_localise(c, img_a, img_b, boxes, n_boxes, ra0_deg, dec0_deg, morph, out),
+                     "fitrig_localise");
+}
+
+toi_status fitrig_strongest_map(toi_ctx* c, const float* cube, int32_t n_maps, const int32_t* boxes,
+                                int32_t n_boxes, int32_t* k_out) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "fitrig_strongest_map: ctx is NULL");
+    if (n_boxes < 0 || n_maps < 1 || (n_boxes > 0 && (!cube || !boxes || !k_out)))
+        return fail(c, TOI_EINVAL, "fitrig_strongest_map: NULL cube/boxes/output, n_boxes < 0 or n_maps < 1");
+    return hip_check(c, launch_strongest_map(c, cube, n_maps, boxes, n_boxes, k_out), "fitrig_strongest_map");
+}
+
 toi_status fitrig_detect_cube(toi_ctx* c, const float* cube, int32_t n_maps, int32_t t, int32_t* boxes,
                               int32_t max_boxes, int32_t* n_boxes) {
     if (!c) return fail(nullptr, TOI_EINVAL, "fitrig_detect_cube: ctx is NULL");

@@ -214,6 +214,10 @@ hipError_t launch_detect(toi_ctx* ctx, const float* window, int t, int32_t* boxe
                          int32_t* n_boxes);
 hipError_t launch_detect_cube(toi_ctx* ctx, const float* cube, int L, int t, int32_t* boxes, int max_boxes,
                               int32_t* n_boxes);
+hipError_t launch_localise(toi_ctx* ctx, const float* a, const float* b, const int32_t* boxes, int n_boxes,
+                           double ra0_deg, double dec0_deg, int morph, double* out);
+hipError_t launch_strongest_map(toi_ctx* ctx, const float* cube, int n_maps, const int32_t* boxes, int n_boxes,
+                                int32_t* k_out);
 
 // RAII stage timer: records a start/stop event pair on the context's stream
 // when profiling is enabled (toi_ctx.cpp).

@@ -61,6 +61,11 @@ _SIGS = {
                                      ctypes.c_int32, ctypes.c_void_p]),
     "fitrig_detect_cube": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "fitrig_localise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.c_void_p]),
+    "fitrig_strongest_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_void_p]),
     "toi_image_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Snapshot), ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "toi_ingest": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Snapshot), ctypes.c_int32,
@@ -238,6 +243,29 @@ class Imager:
         _check(lib().fitrig_detect_cube(self.ctx, _ptr(c), int(c.shape[0]), t_index, _ptr(boxes), max_boxes,
                                         _ptr(n)), self.ctx)
         return boxes, n
+
+    def localise(self, img_a, img_b, boxes, ra0_deg: float, dec0_deg: float, morph: bool = True):
+        """Positions of the candidates in ``boxes`` (device i32 [n, 5]) in img_b - img_a:
+        a device f64 [n, 8] tensor (valid, j1, j2, ra, dec, peak, sigma, pixels)."""
+        t = self.torch
+        bx = boxes.to(t.int32).contiguous()
+        out = t.zeros((bx.shape[0], 8), dtype=t.float64, device=self.device)
+        self._sync_stream()
+        _check(lib().fitrig_localise(self.ctx, _ptr(img_a.contiguous()), _ptr(img_b.contiguous()), _ptr(bx),
+                                     int(bx.shape[0]), float(ra0_deg), float(dec0_deg), 1 if morph else 0,
+                                     _ptr(out)), self.ctx)
+        return out
+
+    def strongest_map(self, cube, boxes):
+        """Per box, the index of the tLISI map with the smallest sum over its tiles."""
+        t = self.torch
+        bx = boxes.to(t.int32).contiguous()
+        k = t.zeros((bx.shape[0],), dtype=t.int32, device=self.device)
+        c = cube.contiguous()
+        self._sync_stream()
+        _check(lib().fitrig_strongest_map(self.ctx, _ptr(c), int(c.shape[0]), _ptr(bx), int(bx.shape[0]),
+                                          _ptr(k)), self.ctx)
+        return k
 
     def image_batch(self, snaps, images_out, tlisi_out=None):
         arr = (Snapshot * len(snaps))(*[snapshot_struct(s) for s in snaps])
