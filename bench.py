@@ -63,7 +63,6 @@ def make_pool(wl, n_pool, device):
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (dense)
 FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X FP32 matrix cores (dense)
-BF16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X bf16 matrix cores (dense)
 
 
 def grid_flops(wl, P):
@@ -449,12 +448,19 @@ def main():
         ach = grid_flops(wl, P) / (stages[dom]["avg_ms"] * 1e-3) / 1e12
         mfma = bool(variant & 1) and K >= 8
         kname = "k_grid_tiles_mfma" if mfma else "k_grid_tiles"
-        # 16 planes per pass: bf16 matrix instructions (split operands); 8: FP32 ones
-        peak = (FP32_MFMA_PEAK_TFLOPS if variant & 4 else BF16_MFMA_PEAK_TFLOPS) if mfma else FP32_VECTOR_PEAK_TFLOPS
-        roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(ach, 2), "peak": peak,
+        # 16 planes per pass: the products run on the bf16 matrix cores beside the
+        # vector ALU, and the kernel is bound by vector-ALU issue (staging, operand
+        # splits): "alu" against the FP32 vector peak.  8 planes per pass: FP32
+        # matrix instructions, which share the vector ALU on gfx950.
+        bf16 = mfma and not (variant & 4)
+        bound = "alu" if (bf16 or not mfma) else "mfma"
+        peak = FP32_MFMA_PEAK_TFLOPS if bound == "mfma" else FP32_VECTOR_PEAK_TFLOPS
+        roofline = {"bound": bound, "achieved": round(ach, 2), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(ach / peak, 4),
                     "traffic": recorded_traffic(kname) if wl.name == "meerkat" else None,
-                    "kernel": kname, "algorithmic_flops": grid_flops(wl, P)}
+                    "kernel": kname, "algorithmic_flops": grid_flops(wl, P),
+                    "note": ("products on the bf16 matrix cores (3-term splits, FP32 accumulation) beside the "
+                             "vector ALU; bound by vector-ALU issue" if bf16 else None)}
     else:
         ach = sb[dom] / (stages[dom]["avg_ms"] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
