@@ -51,7 +51,11 @@ def test_argument_validation_without_device(lib):
         assert lib.toi_last_error(None)
     assert lib.toi_create(None, None, ctypes.byref(h)) == T.TOI_EINVAL
     for fn, args in (("toi_grid", (None, None)), ("toi_image", (None, None, None)),
-                     ("fitrig_tlisi", (None, None, None, None, None)), ("toi_destroy", (None,))):
+                     ("fitrig_tlisi", (None, None, None, None, None)), ("toi_destroy", (None,)),
+                     ("toi_ingest", (None, None, 1, None, None)),
+                     ("fitrig_detect_cube", (None, None, 16, 0, None, 0, None)),
+                     ("fitrig_localise", (None, None, None, None, 1, 0.0, 0.0, 1, None)),
+                     ("fitrig_strongest_map", (None, None, 4, None, 1, None))):
         code = getattr(lib, fn)(*args)
         assert code == (T.TOI_OK if fn == "toi_destroy" else T.TOI_EINVAL), fn
 
