@@ -245,8 +245,12 @@ toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* w
  * (gridding), TOI_STAGE_FFT_ROWS, TOI_STAGE_FFT_COLS
  * (column FFT + correction + combination), TOI_STAGE_REPROJECT,
  * TOI_STAGE_TLISI, TOI_STAGE_DEGRID (adjoint), TOI_STAGE_BATCH (one whole
- * toi_image_batch graph launch; its kernels are not timed individually).  toi_profile_enable(ctx, 1)
- * creates the events and clears the totals (0 disables recording);
+ * toi_image_batch graph launch; its kernels are not timed individually).
+ * toi_profile_enable(ctx, stage_mask) times the stages whose bit
+ * (1 << TOI_STAGE_x) is set (TOI_PROFILE_ALL: every stage; 0 disables
+ * recording; bits past TOI_NSTAGE are ignored); it creates the events on
+ * first use and clears the totals.  Each timed launch adds two event records
+ * to the stream, so timing fewer stages disturbs the timed work less.
  * toi_profile_read synchronises the stream and writes, per stage, the summed
  * duration in milliseconds and the number of timed launches (host arrays of
  * TOI_NSTAGE entries, each nullable). */
@@ -261,7 +265,8 @@ toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* w
 #define TOI_STAGE_BATCH 8
 #define TOI_STAGE_DETECT 9
 #define TOI_NSTAGE 10
-toi_status toi_profile_enable(toi_ctx* ctx, int32_t enable);
+#define TOI_PROFILE_ALL ((1 << TOI_NSTAGE) - 1)
+toi_status toi_profile_enable(toi_ctx* ctx, int32_t stage_mask);
 toi_status toi_profile_read(toi_ctx* ctx, double* total_ms, int32_t* launches);
 
 /* Message for the last failing call on ctx (or a global one if ctx is NULL). */

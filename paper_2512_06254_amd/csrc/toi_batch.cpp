@@ -54,8 +54,8 @@ extern "C" toi_status toi_image_batch(toi_ctx* c, const toi_snapshot* snaps, int
             if (e != hipSuccess) return hip_check(c, e, "toi_image_batch: capture stream");
         }
         hipStream_t user = c->stream;
-        const bool prof = c->prof_on;
-        c->prof_on = false;                       // no event records inside the graph
+        const uint32_t prof = c->prof_mask;
+        c->prof_mask = 0;                         // no event records inside the graph
         c->stream = c->cap_stream;
         hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
         const size_t NN = (size_t)c->N * c->N, TT = (size_t)c->T * c->T;
@@ -70,7 +70,7 @@ extern "C" toi_status toi_image_batch(toi_ctx* c, const toi_snapshot* snaps, int
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
         c->stream = user;
-        c->prof_on = prof;
+        c->prof_mask = prof;
         if (e == hipSuccess) e = e2;
         if (e != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);

@@ -84,7 +84,7 @@ void es_correction_table(int N, int M, double* out) {
 }
 
 StageTimer::StageTimer(toi_ctx* ctx, int stage) : c(ctx), slot(-1) {
-    if (!c->prof_on || c->prof_n >= c->prof_stage.size()) return;
+    if (!((c->prof_mask >> stage) & 1u) || c->prof_n >= c->prof_stage.size()) return;
     slot = (int)c->prof_n++;
     c->prof_stage[slot] = stage;
     (void)hipEventRecord(c->prof_ev[2 * slot], c->stream);
@@ -365,11 +365,11 @@ toi_status toi_plan_info(toi_ctx* c, double V_out[9], double* omega, double* wsu
     return TOI_OK;
 }
 
-toi_status toi_profile_enable(toi_ctx* c, int32_t enable) {
+toi_status toi_profile_enable(toi_ctx* c, int32_t stage_mask) {
     if (!c) return fail(nullptr, TOI_EINVAL, "toi_profile_enable: ctx is NULL");
-    c->prof_on = enable != 0;
+    c->prof_mask = (uint32_t)stage_mask & ((1u << TOI_NSTAGE) - 1u);
     c->prof_n = 0;
-    if (c->prof_on && c->prof_ev.empty()) {
+    if (c->prof_mask && c->prof_ev.empty()) {
         const size_t cap = 8192;
         c->prof_ev.resize(2 * cap);
         c->prof_stage.assign(cap, 0);
@@ -415,8 +415,8 @@ toi_status toi_tune(toi_ctx* c, const toi_snapshot* s, int32_t* variant_out, flo
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    const bool prof = c->prof_on;
-    c->prof_on = false;
+    const uint32_t prof = c->prof_mask;
+    c->prof_mask = 0;
     int best = c->tuning;
     float best_ms = 1e30f;
     for (int v = 0; v < TOI_TUNE_VARIANTS && e == hipSuccess; ++v) {
@@ -438,7 +438,7 @@ toi_status toi_tune(toi_ctx* c, const toi_snapshot* s, int32_t* variant_out, flo
             best = v;
         }
     }
-    c->prof_on = prof;
+    c->prof_mask = prof;
     c->tuning = best;
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);

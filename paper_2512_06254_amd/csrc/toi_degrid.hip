@@ -303,15 +303,7 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                                                      const int4* __restrict__ units,
                                                      const float2* __restrict__ gg, float* __restrict__ gx) {
     typedef float v16 __attribute__((ext_vector_type(16)));
-    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-    auto split_bf16 = [](const float* x, bf16x8& hi, bf16x8& lo) __attribute__((always_inline)) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const __bf16 t = (__bf16)x[e];
-            hi[e] = t;
-            lo[e] = (__bf16)(x[e] - (float)t);
-        }
-    };
+    typedef bf16x8_t bf16x8;
     __shared__ float sw[64 * 16];      // compacted samples: weights at tile columns 0..7, rows 0..7
     __shared__ float sT[64 * 16];      // T_{k0 + k}(s), zero for k >= nk
     __shared__ int sidx[64];           // sample index r * n_chan + c
@@ -351,7 +343,7 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                     v[e] = col < 16 ? gv.x : gv.y;
                 }
             }
-            split_bf16(v, gh[c4], gl[c4]);
+            split_bf16x8(v, gh[c4], gl[c4]);
         }
         for (int it = b0; it < b1; ++it) {
             const int item = list[it];
@@ -414,7 +406,7 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
 #pragma unroll
                     for (int e = 0; e < 8; ++e) a[e] = wx[e] * wr;
                     bf16x8 ah, al;
-                    split_bf16(a, ah, al);
+                    split_bf16x8(a, ah, al);
                     h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, gh[c4], h, 0, 0, 0);
                     h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, gl[c4], h, 0, 0, 0);
                     h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, gh[c4], h, 0, 0, 0);

@@ -21,6 +21,29 @@ __device__ inline void lds_order() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Eight FP32 values as bf16 pairs x = hi + lo: hi = bf16(x) (round to
+// nearest even), lo = bf16(x - hi).  Two values are converted per
+// instruction; hi is widened back to FP32 by bit shifts of the packed word
+// (element 2w is the low half of word w), so the residual x - hi is exact
+// (and fused into an FMA where x is a product).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+__device__ inline void split_bf16x8(const float* x, bf16x8_t& hi, bf16x8_t& lo) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    u4 h, l;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const f2 v = {x[2 * w], x[2 * w + 1]};
+        const unsigned p = __builtin_bit_cast(unsigned, __builtin_convertvector(v, b2));
+        const f2 r = {x[2 * w] - __uint_as_float(p << 16), x[2 * w + 1] - __uint_as_float(p & 0xffff0000u)};
+        h[w] = p;
+        l[w] = __builtin_bit_cast(unsigned, __builtin_convertvector(r, b2));
+    }
+    hi = __builtin_bit_cast(bf16x8_t, h);
+    lo = __builtin_bit_cast(bf16x8_t, l);
+}
+
 // Sum over a 64-lane wavefront with DPP row shifts and row broadcasts (fixed
 // order); the total is returned to every lane (from lane 63).
 template <int CTRL, int ROWS>

@@ -597,7 +597,8 @@ constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
 // k_items (cell, offsets, slab, Chebyshev argument, g x); each next item's
 // records are loaded during the current walk.  LDS: staging of the item's
 // active samples, compacted (kernel weights at the tile's eight columns and
-// eight rows, zero outside the footprint, the NPL Chebyshev values and g x; B =
+// eight rows, zero outside the footprint, the NPL Chebyshev values and g x,
+// which is 0 in the padding slots; B =
 // T_k Re/Im(g x) is formed in the walk, which keeps the staging at 8.5 KB per
 // wave), then the write-out buffer.
 template <int NCOL>
@@ -613,18 +614,10 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
     constexpr int kQuad = NCOL == 32 ? 16 : 4; // samples per step of the walk
     typedef float acc_t __attribute__((ext_vector_type(NREG)));
     typedef float f32x16 __attribute__((ext_vector_type(16)));
-    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+    typedef bf16x8_t bf16x8;
     auto ld8 = [](const float* p, float* o) __attribute__((always_inline)) {
         const float4 u = reinterpret_cast<const float4*>(p)[0], w = reinterpret_cast<const float4*>(p)[1];
         o[0] = u.x; o[1] = u.y; o[2] = u.z; o[3] = u.w; o[4] = w.x; o[5] = w.y; o[6] = w.z; o[7] = w.w;
-    };
-    auto split_bf16 = [](const float* x, bf16x8& hi, bf16x8& lo) __attribute__((always_inline)) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const __bf16 h = (__bf16)x[e];
-            hi[e] = h;
-            lo[e] = (__bf16)(x[e] - (float)h);
-        }
     };
     extern __shared__ float lds[];
     const int tiles = NT * NT;
@@ -637,7 +630,7 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
     float* sx = lds;                           // 8 rows x 68: kernel weight at tile column i
     float* sy = sx + 8 * 68;                   // 8 rows x 64: kernel weight at tile row i
     float* sV = sy + 8 * 64;                   // 2 rows x 64: Re, Im of g x
-    float* sT = sV + 2 * 64;                   // NPL rows x 68: T_{k0 + k}(s), 0 for k >= nk
+    float* sT = sV + 2 * 64;                   // NPL rows x 68: T_{k0 + k}(s)
     const int lane = threadIdx.x;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & (NCOL - 1);
@@ -693,22 +686,27 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
         const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(amask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)amask, 0));
         const int q = act ? below : n_act + (lane - below);
         if (q < n4) {
+            // A padding slot (inactive lane) gets g x = 0, which zeroes its B
+            // row; its other fields are made finite and are otherwise unused.
+            // Chebyshev orders past the group's (k >= nk) fill B columns whose
+            // sums are never written out.
+            const float oxa = act ? ox : 0.f, oya = act ? oy : 0.f, ssa = act ? ss : 0.f;
             // weights at the tile's columns / rows i = 0..7 (0 outside the footprint)
             float wxy[16];
-            tile_axis_weights(tx * kTile, ix, ox, M, wxy);
-            tile_axis_weights(ty * kTile, iy, oy, M, wxy + 8);
+            tile_axis_weights(tx * kTile, ix, oxa, M, wxy);
+            tile_axis_weights(ty * kTile, iy, oya, M, wxy + 8);
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                sx[r * 68 + q] = act ? wxy[r] : 0.f;
-                sy[r * 64 + q] = act ? wxy[8 + r] : 0.f;
+                sx[r * 68 + q] = wxy[r];
+                sy[r * 64 + q] = wxy[8 + r];
             }
             // Chebyshev values T_{k0 + k}(s) of the group's orders, and g x
             float t, tm1;
-            cheb_start(ss, k0, t, tm1);
+            cheb_start(ssa, k0, t, tm1);
 #pragma unroll
             for (int k = 0; k < NPL; ++k) {
-                sT[k * 68 + q] = act && k < nk ? t : 0.f;
-                const float tn = 2.f * ss * t - tm1;
+                sT[k * 68 + q] = t;
+                const float tn = 2.f * ssa * t - tm1;
                 tm1 = t;
                 t = tn;
             }
@@ -743,9 +741,9 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
                     b[e] = t[e] * v[e];
                 }
                 bf16x8 a0h, a0l, a1h, a1l, bh, bl;
-                split_bf16(a0, a0h, a0l);
-                split_bf16(a1, a1h, a1l);
-                split_bf16(b, bh, bl);
+                split_bf16x8(a0, a0h, a0l);
+                split_bf16x8(a1, a1h, a1l);
+                split_bf16x8(b, bh, bl);
                 acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, bh, acc_lo, 0, 0, 0);
                 acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, bh, acc_hi, 0, 0, 0);
                 acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, bl, acc_lo, 0, 0, 0);

@@ -180,7 +180,7 @@ struct toi_ctx {
     int4* det_boxes;      // [T*T] component bounding boxes in tiles
 
     // per-stage timing (measurement only)
-    bool prof_on;
+    uint32_t prof_mask;   // stages whose launches are timed (bit s = stage s)
     std::vector<hipEvent_t> prof_ev;      // pairs (start, stop)
     std::vector<int> prof_stage;          // stage of each recorded pair
     size_t prof_n;

@@ -176,6 +176,9 @@ class Imager:
         with torch.cuda.device(self.device):
             _check(L.toi_create(ctypes.byref(p), ctypes.c_void_p(self._stream()), ctypes.byref(h)))
         self.ctx = h
+        # held by the instance: at interpreter exit the module's globals may be
+        # cleared before a remaining Imager is collected
+        self._destroy = L.toi_destroy
 
     def _stream(self):
         return self.torch.cuda.current_stream(self.device).cuda_stream
@@ -185,7 +188,7 @@ class Imager:
 
     def close(self):
         if getattr(self, "ctx", None):
-            lib().toi_destroy(self.ctx)
+            self._destroy(self.ctx)
             self.ctx = None
 
     __del__ = close
@@ -281,9 +284,13 @@ class Imager:
         self._sync_stream()
         _check(lib().toi_ingest(self.ctx, arr, len(host_snaps), _ptr(images_out), _ptr(tlisi_out)), self.ctx)
 
-    def profile(self, enable: bool = True):
-        """Start (clearing the totals) or stop per-stage HIP-event timing."""
-        _check(lib().toi_profile_enable(self.ctx, 1 if enable else 0), self.ctx)
+    def profile(self, enable: bool = True, stages=None):
+        """Start (clearing the totals) or stop per-stage HIP-event timing: every
+        stage, or only the named ones (names as in ``STAGES``)."""
+        mask = 0
+        if enable:
+            mask = (1 << len(STAGES)) - 1 if stages is None else sum(1 << STAGES.index(n) for n in stages)
+        _check(lib().toi_profile_enable(self.ctx, mask), self.ctx)
 
     def profile_read(self) -> dict:
         """Synchronise; {stage: (total ms, launches)} of the timed stages."""
