@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "toi_fft.h"
 #include "toi_internal.h"
 
 namespace {
@@ -207,7 +208,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
         {(void**)&c->plan, sizeof(DevPlan)},
         {(void**)&c->rows, std::max<size_t>(1, p.n_row_max) * sizeof(RowStat)},
         {(void**)&c->corr, N * sizeof(float)},
-        {(void**)&c->twiddle, M * sizeof(float2)},
+        {(void**)&c->twiddle, (size_t)fft_twiddle_entries((int)M) * sizeof(float2)},
         {(void**)&c->tiles, T * T * sizeof(TileStat)},
         {(void**)&c->scratch_d, 64 * sizeof(double)},
         {(void**)&c->scratch_i, 64 * sizeof(int32_t)},
@@ -232,9 +233,19 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
         const double a = 2.0 * kPi * (double)n / (double)M;
         tw[n] = make_float2((float)std::cos(a), (float)std::sin(a));
     }
+    // stage tables of radix 8, 16, 32 after the full-period table: entry
+    // (stage NS, k, r) = tw[r k M / (NS E)]
+    for (int E = 8; E <= 32; E *= 2)
+        for (int ns = fft_first_radix((int)M, E); ns < (int)M; ns *= E)
+            for (int k = 0; k < ns; ++k)
+                for (int r = 1; r < E; ++r) tw.push_back(tw[(size_t)r * k * (M / ((size_t)ns * E))]);
+    if (tw.size() != (size_t)fft_twiddle_entries((int)M)) {
+        toi_destroy(c);
+        return fail(nullptr, TOI_EINVAL, "toi_create: twiddle table size mismatch");
+    }
     DevPlan zero{};
     hipError_t e = hipMemcpy(c->corr, corr_f.data(), N * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->twiddle, tw.data(), M * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->twiddle, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->plan, &zero, sizeof(DevPlan), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         toi_destroy(c);

@@ -80,8 +80,22 @@ __host__ __device__ constexpr int fft_radix_at(int M, int E, int NS) {
 // e^{+2 pi i r k / (NS E)}, kept at k (E - 1) + r - 1.  Consecutive lanes then
 // read addresses E - 1 values apart, which spreads them over the banks (a
 // single M-entry table read at r k M / (NS E) puts up to 16 lanes in one
-// bank).  The tables hold about M entries in total, built from the
-// full-period table tw[n] = e^{+2 pi i n / M} in HBM.
+// bank).  The tables hold about M entries in total.  In HBM the twiddle
+// buffer holds the full-period table e^{+2 pi i n / M} (n < M) followed by
+// the stage tables of radix 8, 16 and 32 in this order (built on the host),
+// so that a workgroup fills its LDS tables with a plain copy.
+__host__ __device__ constexpr int fft_stage_table_size(int M, int E) {
+    int o = 0;
+    for (int ns = fft_first_radix(M, E); ns < M; ns *= E) o += ns * (E - 1);
+    return o;
+}
+__host__ __device__ constexpr int fft_stage_table_offset(int M, int E) {   // E in {8, 16, 32}; 64: the end
+    int o = M;
+    for (int e = 8; e < E; e *= 2) o += fft_stage_table_size(M, e);
+    return o;
+}
+__host__ __device__ constexpr int fft_twiddle_entries(int M) { return fft_stage_table_offset(M, 64); }
+
 template <int M, int E>
 struct FftTw {
     static constexpr int R1 = fft_first_radix(M, E);
@@ -93,18 +107,18 @@ struct FftTw {
     static constexpr int size() { return off(M); }
 };
 
-// Build the stage tables in LDS (all threads; ends with a barrier).
+// Fill the stage tables in LDS from the twiddle buffer (all threads; ends with
+// a barrier).  Offsets and sizes are even: 16-byte reads.
 template <int M, int E>
 __device__ inline void load_twiddles(float2* tw_s, const float2* __restrict__ tw) {
-    using TW = FftTw<M, E>;
-    for (int i = threadIdx.x; i < TW::size(); i += blockDim.x) {
-        int ns = TW::R1, o = 0;
-        while (i >= o + ns * (E - 1)) {
-            o += ns * (E - 1);
-            ns *= E;
-        }
-        const int k = (i - o) / (E - 1), r = (i - o) % (E - 1) + 1;
-        tw_s[i] = tw[(r * k * (M / (ns * E))) & (M - 1)];
+    static_assert(E == 8 || E == 16 || E == 32, "stage tables exist for radix 8, 16 and 32");
+    constexpr int S = FftTw<M, E>::size();
+    static_assert(S == fft_stage_table_size(M, E) && S % 2 == 0 && fft_stage_table_offset(M, E) % 2 == 0, "");
+    const float4* src = reinterpret_cast<const float4*>(tw + fft_stage_table_offset(M, E));
+    for (int i = threadIdx.x; i < S / 2; i += blockDim.x) {
+        const float4 a = src[i];
+        tw_s[2 * i] = make_float2(a.x, a.y);
+        tw_s[2 * i + 1] = make_float2(a.z, a.w);
     }
     __syncthreads();
 }
