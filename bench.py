@@ -94,10 +94,21 @@ def stage_bytes(wl, P, with_flags):
     }
 
 
-def recorded_traffic(kernel="k_grid_tiles", source="toi_grid.hip", workload="meerkat"):
-    """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (profiles/), or None
-    when the kernel's source has changed since the counters were taken."""
+GRIDDER_SOURCES = ("toi_grid.hip", "toi_grid.h", "toi_device.h")
+
+
+def sources_digest(names=GRIDDER_SOURCES):
+    """First 16 hex digits of the SHA-256 of the named kernel sources, concatenated."""
     import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        h.update(open(os.path.join(ROOT, "paper_2512_06254_amd", "csrc", n), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel="k_grid_tiles", sources=GRIDDER_SOURCES, workload="meerkat"):
+    """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (profiles/), or None
+    when the kernel's sources have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
@@ -106,9 +117,8 @@ def recorded_traffic(kernel="k_grid_tiles", source="toi_grid.hip", workload="mee
         if line.startswith(("traffic_bytes ", "source_sha256 ")):
             key, val = line.split(":", 1)
             rec[key.strip()] = val.strip()
-    src = os.path.join(ROOT, "paper_2512_06254_amd", "csrc", source)
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get(f"source_sha256 {source}") != digest or f"traffic_bytes {kernel}" not in rec:
+    key = "source_sha256 " + "+".join(sources)
+    if rec.get(key) != sources_digest(sources) or f"traffic_bytes {kernel}" not in rec:
         return None
     return int(rec[f"traffic_bytes {kernel}"])
 
