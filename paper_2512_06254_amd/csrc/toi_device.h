@@ -137,17 +137,23 @@ __device__ inline float es_kernel(float z) {
 // Kernel weights of one footprint axis at the eight cells c0 + i (i = 0..7)
 // of an aligned 8-cell tile: footprint start s (cell index), offset o of the
 // sample from s in (3, 4], grid side M (a power of two).  Cell c lies at
-// footprint position d = (c - s) mod M and gets psi((d - o) / 4) for d < 8, 0
-// otherwise.  Computed for all eight cells without branches (the kernel is
-// evaluated everywhere, then masked).
+// footprint position d = (c - s) mod M (taken in [-M/2, M/2)) and gets
+// psi((d - o) / 4) where |d - o| <= 4, 0 elsewhere.  The footprint cells
+// d = 0..7 are exactly those, except at o = 4 exactly (or o rounded to 3),
+// where one more cell lies on |z| = 1 and gets psi(1) = e^-beta (about 1e-8).
+// No index test: outside |z| <= 1 the square root of 1 - z^2 < 0 is NaN,
+// the exponential keeps it, and the maximum with 0 returns 0 (maxNum returns
+// the operand that is not NaN).  o must be finite.
 __device__ inline void tile_axis_weights(int c0, int s, float o, int M, float w[8]) {
+    constexpr float beta_log2e = 18.4f * 1.4426950408889634f;
     int b = (c0 - s) & (M - 1);
     if (b >= (M >> 1)) b -= M;                      // footprint position of cell c0, signed
     const float z0 = ((float)b - o) * 0.25f;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const float e = es_kernel(z0 + 0.25f * (float)i);
-        w[i] = (unsigned)(b + i) < 8u ? e : 0.f;
+        const float z = z0 + 0.25f * (float)i;
+        const float r = __builtin_amdgcn_sqrtf(__builtin_fmaf(-z, z, 1.0f));   // NaN outside |z| <= 1
+        w[i] = fmaxf(__builtin_amdgcn_exp2f(__builtin_fmaf(beta_log2e, r, -beta_log2e)), 0.0f);
     }
 }
 
