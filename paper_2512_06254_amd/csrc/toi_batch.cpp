@@ -4,6 +4,11 @@
 // map of the three youngest images) is captured once for a given set of
 // snapshot descriptors and outputs, instantiated, cached in the context and
 // replayed on the caller's stream; a different descriptor set recaptures.
+// With two or more snapshots the chain runs in two lanes, as the pipeline of
+// Section 4.1 overlaps its stages: the prep and binning of snapshot i + 1
+// (lane B, writing the other of two per-snapshot sets) run while snapshot i is
+// gridded and transformed (lane A).  Lane B waits until the transform of
+// snapshot i - 1, the last reader of that set, has finished.
 // No host synchronisation and no allocation happen inside the graph.
 #include <hip/hip_runtime.h>
 
@@ -49,24 +54,68 @@ extern "C" toi_status toi_image_batch(toi_ctx* c, const toi_snapshot* snaps, int
     key = fnv1a(key, &tlisi_out, sizeof(tlisi_out));
 
     if (!(c->batch_exec && c->batch_key == key)) {
+        const bool two = n >= 2;
         if (!c->cap_stream) {
             hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
             if (e != hipSuccess) return hip_check(c, e, "toi_image_batch: capture stream");
         }
+        if (two && !c->cap_stream2) {
+            hipError_t e = hipStreamCreateWithFlags(&c->cap_stream2, hipStreamNonBlocking);
+            for (int k = 0; k < 4 && e == hipSuccess; ++k)
+                e = hipEventCreateWithFlags(&c->batch_ev[k], hipEventDisableTiming);
+            if (e != hipSuccess) return hip_check(c, e, "toi_image_batch: second lane");
+        }
+        if (two && !c->alt_ready) {   // the second per-snapshot set, same sizes as the first
+            size_t fb[14];
+            front_bytes(c, fb);
+            toi_front& a = c->alt;
+            void** ptrs[14] = {(void**)&a.plan, (void**)&a.rows, (void**)&a.items, (void**)&a.recs,
+                               (void**)&a.bin_count, (void**)&a.bin_off, (void**)&a.bin_cursor,
+                               (void**)&a.bin_list, (void**)&a.bin_order, (void**)&a.bin_aux, (void**)&a.units,
+                               (void**)&a.tile_bits, (void**)&a.row_bits, (void**)&a.scratch_i};
+            for (int k = 0; k < 14; ++k)
+                if (!*ptrs[k] && hipMalloc(ptrs[k], fb[k]) != hipSuccess)
+                    return fail(c, TOI_ENOMEM, "toi_image_batch: second per-snapshot set allocation failed");
+            c->alt_ready = true;
+        }
         hipStream_t user = c->stream;
         const uint32_t prof = c->prof_mask;
         c->prof_mask = 0;                         // no event records inside the graph
-        c->stream = c->cap_stream;
-        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+        hipStream_t A = c->cap_stream, B = c->cap_stream2;
+        hipEvent_t* ev = c->batch_ev;             // [0] fork / join, [1] set ready, [2 + k] set k free
+        c->stream = A;
+        hipError_t e = hipStreamBeginCapture(A, hipStreamCaptureModeRelaxed);
+        if (two && e == hipSuccess) e = hipEventRecord(ev[0], A);
+        if (two && e == hipSuccess) e = hipStreamWaitEvent(B, ev[0], 0);
         const size_t NN = (size_t)c->N * c->N, TT = (size_t)c->T * c->T;
+        bool swapped = false;
         for (int i = 0; i < n && e == hipSuccess; ++i) {
-            e = launch_prep(c, snaps[i]);
-            if (e == hipSuccess) e = launch_grid(c, snaps[i]);
+            if (two && ((i & 1) != 0) != swapped) {   // odd snapshots use the second set
+                front_swap(c);
+                swapped = !swapped;
+            }
+            if (two) {
+                c->stream = B;
+                if (i >= 2) e = hipStreamWaitEvent(B, ev[2 + (i & 1)], 0);
+                if (e == hipSuccess) e = launch_prep(c, snaps[i]);
+                if (e == hipSuccess) e = launch_bin(c, snaps[i]);
+                if (e == hipSuccess) e = hipEventRecord(ev[1], B);
+                c->stream = A;
+                if (e == hipSuccess) e = hipStreamWaitEvent(A, ev[1], 0);
+            } else {
+                e = launch_prep(c, snaps[i]);
+                if (e == hipSuccess) e = launch_bin(c, snaps[i]);
+            }
+            if (e == hipSuccess) e = launch_gridder(c, snaps[i]);
             if (e == hipSuccess) e = launch_image(c, images_out + i * NN, nullptr);
+            if (two && e == hipSuccess) e = hipEventRecord(ev[2 + (i & 1)], A);
             if (e == hipSuccess && tlisi_out && i >= 2)
                 e = launch_tlisi(c, images_out + (i - 2) * NN, images_out + (i - 1) * NN, images_out + i * NN,
                                  tlisi_out + (i - 2) * TT);
         }
+        if (swapped) front_swap(c);
+        if (two && e == hipSuccess) e = hipEventRecord(ev[0], B);   // join lane B
+        if (two && e == hipSuccess) e = hipStreamWaitEvent(A, ev[0], 0);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
         c->stream = user;

@@ -95,6 +95,43 @@ StageTimer::~StageTimer() {
     if (slot >= 0) (void)hipEventRecord(c->prof_ev[2 * slot + 1], c->stream);
 }
 
+void front_bytes(const toi_ctx* c, size_t out[14]) {
+    const toi_params& p = c->p;
+    const size_t NT = c->NT, NG = c->NG_max, words = (NT + 31) / 32;
+    out[0] = sizeof(DevPlan);
+    out[1] = std::max<size_t>(1, p.n_row_max) * sizeof(RowStat);
+    out[2] = (size_t)c->n_items_max * sizeof(ItemBox);
+    out[3] = std::max<size_t>(1, (size_t)p.n_row_max * p.n_chan) * sizeof(SampleRec);
+    out[4] = NG * NT * NT * sizeof(int32_t);                                              // bin_count
+    out[5] = (NG * NT * NT + 1) * sizeof(int32_t);                                        // bin_off
+    out[6] = NG * NT * NT * sizeof(int32_t);                                              // bin_cursor
+    out[7] = (size_t)c->bin_cap * sizeof(int32_t);                                        // bin_list
+    out[8] = NG * NT * NT * sizeof(int32_t);                                              // bin_order
+    out[9] = (64 + (NG * NT * NT + kScanBlock - 1) / kScanBlock) * sizeof(int32_t);       // bin_aux
+    out[10] = (size_t)kSplitSlots * sizeof(int4);                                         // units
+    out[11] = NG * NT * words * sizeof(uint32_t);                                         // tile_bits
+    out[12] = NG * words * sizeof(uint32_t);                                              // row_bits
+    out[13] = 64 * sizeof(int32_t);                                                       // scratch_i
+}
+
+void front_swap(toi_ctx* c) {
+    toi_front& a = c->alt;
+    std::swap(c->plan, a.plan);
+    std::swap(c->rows, a.rows);
+    std::swap(c->items, a.items);
+    std::swap(c->recs, a.recs);
+    std::swap(c->bin_count, a.bin_count);
+    std::swap(c->bin_off, a.bin_off);
+    std::swap(c->bin_cursor, a.bin_cursor);
+    std::swap(c->bin_list, a.bin_list);
+    std::swap(c->bin_order, a.bin_order);
+    std::swap(c->bin_aux, a.bin_aux);
+    std::swap(c->units, a.units);
+    std::swap(c->tile_bits, a.tile_bits);
+    std::swap(c->row_bits, a.row_bits);
+    std::swap(c->scratch_i, a.scratch_i);
+}
+
 }  // namespace toi
 
 using namespace toi;
@@ -184,34 +221,35 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
     c->NG_max = std::max(1, c->P_cap);   // every group holds at least one plane
     c->n_items_max = std::max(1, p.n_row_max * ((p.n_chan + kItemChans - 1) / kItemChans));
     c->bin_cap = c->n_items_max * 32 + 4096;
-    const size_t NT = c->NT, NG = c->NG_max, words = (NT + 31) / 32;
+    size_t fb[14];
+    front_bytes(c, fb);
     struct Alloc { void** ptr; size_t bytes; };
     Alloc allocs[] = {
-        {(void**)&c->items, (size_t)c->n_items_max * sizeof(ItemBox)},
-        {(void**)&c->recs, std::max<size_t>(1, (size_t)p.n_row_max * p.n_chan) * sizeof(SampleRec)},
+        {(void**)&c->plan, fb[0]},
+        {(void**)&c->rows, fb[1]},
+        {(void**)&c->items, fb[2]},
+        {(void**)&c->recs, fb[3]},
+        {(void**)&c->bin_count, fb[4]},
+        {(void**)&c->bin_off, fb[5]},
+        {(void**)&c->bin_cursor, fb[6]},
+        {(void**)&c->bin_list, fb[7]},
+        {(void**)&c->bin_order, fb[8]},
+        {(void**)&c->bin_aux, fb[9]},
+        {(void**)&c->units, fb[10]},
+        {(void**)&c->tile_bits, fb[11]},
+        {(void**)&c->row_bits, fb[12]},
+        {(void**)&c->scratch_i, fb[13]},
         {(void**)&c->gx, std::max<size_t>(1, (size_t)p.n_row_max * p.n_chan) * sizeof(float2)},
-        {(void**)&c->bin_count, NG * NT * NT * sizeof(int32_t)},
-        {(void**)&c->bin_off, (NG * NT * NT + 1) * sizeof(int32_t)},
-        {(void**)&c->bin_cursor, NG * NT * NT * sizeof(int32_t)},
-        {(void**)&c->bin_list, (size_t)c->bin_cap * sizeof(int32_t)},
-        {(void**)&c->bin_order, NG * NT * NT * sizeof(int32_t)},
-        {(void**)&c->bin_aux, (64 + (NG * NT * NT + kScanBlock - 1) / kScanBlock) * sizeof(int32_t)},
-        {(void**)&c->units, (size_t)kSplitSlots * sizeof(int4)},
         {(void**)&c->split_part, (size_t)kSplitSlots * kPartFloats * sizeof(float)},
-        {(void**)&c->tile_bits, NG * NT * words * sizeof(uint32_t)},
-        {(void**)&c->row_bits, NG * words * sizeof(uint32_t)},
         {(void**)&c->grid, P * M * M * sizeof(float2)},
         {(void**)&c->hbuf, P * N * M * sizeof(float2)},
         {(void**)&c->tplane_t, N * N * sizeof(float)},
         {(void**)&c->adj_tp, N * N * sizeof(float)},
         {(void**)&c->item_gain, (size_t)c->n_items_max * sizeof(double2)},
-        {(void**)&c->plan, sizeof(DevPlan)},
-        {(void**)&c->rows, std::max<size_t>(1, p.n_row_max) * sizeof(RowStat)},
         {(void**)&c->corr, N * sizeof(float)},
         {(void**)&c->twiddle, (size_t)fft_twiddle_entries((int)M) * sizeof(float2)},
         {(void**)&c->tiles, T * T * sizeof(TileStat)},
         {(void**)&c->scratch_d, 64 * sizeof(double)},
-        {(void**)&c->scratch_i, 64 * sizeof(int32_t)},
         {(void**)&c->det_scores, 2 * T * T * sizeof(double)},
         {(void**)&c->det_boxes, T * T * sizeof(int4)},
     };
@@ -262,6 +300,16 @@ toi_status toi_destroy(toi_ctx* c) {
     for (auto& e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->cap_stream2) (void)hipStreamDestroy(c->cap_stream2);
+    for (hipEvent_t ev : c->batch_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    {
+        toi_front& a = c->alt;
+        void* alt_ptrs[] = {a.plan, a.rows, a.items, a.recs, a.bin_count, a.bin_off, a.bin_cursor,
+                            a.bin_list, a.bin_order, a.bin_aux, a.units, a.tile_bits, a.row_bits, a.scratch_i};
+        for (void* q : alt_ptrs)
+            if (q) (void)hipFree(q);
+    }
     if (c->batch_exec) (void)hipGraphExecDestroy(c->batch_exec);
     if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
     void* ptrs[] = {c->items, c->recs, c->gx, c->bin_order, c->bin_aux, c->units, c->split_part,

@@ -857,6 +857,11 @@ __global__ __launch_bounds__(256) void k_split_sum(const DevPlan* __restrict__ P
 }
 
 hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
+    const hipError_t e = launch_bin(c, s);
+    return e != hipSuccess ? e : launch_gridder(c, s);
+}
+
+hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
     const toi_params& p = c->p;
     const int M = c->M, NT = c->NT;
     const double cell = p.cell_deg * kPi / 180.0;
@@ -887,6 +892,16 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
             hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, c->items, n_items, NT,
                                c->bin_cap, c->bin_cursor, c->bin_list);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gridder(toi_ctx* c, const toi_snapshot& s) {
+    const toi_params& p = c->p;
+    const int M = c->M, NT = c->NT;
+    const double cell = p.cell_deg * kPi / 180.0;
+    const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;
+    const int n_items = s.n_row * n_chunks;
+    const int n_bins = c->NG_max * NT * NT;
     if (n_items == 0) return hipGetLastError();
     StageTimer timer(c, TOI_STAGE_GRID);
     const GridShape gs = grid_shape(c->tuning, c->kmax);

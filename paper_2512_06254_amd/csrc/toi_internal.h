@@ -134,6 +134,27 @@ struct TileStat {         // FITrig per-tile sums (FP64)
 
 }  // namespace toi
 
+// Per-snapshot state written by sample prep and binning and read by the
+// gridder and the FFT passes.  The context holds one set in its own fields;
+// batched execution adds a second (toi_ctx::alt) so that the prep and binning
+// of snapshot i + 1 can run while snapshot i is transformed.
+struct toi_front {
+    toi::DevPlan* plan;
+    toi::RowStat* rows;
+    toi::ItemBox* items;
+    toi::SampleRec* recs;
+    int32_t* bin_count;
+    int32_t* bin_off;
+    int32_t* bin_cursor;
+    int32_t* bin_list;
+    int32_t* bin_order;
+    int32_t* bin_aux;
+    int4* units;
+    uint32_t* tile_bits;
+    uint32_t* row_bits;
+    int32_t* scratch_i;
+};
+
 struct toi_ctx {
     toi_params p;
     hipStream_t stream;
@@ -192,6 +213,10 @@ struct toi_ctx {
     int batch_n;
     hipStream_t cap_stream;   // internal stream the batch is captured on (default priority)
     void* batch_desc;
+    hipStream_t cap_stream2;  // second capture stream: prep and binning of the next snapshot
+    hipEvent_t batch_ev[4];   // capture-time fork/join and ordering events
+    toi_front alt;            // second per-snapshot set (allocated on the first batch of >= 2)
+    bool alt_ready;
 
     // streaming ingest (toi_ingest.cpp): device staging slots and the copy stream
     struct toi_ingest_state* ingest;
@@ -205,7 +230,9 @@ toi_status hip_check(toi_ctx* ctx, hipError_t e, const char* what);
 
 // launchers, one per translation unit
 hipError_t launch_prep(toi_ctx* ctx, const toi_snapshot& s);
-hipError_t launch_grid(toi_ctx* ctx, const toi_snapshot& s);
+hipError_t launch_grid(toi_ctx* ctx, const toi_snapshot& s);      // launch_bin + launch_gridder
+hipError_t launch_bin(toi_ctx* ctx, const toi_snapshot& s);       // records, bins, work units
+hipError_t launch_gridder(toi_ctx* ctx, const toi_snapshot& s);   // the tile gridder (+ split sums)
 hipError_t launch_image(toi_ctx* ctx, float* image_out, float* tplane_out);
 hipError_t launch_degrid(toi_ctx* ctx, const float* grad_image, const toi_snapshot& s,
                          float2* grad_vis, float2* grad_gains);
@@ -239,6 +266,11 @@ inline int unit_workgroups(int n_items, int n_bins) {
 
 // streaming ingest state (toi_ingest.cpp), released by toi_destroy
 void ingest_release(toi_ctx* ctx);
+
+// Byte sizes of the per-snapshot set's buffers (same order as toi_front's
+// fields), and the swap of the context's set with ctx->alt (toi_ctx.cpp).
+void front_bytes(const toi_ctx* ctx, size_t out[14]);
+void front_swap(toi_ctx* ctx);
 
 // host-side tables (toi_ctx.cpp)
 void es_correction_table(int N, int M, double* out);   // (-1)^a / psi(a)

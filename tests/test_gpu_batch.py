@@ -49,3 +49,35 @@ def test_batched_graph_matches_eager_and_oracle():
     print(f"[batch] oracle err {e:.3e}; kept samples per snapshot {kept}", flush=True)
     assert e < 1e-4
     im.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 5])
+def test_batched_lengths_match_eager(n):
+    """One lane (n = 1) and two lanes ending on either per-snapshot set (n = 2, 5)."""
+    import torch
+    from paper_2512_06254_amd import toi as T
+    wl = S.scaled(S.WORKLOADS["batched"], n_ant=9, n_chan=40, n_pix=64, n_steady=4, cell_arcsec=60.0,
+                  diameter_m=1500.0, n_snap=8)
+    sky, enu = S.make_sky(wl), S.antenna_enu(wl)
+    dev = [T.to_device(S.make_snapshot(wl, t, sky=sky, enu=enu)) for t in range(n)]
+    N, TT = wl.n_pix, wl.n_pix // 32
+    im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=1, cheb_k=8, tile=32)
+    print(f"[batch lengths] n={n}", flush=True)
+    eager = []
+    for d in dev:
+        im.grid(d)
+        eager.append(im.image().clone())
+    imgs = torch.zeros((n, N, N), device="cuda")
+    tls = torch.zeros((max(n - 2, 1), TT, TT), device="cuda")
+    for _ in range(2):
+        imgs.zero_()
+        im.image_batch(dev, imgs, tls if n >= 3 else None)
+        torch.cuda.synchronize()
+        for i in range(n):
+            peak = eager[i].abs().max().item()
+            assert (imgs[i] - eager[i]).abs().max().item() / peak < 1e-5, (n, i)
+    im.grid(dev[0])                                    # the eager path after a batch
+    again = im.image()
+    torch.cuda.synchronize()
+    assert (again - eager[0]).abs().max().item() / eager[0].abs().max().item() < 1e-5
+    im.close()
