@@ -125,6 +125,15 @@ __device__ inline int xcd_block_id(int bid, int nblk) {
     return (bid & 7) * (nblk >> 3) + (bid >> 3);
 }
 
+// a / b given rb = 1 / b (correctly rounded): q = a rb, then one correction
+// with the exact residual a - q b (an FMA): q + (a - q b) rb, within an ulp
+// of the correctly rounded quotient (equal to it in all but rare cases), in
+// three FP64 operations instead of a division sequence.
+__host__ __device__ inline double div_by(double a, double b, double rb) {
+    const double q = a * rb;
+    return fma(fma(-q, b, a), rb, q);
+}
+
 // Exponential-of-semicircle gridding kernel on |z| <= 1 (beta = 2.30 * 8):
 // exp(beta (sqrt(1 - z^2) - 1)) = 2^(beta log2(e) (sqrt(1 - z^2) - 1)), with the
 // hardware square root and base-2 exponential (about 1 ulp each).

@@ -51,11 +51,11 @@ __device__ inline Track row_track(const double* __restrict__ uvw, int r, const D
                                   double cell_rad) {
     const double u0 = uvw[3 * r], u1 = uvw[3 * r + 1], u2 = uvw[3 * r + 2];
     const double* V = P->V;
-    const double sc = (double)M * cell_rad / kCLight;
+    const double sc = div_by((double)M * cell_rad, kCLight, kInvCLight);
     Track t;
     t.ax = -(V[0] * u0 + V[1] * u1 + V[2] * u2) * sc;
     t.ay = (V[3] * u0 + V[4] * u1 + V[5] * u2) * sc;
-    t.a3 = (V[6] * u0 + V[7] * u1 + V[8] * u2) / kCLight;
+    t.a3 = div_by(V[6] * u0 + V[7] * u1 + V[8] * u2, kCLight, kInvCLight);
     return t;
 }
 
@@ -72,7 +72,7 @@ __device__ inline float2 row_gain(const float2* __restrict__ gains, const int32_
 // Slab of a residual coordinate: p = min(N_slab - 1, floor((r3 - r3min) / (2 dr3))).
 __device__ inline int slab_index(double r3, const DevPlan* __restrict__ P) {
     if (!(P->dr3 > 0.0)) return 0;
-    int p = (int)floor((r3 - P->r3min) / (2.0 * P->dr3));
+    int p = (int)floor(div_by(r3 - P->r3min, 2.0 * P->dr3, 0.5 * P->inv_dr3));
     return max(0, min(P->n_slab - 1, p));
 }
 

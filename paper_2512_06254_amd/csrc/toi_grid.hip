@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
             if (mode == 3 && P->dr3 > 0.0) {
                 const double r3 = tr.a3 * nu;
                 rec.sp = slab_index(r3, P);
-                rec.ss = (float)((r3 - (P->r3min + (2 * rec.sp + 1) * P->dr3)) / P->dr3);
+                rec.ss = (float)div_by(r3 - (P->r3min + (2 * rec.sp + 1) * P->dr3), P->dr3, P->inv_dr3);
             }
             const double X = 0.5 * M + tr.ax * nu, Y = 0.5 * M + tr.ay * nu;
             const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
@@ -373,7 +373,7 @@ __device__ inline Prep prepare_sample(const double* __restrict__ uvw, const floa
     if (cheb) {
         const double r3 = trk.a3 * nu;
         q.sp = slab_index(r3, P);
-        q.ss = (float)((r3 - (P->r3min + (2 * q.sp + 1) * P->dr3)) / P->dr3);
+        q.ss = (float)div_by(r3 - (P->r3min + (2 * q.sp + 1) * P->dr3), P->dr3, P->inv_dr3);
     }
     const double hM = 0.5 * M;
     const double X = hM + trk.ax * nu, Y = hM + trk.ay * nu;

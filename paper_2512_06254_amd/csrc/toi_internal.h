@@ -13,6 +13,7 @@
 namespace toi {
 
 constexpr double kCLight = 299792458.0;
+constexpr double kInvCLight = 1.0 / kCLight;   // correctly rounded at compile time
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kSupport = 8;                 // ES kernel support W (cells)
 constexpr double kEsBetaPerW = 2.30;        // beta = 2.30 W for a 2x oversampled grid
@@ -27,6 +28,7 @@ struct DevPlan {
     double r3min, r3max;
     double t3max;         // written through its bit pattern by an atomic max
     double phimax, dr3, alpha_slab;
+    double inv_dr3;       // 1 / dr3 (0 when dr3 = 0)
     double norm;          // 1 / (omega W)
     double sum_b[3];
     double sum_bb[6];

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ wei
         }
         if (w > 0.0) {
             const double nu = freq[c];
-            const double kk = nu / kCLight;
+            const double kk = div_by(nu, kCLight, kInvCLight);
             cnt += 1.0;
             s1 += kk;
             s2 += kk * kk;
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, c
     for (int r = threadIdx.x; r < n_row; r += blockDim.x) {
         const RowStat s = rows[r];
         if (s.cnt == 0) continue;
-        const double a = (V_s[6] * uvw[3 * r] + V_s[7] * uvw[3 * r + 1] + V_s[8] * uvw[3 * r + 2]) / kCLight;
+        const double a = div_by(V_s[6] * uvw[3 * r] + V_s[7] * uvw[3 * r + 1] + V_s[8] * uvw[3 * r + 2], kCLight, kInvCLight);
         const double x0 = a * s.numin, x1 = a * s.numax;
         lo = fmin(lo, fmin(x0, x1));
         hi = fmax(hi, fmax(x0, x1));
@@ -281,6 +281,7 @@ __global__ __launch_bounds__(256) void k_plan(double alpha_target, double gamma,
         plan->phimax = phimax;
         plan->n_slab = ns;
         plan->dr3 = dr3;
+        plan->inv_dr3 = dr3 > 0.0 ? 1.0 / dr3 : 0.0;
         plan->alpha_slab = 2.0 * kPi * t3max * dr3;
         a_slab = plan->alpha_slab;
     }
