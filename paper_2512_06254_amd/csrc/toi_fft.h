@@ -224,6 +224,37 @@ __device__ inline void fft_load_masked(float2* v, const float2* __restrict__ src
         }
 }
 
+// Bit e (element e of the stage-1 pattern) set where pred holds for the
+// element's index: the occupancy of this thread's elements, computed once for
+// rows or columns that share it.
+template <int M, int E, typename Pred>
+__device__ inline uint32_t fft_element_bits(Pred pred) {
+    constexpr int T = M / E;
+    constexpr int R1 = fft_first_radix(M, E);
+    static_assert(E <= 32, "one bit per element");
+    uint32_t bits = 0;
+#pragma unroll
+    for (int b = 0; b < E / R1; ++b)
+#pragma unroll
+        for (int r = 0; r < R1; ++r)
+            if (pred(threadIdx.x + b * T + r * (M / R1))) bits |= 1u << (b * R1 + r);
+    return bits;
+}
+
+// As fft_load, with the elements whose bit is clear read as zero (not loaded).
+template <int M, int E>
+__device__ inline void fft_load_bits(float2* v, const float2* __restrict__ src, uint32_t bits) {
+    constexpr int T = M / E;
+    constexpr int R1 = fft_first_radix(M, E);
+#pragma unroll
+    for (int b = 0; b < E / R1; ++b)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int e = b * R1 + r;
+            v[e] = ((bits >> e) & 1u) ? src[threadIdx.x + b * T + r * (M / R1)] : make_float2(0.f, 0.f);
+        }
+}
+
 // Output slot r (0 <= r < E) of thread t is bin k = t + r T.  With M = 2N the
 // kept bins are a = k (k < N/2) and a = k - M (k >= M - N/2), a in [-N/2, N/2),
 // i.e. the slots r < E/4 and r >= 3E/4.

@@ -36,13 +36,17 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict_
     if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) return;   // empty tile row
     if (threadIdx.x < WORDS) tb[threadIdx.x] = tile_bits[((size_t)g * NT + ty) * WORDS + threadIdx.x];
     load_twiddles<M, E>(tw_s, tw);
-    auto occupied = [&](int x) { return (tb[x >> (kTileShift + 5)] >> ((x >> kTileShift) & 31)) & 1u; };
+    // the band's rows lie in one tile row (B divides the tile side): one
+    // occupancy mask of this thread's elements serves all of them
+    static_assert(kTile % B == 0, "a band within one tile row");
+    const uint32_t occ = fft_element_bits<M, E>(
+        [&](int x) { return (tb[x >> (kTileShift + 5)] >> ((x >> kTileShift) & 31)) & 1u; });
     float2 keep[B][KEEP];
 #pragma unroll
     for (int rb = 0; rb < B; ++rb) {
         const int y = band * B + rb;
         float2 v[E];
-        fft_load_masked<M, E>(v, grid + ((size_t)plane * M + y) * M, occupied);
+        fft_load_bits<M, E>(v, grid + ((size_t)plane * M + y) * M, occ);
         fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) keep[rb][q] = v[fft_kept_slot<E>(q)];
@@ -126,6 +130,8 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict_
             ialpha[q] = small[q] ? 0.f : 1.f / alpha[q];
         }
         const int L = max(plan->miller_top, K + 2);
+        int occ_g = -1;                                // plane group whose occupancy mask is in occ
+        uint32_t occ = 0;
         for (int p = 0; p < ns; ++p) {
             float jp1[KEEP], jc[KEEP], nrm[KEEP], ar[KEEP], ai[KEEP];
 #pragma unroll
@@ -147,9 +153,14 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict_
             // orders K-1 .. 0 with their planes
             for (int k = K - 1; k >= 0; --k) {
                 float2 v[E];
-                const uint32_t* rbg = rb_s + group_of_plane(p * K + k, plan) * WORDS;
-                fft_load_masked<M, E>(v, hbuf + ((size_t)(p * K + k) * N + j1) * M,
-                                      [&](int y) { return (rbg[y >> (kTileShift + 5)] >> ((y >> kTileShift) & 31)) & 1u; });
+                const int gk = group_of_plane(p * K + k, plan);
+                if (gk != occ_g) {   // planes of one group share the occupancy of their tile rows
+                    const uint32_t* rbg = rb_s + gk * WORDS;
+                    occ = fft_element_bits<M, E>(
+                        [&](int y) { return (rbg[y >> (kTileShift + 5)] >> ((y >> kTileShift) & 31)) & 1u; });
+                    occ_g = gk;
+                }
+                fft_load_bits<M, E>(v, hbuf + ((size_t)(p * K + k) * N + j1) * M, occ);
                 fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
                 for (int q = 0; q < KEEP; ++q) {
