@@ -112,10 +112,12 @@ __device__ inline double miller_norm(double alpha, int L) {
 template <int M, int E>
 __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__ gtp, float2* __restrict__ gh,
                                                        const float2* __restrict__ tw, const float* __restrict__ corr,
-                                                       const DevPlan* __restrict__ plan, float cell_rad, int mode) {
+                                                       const DevPlan* __restrict__ plan, float cell_rad, int mode,
+                                                       const uint32_t* __restrict__ row_bits) {
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
     constexpr int T = M / E;
+    constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[fft_lds_size<M, E>()];
     __shared__ float2 tw_s[FftTw<M, E>::size()];
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
@@ -149,6 +151,8 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
             nrm[q] = fabs(alpha[q]) < 1e-3 ? 1.0 : miller_norm(alpha[q], Lq[q]);
         }
     }
+    int wg = -1;              // plane group whose row mask is in wbits
+    uint32_t wbits = 0;
     for (int p = 0; p < ns; ++p) {
         float cs[KEEP], sn[KEEP];
         if (mode == 3) {
@@ -222,18 +226,34 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
 #pragma unroll
                 for (int r = 0; r < R1; ++r) v[b * R1 + r] = lds[threadIdx.x + b * T + r * (M / R1)];
             fft_stages<M, E, 1>(v, lds, tw_s);
+            // output element r is row y = t + r T: written only in tile rows
+            // that hold samples (the row pass reads no others)
+            const int gk = group_of_plane(p * K + k, plan);
+            if (gk != wg) {
+                wbits = 0;
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const int yy = threadIdx.x + r * T;
+                    if ((row_bits[gk * WORDS + (yy >> (kTileShift + 5))] >> ((yy >> kTileShift) & 31)) & 1u)
+                        wbits |= 1u << r;
+                }
+                wg = gk;
+            }
             float2* dst = gh + ((size_t)(p * K + k) * N + j1) * M;
 #pragma unroll
-            for (int r = 0; r < E; ++r) dst[threadIdx.x + r * T] = make_float2(v[r].x, -v[r].y);
+            for (int r = 0; r < E; ++r)
+                if ((wbits >> r) & 1u) dst[threadIdx.x + r * T] = make_float2(v[r].x, -v[r].y);
         }
     }
 }
 
-// 3. row pass of the adjoint (rows of tile rows that hold samples)
+// 3. row pass of the adjoint (rows of tile rows that hold samples; only the
+// tiles that hold samples are written, the only ones the gather reads)
 template <int M, int E, int B>
 __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict__ gh, float2* __restrict__ gg,
                                                        const float2* __restrict__ tw,
                                                        const DevPlan* __restrict__ plan, int nbands,
+                                                       const uint32_t* __restrict__ tile_bits,
                                                        const uint32_t* __restrict__ row_bits) {
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
@@ -241,13 +261,24 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict_
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[fft_lds_size<M, E>()];
     __shared__ float2 tw_s[FftTw<M, E>::size()];
+    __shared__ uint32_t tb[WORDS];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
     const int plane = id / nbands, band = id % nbands;
     if ((plan->status & kStatusFatal) || plane >= plan->planes) return;
     const int g = group_of_plane(plane, plan);
     const int ty = (band * B) / kTile;
     if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) return;
-    load_twiddles<M, E>(tw_s, tw);
+    if (threadIdx.x < WORDS) tb[threadIdx.x] = tile_bits[((size_t)g * NT + ty) * WORDS + threadIdx.x];
+    load_twiddles<M, E>(tw_s, tw);   // its barrier also publishes tb
+    // output element r of this thread is column x = t + r T: written only
+    // where its tile holds samples (the band's rows share one tile row)
+    static_assert(kTile % B == 0, "a band within one tile row");
+    uint32_t wbits = 0;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int x = threadIdx.x + r * T;
+        if ((tb[x >> (kTileShift + 5)] >> ((x >> kTileShift) & 31)) & 1u) wbits |= 1u << r;
+    }
     float2 in[B][KEEP];
 #pragma unroll
     for (int q = 0; q < KEEP; ++q) {
@@ -274,7 +305,8 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict_
         fft_stages<M, E, 1>(v, lds, tw_s);
         float2* dst = gg + ((size_t)plane * M + band * B + rb) * M;
 #pragma unroll
-        for (int r = 0; r < E; ++r) dst[threadIdx.x + r * T] = make_float2(v[r].x, -v[r].y);
+        for (int r = 0; r < E; ++r)
+            if ((wbits >> r) & 1u) dst[threadIdx.x + r * T] = make_float2(v[r].x, -v[r].y);
     }
 }
 
@@ -509,10 +541,10 @@ static void launch_adj_ffts(toi_ctx* c) {
     constexpr int B = (M >= 8192) ? 2 : 4;
     const float cell = (float)(c->p.cell_deg * kPi / 180.0);
     hipLaunchKernelGGL((k_adj_cols<M, EC>), dim3(M / 2), dim3(M / EC), 0, c->stream, c->adj_tp, c->hbuf, c->twiddle,
-                       c->corr, c->plan, cell, c->p.mode);
+                       c->corr, c->plan, cell, c->p.mode, c->row_bits);
     const int nbands = M / B;
     hipLaunchKernelGGL((k_adj_rows<M, E, B>), dim3(nbands * c->P_cap), dim3(M / E), 0, c->stream, c->hbuf, c->grid,
-                       c->twiddle, c->plan, nbands, c->row_bits);
+                       c->twiddle, c->plan, nbands, c->tile_bits, c->row_bits);
 }
 
 hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot& s, float2* grad_vis,
