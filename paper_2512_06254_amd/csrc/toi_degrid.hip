@@ -445,6 +445,9 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                 }
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
+                    // registers 4 j .. 4 j + 3 hold rows 8 j .. 8 j + 7: none
+                    // past the last sample slot needs reducing (uniform branch)
+                    if (b + 8 * (r >> 2) >= n_act) break;
                     const int q = b + (r & 3) + 8 * (r >> 2) + 4 * half;   // sample slot of this register's row
                     const bool ok = q < n_act;
                     float v = ok ? h[r] * sT[q * 16 + pl] : 0.f;
