@@ -210,8 +210,9 @@ __device__ inline void fft_load(float2* v, const float2* __restrict__ src) {
         for (int r = 0; r < R1; ++r) v[b * R1 + r] = src[threadIdx.x + b * T + r * (M / R1)];
 }
 
-// As fft_load, with elements whose index fails pred(i) read as zero (not loaded).
-template <int M, int E, typename Pred>
+// As fft_load, with elements whose index fails pred(i) read as zero (not
+// loaded); element i of the sequence is src[i S].
+template <int M, int E, int S = 1, typename Pred>
 __device__ inline void fft_load_masked(float2* v, const float2* __restrict__ src, Pred pred) {
     constexpr int T = M / E;
     constexpr int R1 = fft_first_radix(M, E);
@@ -220,7 +221,7 @@ __device__ inline void fft_load_masked(float2* v, const float2* __restrict__ src
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
             const int i = threadIdx.x + b * T + r * (M / R1);
-            v[b * R1 + r] = pred(i) ? src[i] : make_float2(0.f, 0.f);
+            v[b * R1 + r] = pred(i) ? src[(size_t)i * S] : make_float2(0.f, 0.f);
         }
 }
 
@@ -241,8 +242,9 @@ __device__ inline uint32_t fft_element_bits(Pred pred) {
     return bits;
 }
 
-// As fft_load, with the elements whose bit is clear read as zero (not loaded).
-template <int M, int E>
+// As fft_load, with the elements whose bit is clear read as zero (not
+// loaded); element i of the sequence is src[i S].
+template <int M, int E, int S = 1>
 __device__ inline void fft_load_bits(float2* v, const float2* __restrict__ src, uint32_t bits) {
     constexpr int T = M / E;
     constexpr int R1 = fft_first_radix(M, E);
@@ -251,7 +253,7 @@ __device__ inline void fft_load_bits(float2* v, const float2* __restrict__ src, 
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
             const int e = b * R1 + r;
-            v[e] = ((bits >> e) & 1u) ? src[threadIdx.x + b * T + r * (M / R1)] : make_float2(0.f, 0.f);
+            v[e] = ((bits >> e) & 1u) ? src[(size_t)(threadIdx.x + b * T + r * (M / R1)) * S] : make_float2(0.f, 0.f);
         }
 }
 
