@@ -194,8 +194,15 @@ toi_status fitrig_strongest_map(toi_ctx* ctx, const float* cube, int32_t n_maps,
  * the pipeline of Section 4.1 as one launch.  snaps is a HOST array of n
  * descriptors.  The whole batch is captured into one HIP graph, cached for
  * the same descriptors and outputs and replayed on the context's stream (a
- * new set recaptures; capture allocates graph resources on first use).  The
- * context's grid workspace holds the last snapshot's planes afterwards. */
+ * new set recaptures; capture allocates graph resources on first use).  With
+ * n >= 2 the graph has two lanes: the sample prep and binning of snapshot
+ * i + 1 run while snapshot i is gridded and transformed, into a second set of
+ * per-snapshot buffers (plan, records, bins; the size of the first set's,
+ * allocated on the first such call and kept by the context; TOI_ENOMEM if it
+ * cannot be).  The descriptors' arrays must be ready when the launch starts
+ * on the context's stream.  The context's grid workspace holds the last
+ * snapshot's planes afterwards; toi_plan_info then reports the plan of the
+ * last even-indexed snapshot of the batch. */
 toi_status toi_image_batch(toi_ctx* ctx, const toi_snapshot* snaps, int32_t n,
                            float* images_out, float* tlisi_out);
 
