@@ -215,16 +215,19 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
                 }
                 v[fft_kept_slot<E>(q)] = e;
             }
-            // natural-order scatter, then the stage-1 pattern
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < E; ++r) lds[threadIdx.x + r * T] = v[r];
-            __syncthreads();
+            // natural-order scatter, then the stage-1 pattern (the same
+            // pattern when the first radix is E: nothing to move)
             constexpr int R1 = fft_first_radix(M, E);
+            if constexpr (R1 != E) {
+                __syncthreads();
 #pragma unroll
-            for (int b = 0; b < E / R1; ++b)
+                for (int r = 0; r < E; ++r) lds[threadIdx.x + r * T] = v[r];
+                __syncthreads();
 #pragma unroll
-                for (int r = 0; r < R1; ++r) v[b * R1 + r] = lds[threadIdx.x + b * T + r * (M / R1)];
+                for (int b = 0; b < E / R1; ++b)
+#pragma unroll
+                    for (int r = 0; r < R1; ++r) v[b * R1 + r] = lds[threadIdx.x + b * T + r * (M / R1)];
+            }
             fft_stages<M, E, 1>(v, lds, tw_s);
             // output element r is row y = t + r T: written only in tile rows
             // that hold samples (the row pass reads no others)
@@ -293,15 +296,19 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict_
         for (int r = 0; r < E; ++r) v[r] = make_float2(0.f, 0.f);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) v[fft_kept_slot<E>(q)] = make_float2(in[rb][q].x, -in[rb][q].y);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < E; ++r) lds[threadIdx.x + r * T] = v[r];
-        __syncthreads();
+        // natural order to the stage-1 pattern (the same pattern when the
+        // first radix is E: nothing to move)
         constexpr int R1 = fft_first_radix(M, E);
+        if constexpr (R1 != E) {
+            __syncthreads();
 #pragma unroll
-        for (int b = 0; b < E / R1; ++b)
+            for (int r = 0; r < E; ++r) lds[threadIdx.x + r * T] = v[r];
+            __syncthreads();
 #pragma unroll
-            for (int r = 0; r < R1; ++r) v[b * R1 + r] = lds[threadIdx.x + b * T + r * (M / R1)];
+            for (int b = 0; b < E / R1; ++b)
+#pragma unroll
+                for (int r = 0; r < R1; ++r) v[b * R1 + r] = lds[threadIdx.x + b * T + r * (M / R1)];
+        }
         fft_stages<M, E, 1>(v, lds, tw_s);
         float2* dst = gg + ((size_t)plane * M + band * B + rb) * M;
 #pragma unroll

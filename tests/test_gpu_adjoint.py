@@ -97,3 +97,26 @@ def test_autograd_function_gradients():
     print(f"[autograd] grad_vis err {e_v:.3e}  grad_gains err {e_g:.3e}", flush=True)
     assert e_v < 1e-3 and e_g < 1e-3
     im.close()
+
+
+@pytest.mark.parametrize("n_pix", [32, 128])
+def test_adjoint_sizes_whose_first_radix_is_the_pass_radix(n_pix):
+    """Grids of 64 and 256 (radix 8 and 16, first stage of full radix): the
+    adjoint passes take their input straight in the stage-1 pattern."""
+    import torch
+    from paper_2512_06254_amd import toi as T
+    wl, snap = _setup(n_pix=n_pix)
+    op = A.SnapshotOperator(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=8)
+    rng = np.random.default_rng(5)
+    y = rng.normal(size=(wl.n_pix, wl.n_pix))
+    gx = op.adjoint(y)
+    gv_ref, gg_ref = A.vis_gradients(snap, op.res.samples, gx)
+    im = _imager(wl, snap, 1, 8)
+    d = T.to_device(snap)
+    im.grid(d)
+    gv, gg = im.degrid(torch.from_numpy(y.astype(np.float32)).cuda(), d, want_vis=True, want_gains=True)
+    e_v = np.abs(gv.cpu().numpy() - gv_ref).max() / np.abs(gv_ref).max()
+    e_g = np.abs(gg.cpu().numpy() - gg_ref).max() / np.abs(gg_ref).max()
+    print(f"[adjoint n_pix={n_pix}] grad_vis err {e_v:.3e}  grad_gains err {e_g:.3e}", flush=True)
+    assert e_v < 1e-4 and e_g < 1e-4
+    im.close()
