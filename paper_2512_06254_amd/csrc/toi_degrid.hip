@@ -133,7 +133,10 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
         y[q] = gtp[(size_t)j1 * N + j2[q]] * c1 * corr[j2[q]];
     }
     // per-pixel geometry (FP64 here: the adjoint runs once per backward pass)
-    double t3[KEEP], alpha[KEEP], nrm[KEEP], jp1[KEEP], jc[KEEP];
+    // ia: 1 / alpha (0 where |alpha| < 1e-3: the power series, from af = alpha);
+    // inrm: 1 / Miller normalisation
+    double t3[KEEP], ia[KEEP], inrm[KEEP], jp1[KEEP], jc[KEEP];
+    float af[KEEP];
     int Lq[KEEP];
     if (mode == 3) {
         const double V13 = plan->V[2], V23 = plan->V[5], V33 = plan->V[8];
@@ -146,9 +149,12 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
             if (a < 0) y[q] = 0.f;
             const double num = t1 * t1 + t2 * t2 + 2.0 * t1 * V13 + 2.0 * t2 * V23;
             t3[q] = a >= 0 ? -sg * num / (sqrt(fmax(a, 0.0)) + fabs(V33)) : 0.0;
-            alpha[q] = 2.0 * kPi * plan->dr3 * t3[q];
-            Lq[q] = miller_start(K, alpha[q]);
-            nrm[q] = fabs(alpha[q]) < 1e-3 ? 1.0 : miller_norm(alpha[q], Lq[q]);
+            const double al = 2.0 * kPi * plan->dr3 * t3[q];
+            const bool series = fabs(al) < 1e-3;
+            af[q] = (float)al;
+            ia[q] = series ? 0.0 : 1.0 / al;
+            Lq[q] = miller_start(K, al);
+            inrm[q] = series ? 1.0 : 1.0 / miller_norm(al, Lq[q]);
         }
     }
     int wg = -1;              // plane group whose row mask is in wbits
@@ -165,10 +171,9 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
                 // Miller state at order K (recurrence only above)
                 jp1[q] = 0.0;
                 jc[q] = 1e-100;
-                if (fabs(alpha[q]) >= 1e-3) {
-                    const double ia = 1.0 / alpha[q];
+                if (ia[q] != 0.0) {
                     for (int n = Lq[q]; n >= K; --n) {
-                        const double jm1 = 2.0 * n * ia * jc[q] - jp1[q];
+                        const double jm1 = 2.0 * n * ia[q] * jc[q] - jp1[q];
                         jp1[q] = jc[q];
                         jc[q] = jm1;
                     }
@@ -187,17 +192,17 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
             for (int q = 0; q < KEEP; ++q) {
                 float jk = 1.f;
                 if (mode == 3) {
-                    const double a = alpha[q];
+                    const double a = af[q];
                     double J;
-                    if (fabs(a) < 1e-3) {
+                    if (ia[q] == 0.0) {
                         J = k == 0 ? 1.0 - 0.25 * a * a
                           : k == 1 ? 0.5 * a * (1.0 - 0.125 * a * a)
                           : k == 2 ? 0.125 * a * a
                           : k == 3 ? a * a * a / 48.0 : 0.0;
                     } else {
-                        J = jc[q] / nrm[q];
-                        if (k > 0) {
-                            const double jm1 = 2.0 * k / a * jc[q] - jp1[q];
+                        J = jc[q] * inrm[q];
+                        if (k > 0) {   // the recurrence of the prologue, 2 n / alpha from 1 / alpha
+                            const double jm1 = 2.0 * k * ia[q] * jc[q] - jp1[q];
                             jp1[q] = jc[q];
                             jc[q] = jm1;
                         }
