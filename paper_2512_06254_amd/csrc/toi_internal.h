@@ -188,7 +188,8 @@ struct toi_ctx {
     int bin_cap;
     uint32_t* tile_bits;  // [NG_max][NT][NT/32]  nonempty tiles of each tile row
     uint32_t* row_bits;   // [NG_max][NT/32]      nonempty tile rows
-    float2* hbuf;         // [P_cap][N][M]   row-pass output, column major per plane
+    float2* hbuf;         // [P_cap][N/4][M][4] row-pass output: column major per plane in groups of 4 columns
+                          // (the adjoint uses it as [P_cap][N][M])
     float* tplane_t;      // [N][N]          transformed-plane image, j1 major
     float* adj_tp;        // [N][N]          adjoint: transformed-plane gradient, j1 major
     double2* item_gain;   // [n_items_max]   adjoint: per-item gain partial sums
