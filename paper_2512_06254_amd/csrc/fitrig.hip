@@ -45,9 +45,9 @@ __global__ __launch_bounds__(256) void k_tlisi_tiles(const float* __restrict__ a
     }
 }
 
-__global__ __launch_bounds__(256) void k_tlisi_final(const TileStat* __restrict__ st, int n_tiles, int tile,
-                                                     float* __restrict__ out) {
-    __shared__ double red[2][4];
+__global__ __launch_bounds__(1024) void k_tlisi_final(const TileStat* __restrict__ st, int n_tiles, int tile,
+                                                      float* __restrict__ out) {
+    __shared__ double red[2][16];
     double mn = 1e300, mx = -1e300;
     for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
         mn = fmin(mn, st[i].mn);
@@ -76,7 +76,7 @@ hipError_t launch_tlisi(toi_ctx* c, const float* a, const float* b, const float*
     const int T = c->T;
     StageTimer timer(c, TOI_STAGE_TLISI);
     hipLaunchKernelGGL(k_tlisi_tiles, dim3(T * T), dim3(256), 0, c->stream, a, b, d, c->N, c->p.tile, c->tiles);
-    hipLaunchKernelGGL(k_tlisi_final, dim3(1), dim3(256), 0, c->stream, c->tiles, T * T, c->p.tile, out);
+    hipLaunchKernelGGL(k_tlisi_final, dim3(1), dim3(1024), 0, c->stream, c->tiles, T * T, c->p.tile, out);
     return hipGetLastError();
 }
 
