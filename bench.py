@@ -137,10 +137,10 @@ def cpu_baseline(wl, snap_dev, n_slab, K, n_pixels=6):
     plan = O.make_plan(r[:, 2], bas.V, wl.n_pix, wl.cell_deg, n_slab=n_slab, K=K)
     t_fixed = time.perf_counter() - t0
     rng = np.random.default_rng(0)
-    j1 = rng.integers(0, wl.n_pix, n_pixels)
-    j2 = rng.integers(0, wl.n_pix, n_pixels)
+    j1 = rng.choice(wl.n_pix, n_pixels, replace=False)
+    j2 = rng.choice(wl.n_pix, 1, replace=False)
     t1 = time.perf_counter()
-    O.image_cheb_at(r, smp.x, smp.W, bas.omega, bas.V, plan, j1, j2, wl.n_pix, wl.cell_deg)
+    O.image_3d_cheb(r, smp.x, smp.W, bas.omega, bas.V, plan, wl.n_pix, wl.cell_deg, j1=j1, j2=j2)
     t_pix = (time.perf_counter() - t1) / n_pixels
     tp = np.zeros((wl.n_pix, wl.n_pix))
     t2 = time.perf_counter()

@@ -281,28 +281,50 @@ def slab_of(r3, plan: Plan):
     return p, s
 
 
-def moments(r, x, plan: Plan, n_pix, cell_deg):
-    """M_{p,k}(t1, t2) = sum_{q in S_p} T_k(s_q) x_q e^{i 2 pi (r1 t1 + r2 t2)}; shape (P, N, N)."""
-    t1, t2 = pixel_offsets(n_pix, cell_deg)
+def pixel_subgrid(n_pix: int, cell_deg: float, j1=None, j2=None):
+    """(t1 of the pixel columns j1, t2 of the pixel rows j2); every pixel by default."""
+    t1a, t2a = pixel_offsets(n_pix, cell_deg)
+    if j1 is not None:
+        t1a = t1a[np.asarray(j1, dtype=np.int64)]
+    if j2 is not None:
+        t2a = t2a[np.asarray(j2, dtype=np.int64)]
+    return t1a, t2a
+
+
+def moments(r, x, plan: Plan, n_pix, cell_deg, j1=None, j2=None):
+    """M_{p,k}(t1, t2) = sum_{q in S_p} T_k(s_q) x_q e^{i 2 pi (r1 t1 + r2 t2)} at the pixel
+    columns j1 and rows j2 (all pixels by default); shape (n_slab, K, len(j2), len(j1)).
+
+    The sum over samples runs in chunks; each chunk's phasors are formed once
+    and contracted with every order k (a matrix product over the samples)."""
+    t1, t2 = pixel_subgrid(n_pix, cell_deg, j1, j2)
     p, s = slab_of(r[:, 2], plan)
     T = cheb_T(plan.K, s)
-    out = np.zeros((plan.n_slab, plan.K, n_pix, n_pix), dtype=np.complex128)
+    out = np.zeros((plan.n_slab, plan.K, t2.size, t1.size), dtype=np.complex128)
+    chunk = max(512, 4_000_000 // max(t1.size, t2.size))
     for ps in range(plan.n_slab):
-        sel = p == ps
-        for k in range(plan.K):
-            out[ps, k] = dft_sum_2d(r[sel, 0], r[sel, 1], x[sel] * T[sel, k], t1, t2)
+        sel = np.nonzero(p == ps)[0]
+        for q0 in range(0, sel.size, chunk):
+            q = sel[q0:q0 + chunk]
+            e1 = _phasor_matrix(r[q, 0], t1)                         # (nq, columns)
+            e2t = _phasor_matrix(r[q, 1], t2).T                      # (rows, nq)
+            for k in range(plan.K):
+                out[ps, k] += e2t @ (e1 * (x[q] * T[q, k])[:, None])
     return out
 
 
-def image_3d_cheb(r, x, W, omega, V, plan: Plan, n_pix, cell_deg, M=None):
-    """Chebyshev/slab form of eq. (10); zero where t3 is not real."""
+def image_3d_cheb(r, x, W, omega, V, plan: Plan, n_pix, cell_deg, M=None, j1=None, j2=None):
+    """Chebyshev/slab form of eq. (10) at the pixel columns j1 and rows j2 (all
+    pixels by default); zero where t3 is not real.  ``M``: the moments on the
+    same pixels, if already computed."""
     if M is None:
-        M = moments(r, x, plan, n_pix, cell_deg)
-    t3 = t3_grid(V, n_pix, cell_deg)
+        M = moments(r, x, plan, n_pix, cell_deg, j1, j2)
+    t1, t2 = pixel_subgrid(n_pix, cell_deg, j1, j2)
+    t3 = t3_of(t1[None, :], t2[:, None], V)
     valid = np.isfinite(t3)
     t3z = np.where(valid, t3, 0.0)
-    c = cheb_coeffs(2.0 * math.pi * plan.dr3 * t3z, plan.K)          # (N, N, K)
-    acc = np.zeros((n_pix, n_pix), dtype=np.complex128)
+    c = cheb_coeffs(2.0 * math.pi * plan.dr3 * t3z, plan.K)          # (rows, columns, K)
+    acc = np.zeros(t3.shape, dtype=np.complex128)
     for ps in range(plan.n_slab):
         inner = np.einsum("yxk,kyx->yx", c, M[ps])
         acc += np.exp(2j * math.pi * plan.centre(ps) * t3z) * inner
@@ -335,32 +357,6 @@ def tplane_at(r, x, W, omega, t1, t2, t3=None):
     if t3 is not None:
         ph = ph + np.outer(r[:, 2], np.atleast_1d(t3))
     return np.real(x @ np.exp(2j * math.pi * ph)) / (omega * W)
-
-
-def image_cheb_at(r, x, W, omega, V, plan: Plan, j1, j2, n_pix, cell_deg):
-    """The Chebyshev/slab t-plane image at selected pixel centres (for large inputs)."""
-    t1a, t2a = pixel_offsets(n_pix, cell_deg)
-    j1 = np.atleast_1d(j1); j2 = np.atleast_1d(j2)
-    t1 = t1a[j1]; t2 = t2a[j2]
-    t3 = t3_of(t1, t2, V)
-    p, s = slab_of(r[:, 2], plan)
-    order = np.argsort(p, kind="stable")                             # samples grouped by slab
-    bounds = np.searchsorted(p[order], np.arange(plan.n_slab + 1))
-    rs, xs = r[order], x[order]
-    T = cheb_T(plan.K, s[order])                                     # (Nq, K)
-    out = np.zeros(j1.size)
-    for i in range(j1.size):
-        if not np.isfinite(t3[i]):
-            continue
-        e = xs * np.exp(2j * math.pi * (rs[:, 0] * t1[i] + rs[:, 1] * t2[i]))
-        c = cheb_coeffs(2.0 * math.pi * plan.dr3 * t3[i], plan.K)
-        acc = 0.0 + 0.0j
-        for ps in range(plan.n_slab):
-            a, b = bounds[ps], bounds[ps + 1]
-            mk = T[a:b].T @ e[a:b]                                   # M_{p,k} at this pixel
-            acc += np.exp(2j * math.pi * plan.centre(ps) * t3[i]) * (c @ mk)
-        out[i] = np.real(acc) / (omega * W)
-    return out
 
 
 # ----------------------------------------------------------------------------

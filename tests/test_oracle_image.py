@@ -198,3 +198,32 @@ def test_es_gridding_matches_direct_moments():
     grid = gridded.gridded_moments(res.r, res.samples.x, res.plan, wl.n_pix, wl.cell_deg)
     scale = np.abs(res.samples.x).sum()
     assert np.abs(grid - direct).max() < 1e-6 * scale
+
+
+def test_subgrid_evaluation_equals_the_full_image_multi_slab():
+    """The pixel sub-grid evaluation of the moments and of the Chebyshev/slab
+    image (used at full size, where the whole image is out of reach) equals the
+    whole-image evaluation at every selected pixel: three slabs, K = 6, columns
+    and rows of different counts (a transposed selection would fail)."""
+    wl = _wl(n_pix=32, n_ant=10, n_chan=12, sigma_h_m=60.0, cell_arcsec=90.0)
+    snap = S.make_snapshot(wl, 0)
+    res = toi.image_snapshot(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=3, K=6)
+    assert res.plan.n_slab == 3 and res.plan.K == 6
+    p, _ = toi.slab_of(res.r[:, 2], res.plan)
+    assert np.bincount(p, minlength=3).min() > 0            # every slab holds samples
+    s, b = res.samples, res.basis
+    full_m = toi.moments(res.r, s.x, res.plan, wl.n_pix, wl.cell_deg)
+    rng = np.random.default_rng(7)
+    j1 = np.sort(rng.choice(wl.n_pix, 9, replace=False))
+    j2 = np.sort(rng.choice(wl.n_pix, 5, replace=False))[::-1]
+    sub_m = toi.moments(res.r, s.x, res.plan, wl.n_pix, wl.cell_deg, j1=j1, j2=j2)
+    np.testing.assert_allclose(sub_m, full_m[:, :, j2][:, :, :, j1], atol=1e-12 * np.abs(full_m).max())
+    sub = toi.image_3d_cheb(res.r, s.x, s.W, b.omega, b.V, res.plan, wl.n_pix, wl.cell_deg, j1=j1, j2=j2)
+    assert sub.shape == (j2.size, j1.size)
+    np.testing.assert_allclose(sub, res.tplane[np.ix_(j2, j1)], atol=1e-12 * np.abs(res.tplane).max())
+    # every pixel, one row and one column at a time
+    for jj in range(wl.n_pix):
+        row = toi.image_3d_cheb(res.r, s.x, s.W, b.omega, b.V, res.plan, wl.n_pix, wl.cell_deg, j2=[jj])
+        col = toi.image_3d_cheb(res.r, s.x, s.W, b.omega, b.V, res.plan, wl.n_pix, wl.cell_deg, j1=[jj])
+        np.testing.assert_allclose(row[0], res.tplane[jj], atol=1e-12 * np.abs(res.tplane).max())
+        np.testing.assert_allclose(col[:, 0], res.tplane[:, jj], atol=1e-12 * np.abs(res.tplane).max())

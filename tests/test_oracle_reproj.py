@@ -104,3 +104,46 @@ def test_reprojection_of_gridded_tplane_approaches_standard_dft():
     v = res.valid
     assert v.mean() > 0.8
     assert np.abs(res.image[v] - std[v]).max() < 0.15 * np.abs(std).max()
+
+
+def _bilinear_form(a, b, c, d, n):
+    """img[j2][j1] = a + b j1 + c j2 + d j1 j2 (reproduced exactly by bilinear interpolation)."""
+    j1 = np.arange(n, dtype=np.float64)[None, :]
+    j2 = np.arange(n, dtype=np.float64)[:, None]
+    return a + b * j1 + c * j2 + d * j1 * j2
+
+
+def test_bilinear_reproduces_a_bilinear_form_at_fractional_positions():
+    # distinct coefficients on j1 and j2: a swap of the fractions, of the axes
+    # or of two corner weights changes the value
+    N = 37
+    a, b, c, d = 0.3, 1.7, -2.9, 0.011
+    img = _bilinear_form(a, b, c, d, N)
+    rng = np.random.default_rng(11)
+    u1 = rng.uniform(0.0, N - 1.0, 500)
+    u2 = rng.uniform(0.0, N - 1.0, 500)
+    u1[:3] = [0.0, 35.999999, 12.5]
+    u2[:3] = [35.25, 0.0, 7.0]                             # integer and edge positions
+    v, valid = toi.bilinear(img, u1, u2)
+    assert valid.all()
+    np.testing.assert_allclose(v, a + b * u1 + c * u2 + d * u1 * u2, atol=1e-11)
+    # outside: any neighbour beyond the image -> 0 and invalid
+    v2, valid2 = toi.bilinear(img, np.array([-0.01, N - 1.0, 3.0, 3.0]), np.array([3.0, 3.0, -1e-9, N - 0.5]))
+    assert not valid2.any() and (v2 == 0).all()
+
+
+def test_reprojection_of_a_bilinear_tplane_is_exact_at_the_mapped_positions():
+    # With a tilted basis the output pixel (j1, j2) reads the transformed plane
+    # at (u1, u2) = reproject_coords; for a bilinear-form t-plane the
+    # re-projected value is the form at exactly that position.
+    bas = _basis(sigma_h=60.0, seed=3)
+    assert abs(bas.xi) + abs(bas.eta) > 1e-3
+    N, cell = 64, 0.05
+    a, b, c, d = -1.25, 0.75, 2.5, -0.004
+    tp = _bilinear_form(a, b, c, d, N)
+    img, valid = toi.reproject(tp, bas.V, N, cell)
+    u1, u2, ok = toi.reproject_coords(bas.V, N, cell)
+    assert valid.mean() > 0.5
+    want = a + b * u1 + c * u2 + d * u1 * u2
+    np.testing.assert_allclose(img[valid], want[valid], atol=1e-10)
+    assert (img[~valid] == 0).all()
