@@ -47,7 +47,7 @@ typedef enum {
 #define TOI_STATUS_NO_SAMPLES 1u   /* every sample flagged or zero-weight: zero image      */
 #define TOI_STATUS_DEGENERATE 2u   /* |V33| < 1e-6: transformed plane edge-on, zero image   */
 #define TOI_STATUS_PLANES     4u   /* automatic N_slab * K exceeds max_planes: zero image   */
-#define TOI_STATUS_OVERFLOW   8u   /* gridding bin lists overflowed: image incomplete       */
+#define TOI_STATUS_OVERFLOW   8u   /* gridding bin lists exceed bin_cap: zero image          */
 
 typedef struct {
     int32_t  n_pix;        /* N, image side: power of two, 32 .. 4096                       */
@@ -65,6 +65,10 @@ typedef struct {
     int32_t  n_chan;
     int32_t  n_corr;       /* 1, 2 or 4                                                      */
     int32_t  n_ant;        /* antennas (gains length), may be 0 when no gains are used       */
+    int32_t  bin_cap;      /* capacity of the gridding bin lists in (work item, 8 x 8 tile)  */
+                           /* entries; 0 = 32 per work item (a work item is 64 channels of */
+                           /* one row) + 4096.  A snapshot needing more sets                 */
+                           /* TOI_STATUS_OVERFLOW and images to zero.                        */
 } toi_params;
 
 typedef struct {

@@ -107,7 +107,7 @@ void front_bytes(const toi_ctx* c, size_t out[14]) {
     out[6] = NG * NT * NT * sizeof(int32_t);                                              // bin_cursor
     out[7] = (size_t)c->bin_cap * sizeof(int32_t);                                        // bin_list
     out[8] = NG * NT * NT * sizeof(int32_t);                                              // bin_order
-    out[9] = (64 + (NG * NT * NT + kScanBlock - 1) / kScanBlock) * sizeof(int32_t);       // bin_aux
+    out[9] = (kAuxTotals + (NG * NT * NT + kScanBlock - 1) / kScanBlock) * sizeof(int32_t); // bin_aux
     out[10] = (size_t)kSplitSlots * sizeof(int4);                                         // units
     out[11] = NG * NT * words * sizeof(uint32_t);                                         // tile_bits
     out[12] = NG * words * sizeof(uint32_t);                                              // row_bits
@@ -187,6 +187,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
         return fail(nullptr, TOI_EINVAL, "toi_create: tile must divide n_pix");
     if (p.n_slab < 0 || p.cheb_k < 0 || p.cheb_k > 32 || p.max_planes < 0)
         return fail(nullptr, TOI_EINVAL, "toi_create: n_slab, cheb_k in [0, 32], max_planes must be >= 0");
+    if (p.bin_cap < 0) return fail(nullptr, TOI_EINVAL, "toi_create: bin_cap must be >= 0");
     if (!(p.alpha_target > 0.0) || !(p.cheb_gamma > 0.0))
         return fail(nullptr, TOI_EINVAL, "toi_create: alpha_target and cheb_gamma must be > 0");
 
@@ -220,7 +221,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
     c->NT = c->M / kTile;
     c->NG_max = std::max(1, c->P_cap);   // every group holds at least one plane
     c->n_items_max = std::max(1, p.n_row_max * ((p.n_chan + kItemChans - 1) / kItemChans));
-    c->bin_cap = c->n_items_max * 32 + 4096;
+    c->bin_cap = p.bin_cap > 0 ? p.bin_cap : c->n_items_max * 32 + 4096;
     size_t fb[14];
     front_bytes(c, fb);
     struct Alloc { void** ptr; size_t bytes; };

@@ -8,7 +8,11 @@
 
 namespace toi {
 
-constexpr uint32_t kStatusFatal = TOI_STATUS_NO_SAMPLES | TOI_STATUS_DEGENERATE | TOI_STATUS_PLANES;
+// Every status bit is fatal: the gridder, the FFT passes and the
+// re-projection then produce an all-zero image (an overflowing bin list would
+// leave tiles unwritten).
+constexpr uint32_t kStatusFatal =
+    TOI_STATUS_NO_SAMPLES | TOI_STATUS_DEGENERATE | TOI_STATUS_PLANES | TOI_STATUS_OVERFLOW;
 
 // Weighted sum of the selected correlations of one (row, channel) sample with
 // flags as zero weight (Section 3.5).  Returns the sample weight w.

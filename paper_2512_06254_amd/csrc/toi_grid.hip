@@ -10,7 +10,9 @@
 //  2. k_scan_local / k_scan_top / k_scan_apply turn the counts into list
 //     offsets, a heaviest-first launch order and occupancy bit masks; k_units
 //     splits the heaviest bins into work units of at most kUnitItems items;
-//     k_bin_fill writes the item lists.
+//     k_bin_fill writes the item lists and k_bin_sort_* put every list in
+//     increasing item order, so that the accumulation order, and the image,
+//     is the same on every run.
 //  3. k_grid_tiles_mfma (default): one wavefront per work unit keeps the whole
 //     tile in matrix-core accumulators and writes it to HBM once (the units of
 //     a split bin add their partial tiles in a fixed order first).
@@ -126,7 +128,8 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
 // ---------------------------------------------------------------- 2. scan
 // Three passes over the bin counts, kScanBlock bins per workgroup:
 //  local: exclusive scan inside the workgroup, its total, and the global
-//         histogram of non-empty bins by floor(log2(count));
+//         histogram of non-empty bins by floor(log2(count)) with the work
+//         units of each bucket;
 //  top:   one workgroup scans the workgroup totals, writes the list length
 //         (overflow check) and turns the histogram into bucket offsets,
 //         heaviest bucket first;
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
 //         non-empty bins in launch order (heaviest bucket first; order inside
 //         a bucket is arbitrary) and writes the occupancy masks
 //         tile_bits[g][ty][tx/32] and row_bits[g][ty/32].
-// aux: [0, 32) bucket sizes, [32, 64) bucket cursors, [64, 64 + blocks) totals.
+// aux: layout kAux* (toi_internal.h).
 constexpr int kScanPer = kScanBlock / 1024;
 
 __global__ __launch_bounds__(256) void k_scan_clear(int32_t* __restrict__ count, int n_bins,
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(256) void k_scan_clear(int32_t* __restrict__ count,
     const int stride = gridDim.x * blockDim.x;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     for (int i = t; i < n_bins; i += stride) count[i] = 0;
-    if (t < 64) aux[t] = 0;
+    if (t < kAuxTotals) aux[t] = 0;
     for (int i = t; i < n_row_words; i += stride) row_bits[i] = 0;
 }
 
@@ -171,12 +174,15 @@ __device__ inline int block_exclusive_scan(int v, int& total) {
 __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__ count, int n_bins,
                                                      const DevPlan* __restrict__ P, int tiles,
                                                      int32_t* __restrict__ off, int32_t* __restrict__ aux) {
-    __shared__ int32_t hist[32];
+    __shared__ int32_t hist[32], hunits[32];
     if (blockIdx.x * kScanBlock >= P->ng * tiles) {   // bins of unused plane groups hold no items
-        if (threadIdx.x == 0) aux[64 + blockIdx.x] = 0;
+        if (threadIdx.x == 0) aux[kAuxTotals + blockIdx.x] = 0;
         return;
     }
-    if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+    if (threadIdx.x < 32) {
+        hist[threadIdx.x] = 0;
+        hunits[threadIdx.x] = 0;
+    }
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
     int c[kScanPer], sum = 0;
 #pragma unroll
@@ -190,11 +196,18 @@ __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__
     for (int j = 0; j < kScanPer; ++j) {
         if (base + j < n_bins) off[base + j] = run;
         run += c[j];
-        if (c[j] > 0) atomicAdd(&hist[31 - __clz(c[j])], 1);
+        if (c[j] > 0) {
+            const int k = 31 - __clz(c[j]);
+            atomicAdd(&hist[k], 1);
+            atomicAdd(&hunits[k], (c[j] + kUnitItems - 1) >> kUnitShift);
+        }
     }
     __syncthreads();
-    if (threadIdx.x < 32 && hist[threadIdx.x]) atomicAdd(&aux[threadIdx.x], hist[threadIdx.x]);
-    if (threadIdx.x == 0) aux[64 + blockIdx.x] = total;
+    if (threadIdx.x < 32) {
+        if (hist[threadIdx.x]) atomicAdd(&aux[kAuxBuckets + threadIdx.x], hist[threadIdx.x]);
+        if (hunits[threadIdx.x]) atomicAdd(&aux[kAuxUnits + threadIdx.x], hunits[threadIdx.x]);
+    }
+    if (threadIdx.x == 0) aux[kAuxTotals + blockIdx.x] = total;
 }
 
 __global__ __launch_bounds__(1024) void k_scan_top(int n_blocks, int n_bins, int bin_cap, DevPlan* __restrict__ P,
@@ -203,10 +216,10 @@ __global__ __launch_bounds__(1024) void k_scan_top(int n_blocks, int n_bins, int
     int carry = 0;
     for (int b0 = 0; b0 < n_blocks; b0 += 1024) {
         const int b = b0 + (int)threadIdx.x;
-        const int v = b < n_blocks ? aux[64 + b] : 0;
+        const int v = b < n_blocks ? aux[kAuxTotals + b] : 0;
         int total;
         const int ex = block_exclusive_scan(v, total);
-        if (b < n_blocks) aux[64 + b] = carry + ex;
+        if (b < n_blocks) aux[kAuxTotals + b] = carry + ex;
         carry += total;
     }
     if (threadIdx.x == 0) {
@@ -214,8 +227,8 @@ __global__ __launch_bounds__(1024) void k_scan_top(int n_blocks, int n_bins, int
         if (carry > bin_cap) atomicOr(&P->status, (uint32_t)TOI_STATUS_OVERFLOW);
         int acc = 0;
         for (int k = 31; k >= 0; --k) {
-            aux[32 + k] = acc;
-            acc += aux[k];
+            aux[kAuxCursors + k] = acc;
+            acc += aux[kAuxBuckets + k];
         }
         *n_active = acc;
     }
@@ -231,7 +244,7 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
     if (blockIdx.x * kScanBlock >= P->ng * NT * NT) return;   // unused plane groups: never read
     if (threadIdx.x < 32) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int add = aux[64 + blockIdx.x];
+    const int add = aux[kAuxTotals + blockIdx.x];
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
     int c[kScanPer];
 #pragma unroll
@@ -248,7 +261,7 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
     __syncthreads();
     if (threadIdx.x < 32) {
         const int h = hist[threadIdx.x];
-        start[threadIdx.x] = h ? atomicAdd(&aux[32 + threadIdx.x], h) : 0;
+        start[threadIdx.x] = h ? atomicAdd(&aux[kAuxCursors + threadIdx.x], h) : 0;
         hist[threadIdx.x] = 0;
     }
     __syncthreads();
@@ -280,18 +293,26 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
     }
 }
 
-// Work units of the matrix-core passes (one workgroup): the bins of buckets
-// kUnitShift and up (at least kUnitItems items; the first entries of the launch
-// order) are listed unit by unit, ceil(count / kUnitItems) units each, as long
-// as the units fit in kSplitSlots; from the first bin that does not fit on,
-// bins run whole.  cnt[1] = units listed, cnt[2] = bins they cover.
+// Work units of the matrix-core passes (one workgroup).  The bins of the
+// heaviest buckets are listed unit by unit, ceil(count / kUnitItems) units
+// each: every bucket from the top down to kUnitShift (at least kUnitItems
+// items per bin) while the units of the buckets taken fit in kSplitSlots.
+// The cut falls between whole buckets, so which bins are split depends only on
+// the bin counts, not on the order of the bins inside a bucket; the bins of
+// the buckets below the cut run whole.  The split bins are the first entries
+// of the launch order (heaviest bucket first).  cnt[1] = units listed,
+// cnt[2] = bins they cover.
 __global__ __launch_bounds__(1024) void k_units(const int32_t* __restrict__ count, const int32_t* __restrict__ order,
                                                 const int32_t* __restrict__ aux, int4* __restrict__ units,
                                                 int32_t* __restrict__ cnt) {
-    __shared__ int cut_i, cut_p;
-    int n_big = 0;
-    for (int k = kUnitShift; k < 32; ++k) n_big += aux[k];
-    int carry = 0, n_fit = n_big;
+    int n_big = 0, n_units = 0;
+    for (int k = 31; k >= kUnitShift; --k) {   // uniform over the workgroup
+        const int u = aux[kAuxUnits + k];
+        if (n_units + u > kSplitSlots) break;
+        n_units += u;
+        n_big += aux[kAuxBuckets + k];
+    }
+    int carry = 0;
     for (int i0 = 0; i0 < n_big; i0 += 1024) {
         const int i = i0 + (int)threadIdx.x;
         int bin = 0, u = 0;
@@ -301,27 +322,12 @@ __global__ __launch_bounds__(1024) void k_units(const int32_t* __restrict__ coun
         }
         int total;
         const int p0 = carry + block_exclusive_scan(u, total);   // barriers inside
-        if (threadIdx.x == 0) cut_i = INT_MAX;
-        __syncthreads();
-        const bool over = i < n_big && p0 + u > kSplitSlots;
-        if (over) atomicMin(&cut_i, i);
-        __syncthreads();
-        const int cut = cut_i;
-        if (i == cut) cut_p = p0;
-        if (i < n_big && i < cut) {
-            for (int p = 0; p < u; ++p) units[p0 + p] = make_int4(bin, p, u, p0);
-        }
-        __syncthreads();
-        if (cut != INT_MAX) {   // the rest runs whole
-            n_fit = cut;
-            carry = cut_p;
-            break;
-        }
+        for (int p = 0; p < u; ++p) units[p0 + p] = make_int4(bin, p, u, p0);
         carry += total;
     }
     if (threadIdx.x == 0) {
         cnt[1] = carry;
-        cnt[2] = n_fit;
+        cnt[2] = n_big;
     }
 }
 
@@ -342,6 +348,102 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
         const int g = box.g0 + e / (nx * ny);
         const int pos = atomicAdd(&cursor[(size_t)g * tiles + ty * NT + tx], 1);
         if (pos < bin_cap) list[pos] = item;
+    }
+}
+
+// ---------------------------------------------------------------- 2c. order
+// The fill leaves each bin's items in the order of the atomic cursor; these
+// kernels sort every bin's list into increasing item order (the items of a
+// bin are distinct).  Bins of buckets below kUnitShift (fewer than kUnitItems
+// items; the launch order's entries from the heavy buckets' total on) are
+// sorted by one wavefront each, by a bitonic network across the lanes.  The
+// others (the first entries of the launch order) by one workgroup each: a
+// bitonic network whose every comparison puts the smaller value at the lower
+// index (the first substage of each merge compares mirrored positions), so a
+// list of any length sorts as if padded to a power of two with values larger
+// than every item, and the padding is never stored.  Up to kSortLds items the
+// list is sorted in LDS; longer lists in place in HBM (each substage a pass
+// over the list, the workgroup's barrier between passes).
+__device__ inline int heavy_bins(const int32_t* __restrict__ aux) {
+    int n = 0;
+    for (int k = kUnitShift; k < 32; ++k) n += aux[kAuxBuckets + k];
+    return n;
+}
+
+__global__ __launch_bounds__(256) void k_bin_sort_wave(const DevPlan* __restrict__ P, const int32_t* __restrict__ order,
+                                                       const int32_t* __restrict__ n_active,
+                                                       const int32_t* __restrict__ aux,
+                                                       const int32_t* __restrict__ off, int32_t* __restrict__ list) {
+    if (P->status & kStatusFatal) return;
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    const int n_act = *n_active;
+    for (int ob = heavy_bins(aux) + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ob < n_act; ob += waves) {
+        const int bin = order[ob];
+        const int b0 = off[bin], n = off[bin + 1] - b0;   // n < kUnitItems = 64
+        int v = lane < n ? list[b0 + lane] : INT_MAX;
+#pragma unroll
+        for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int o = __shfl_xor(v, j, 64);
+                const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+                v = keep_min ? min(v, o) : max(v, o);
+            }
+        }
+        if (lane < n) list[b0 + lane] = v;
+    }
+}
+
+template <typename Buf>
+__device__ inline void sort_network(Buf a, int n) {
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    const int nt = blockDim.x;
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < P2 / 2; t += nt) {
+                const int blk = t / j, o = t % j;
+                int i, l;
+                if (j == (k >> 1)) {   // mirrored pair of the k-block
+                    i = (t / (k >> 1)) * k + t % (k >> 1);
+                    l = (t / (k >> 1)) * k + k - 1 - t % (k >> 1);
+                } else {
+                    i = blk * 2 * j + o;
+                    l = i + j;
+                }
+                if (l < n) {
+                    const int x = a[i], y = a[l];
+                    if (x > y) {
+                        a[i] = y;
+                        a[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_bin_sort_block(const DevPlan* __restrict__ P,
+                                                         const int32_t* __restrict__ order,
+                                                         const int32_t* __restrict__ aux,
+                                                         const int32_t* __restrict__ off, int32_t* __restrict__ list) {
+    __shared__ int32_t s[kSortLds];
+    if (P->status & kStatusFatal) return;
+    const int n_heavy = heavy_bins(aux);
+    for (int ob = blockIdx.x; ob < n_heavy; ob += gridDim.x) {
+        const int bin = order[ob];
+        const int b0 = off[bin], n = off[bin + 1] - b0;
+        if (n <= kSortLds) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = list[b0 + i];
+            __syncthreads();
+            sort_network(s, n);
+            for (int i = threadIdx.x; i < n; i += blockDim.x) list[b0 + i] = s[i];
+        } else {
+            sort_network(list + b0, n);
+        }
+        __syncthreads();   // the write-back precedes the next bin's loads into LDS
     }
 }
 
@@ -861,6 +963,8 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
     return e != hipSuccess ? e : launch_gridder(c, s);
 }
 
+constexpr int kBinSortBlocks = 512, kBinSortWaveGroups = 2048;
+
 hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
     const toi_params& p = c->p;
     const int M = c->M, NT = c->NT;
@@ -888,9 +992,14 @@ hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
                            c->plan);
         hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->bin_count, c->bin_order, c->bin_aux,
                            c->units, c->scratch_i);
-        if (n_items > 0)
+        if (n_items > 0) {
             hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, c->items, n_items, NT,
                                c->bin_cap, c->bin_cursor, c->bin_list);
+            hipLaunchKernelGGL(k_bin_sort_block, dim3(kBinSortBlocks), dim3(1024), 0, c->stream, c->plan,
+                               c->bin_order, c->bin_aux, c->bin_off, c->bin_list);
+            hipLaunchKernelGGL(k_bin_sort_wave, dim3(kBinSortWaveGroups), dim3(256), 0, c->stream, c->plan,
+                               c->bin_order, c->scratch_i, c->bin_aux, c->bin_off, c->bin_list);
+        }
     }
     return hipGetLastError();
 }

@@ -57,6 +57,14 @@ constexpr int kScanBlock = 4096;   // bins per workgroup of the bin scan
 // snapshot (bins past that run whole).
 constexpr int kUnitShift = 6, kUnitItems = 1 << kUnitShift;
 constexpr int kSplitSlots = 16384;
+// Layout of the bin scan's auxiliary array: per floor(log2(count)) bucket the
+// number of non-empty bins, the launch-order cursor and the work units of its
+// bins (ceil(count / kUnitItems) each), then one total per scan workgroup.
+constexpr int kAuxBuckets = 0, kAuxCursors = 32, kAuxUnits = 64, kAuxTotals = 96;
+// After the list fill, every bin's items are put in increasing item order:
+// bins of fewer than kUnitItems items by one wavefront, larger ones by a
+// workgroup in LDS up to kSortLds items, beyond that in place in HBM.
+constexpr int kSortLds = 16384;
 constexpr int kPartFloats = 64 * 32;   // one partial tile: 64 cells x up to 16 complex planes
 
 // Gridder variant chosen by the autotuner (toi_tune / toi_set_tuning):
@@ -182,7 +190,7 @@ struct toi_ctx {
     int32_t* bin_list;    // [bin capacity]
     int32_t* bin_order;   // [NG_max][NT*NT] non-empty bins, heaviest first (count in scratch_i[0];
                           // scratch_i[1]: units of split bins, scratch_i[2]: bins listed as units)
-    int32_t* bin_aux;     // [32] bucket sizes, [32] bucket cursors, then one total per scan block
+    int32_t* bin_aux;     // bucket sizes, cursors and unit counts (32 each), one total per scan block
     int4* units;          // [kSplitSlots] listed work units {bin, part, parts, index of part 0}
     float* split_part;    // [kSplitSlots][kPartFloats] partial tiles of split bins ([plane][cell] complex)
     int bin_cap;

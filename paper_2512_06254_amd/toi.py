@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtoi.so")
 
 TOI_OK, TOI_EINVAL, TOI_ENOMEM, TOI_EDEVICE, TOI_EUNSUPPORTED = range(5)
-STATUS_NO_SAMPLES, STATUS_DEGENERATE, STATUS_PLANES = 1, 2, 4
+STATUS_NO_SAMPLES, STATUS_DEGENERATE, STATUS_PLANES, STATUS_OVERFLOW = 1, 2, 4, 8
 
 
 class ToiError(RuntimeError):
@@ -32,6 +32,7 @@ class Params(ctypes.Structure):
         ("cheb_gamma", ctypes.c_double), ("max_planes", ctypes.c_int32), ("support", ctypes.c_int32),
         ("corr_mask", ctypes.c_uint32), ("tile", ctypes.c_int32), ("n_row_max", ctypes.c_int32),
         ("n_chan", ctypes.c_int32), ("n_corr", ctypes.c_int32), ("n_ant", ctypes.c_int32),
+        ("bin_cap", ctypes.c_int32),
     ]
 
 
@@ -159,7 +160,7 @@ class Imager:
     def __init__(self, n_pix: int, cell_deg: float, n_row_max: int, n_chan: int, n_corr: int, *,
                  mode: int = 3, n_slab: int = 0, cheb_k: int = 0, max_planes: int = 0, n_ant: int = 0,
                  tile: int = 32, corr_mask: int = 0, alpha_target: float = 10.0,
-                 cheb_gamma: float = 1e-2, device=None):
+                 cheb_gamma: float = 1e-2, bin_cap: int = 0, device=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
@@ -170,12 +171,17 @@ class Imager:
         p.mode, p.n_slab, p.cheb_k, p.max_planes = mode, n_slab, cheb_k, max_planes
         p.n_ant, p.tile, p.corr_mask = n_ant, tile, corr_mask
         p.alpha_target, p.cheb_gamma = alpha_target, cheb_gamma
+        p.bin_cap = bin_cap
         self.params = p
         self.n_pix, self.tile = n_pix, tile
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(L.toi_create(ctypes.byref(p), ctypes.c_void_p(self._stream()), ctypes.byref(h)))
         self.ctx = h
+        # bumped by every call that runs sample prep or binning (grid, image_batch,
+        # ingest, tune): the per-snapshot state the adjoint reads then belongs to
+        # another snapshot
+        self._gen = 0
         # held by the instance: at interpreter exit the module's globals may be
         # cleared before a remaining Imager is collected
         self._destroy = L.toi_destroy
@@ -196,6 +202,7 @@ class Imager:
     def grid(self, snap: dict):
         self._sync_stream()
         self._snap = snapshot_struct(snap)
+        self._gen += 1
         _check(lib().toi_grid(self.ctx, ctypes.byref(self._snap)), self.ctx)
 
     def image(self, out=None, tplane: bool = False):
@@ -274,6 +281,7 @@ class Imager:
         arr = (Snapshot * len(snaps))(*[snapshot_struct(s) for s in snaps])
         self._keep = arr
         self._sync_stream()
+        self._gen += 1
         _check(lib().toi_image_batch(self.ctx, arr, len(snaps), _ptr(images_out), _ptr(tlisi_out)),
                self.ctx)
 
@@ -282,6 +290,7 @@ class Imager:
         arr = (Snapshot * len(host_snaps))(*[host_snapshot_struct(s) for s in host_snaps])
         self._keep_ingest = (arr, host_snaps)
         self._sync_stream()
+        self._gen += 1
         _check(lib().toi_ingest(self.ctx, arr, len(host_snaps), _ptr(images_out), _ptr(tlisi_out)), self.ctx)
 
     def profile(self, enable: bool = True, stages=None):
@@ -306,6 +315,7 @@ class Imager:
         v = ctypes.c_int32()
         ms = (ctypes.c_float * TUNE_VARIANTS)()
         self._sync_stream()
+        self._gen += 1
         _check(lib().toi_tune(self.ctx, ctypes.byref(desc), ctypes.byref(v), ms), self.ctx)
         return v.value, list(ms)
 
@@ -370,16 +380,15 @@ def _autograd_function():
                 s["gains"] = gains.contiguous()
             imager.grid(s)
             img = imager.image()
-            imager._last_snap = s
-            ctx.imager, ctx.snap, ctx.has_gains = imager, s, gains is not None
+            ctx.imager, ctx.snap, ctx.has_gains, ctx.gen = imager, s, gains is not None, imager._gen
             return img
 
         @staticmethod
         def backward(ctx, grad_img):
             im, s = ctx.imager, ctx.snap
-            if getattr(im, "_last_snap", None) is not s:
-                im.grid(s)             # the context imaged another snapshot since: re-establish its plan
-                im._last_snap = s
+            if im._gen != ctx.gen:
+                im.grid(s)             # the context prepared another snapshot since: re-establish this one's
+                ctx.gen = im._gen      # plan, records and bins
             want_g = ctx.has_gains and ctx.needs_input_grad[1]
             gv, gg = im.degrid(grad_img.contiguous(), s, want_vis=ctx.needs_input_grad[0], want_gains=want_g)
             return gv, gg, None, None

@@ -120,3 +120,32 @@ def test_adjoint_sizes_whose_first_radix_is_the_pass_radix(n_pix):
     print(f"[adjoint n_pix={n_pix}] grad_vis err {e_v:.3e}  grad_gains err {e_g:.3e}", flush=True)
     assert e_v < 1e-4 and e_g < 1e-4
     im.close()
+
+
+def test_backward_after_the_context_gridded_another_snapshot():
+    """Forward on snapshot A, then grid() (and a batch) of snapshot B on the same
+    context, then backward of A: the gradients are A's (the context's plan,
+    records and bins are re-established for A), checked against the oracle."""
+    import torch
+    from paper_2512_06254_amd import toi as T
+    wl, snap_a = _setup(seed=0)
+    _, snap_b = _setup(seed=7)
+    im = _imager(wl, snap_a, 1, 8)
+    da, db = T.to_device(snap_a), T.to_device(snap_b)
+    vis = da["vis"].clone().requires_grad_(True)
+    gains = da["gains"].clone().requires_grad_(True)
+    img = T.toi_image(im, da, vis=vis, gains=gains)
+    rng = np.random.default_rng(9)
+    y = rng.normal(size=(wl.n_pix, wl.n_pix))
+    loss = (img * torch.from_numpy(y.astype(np.float32)).cuda()).sum()
+    im.grid(db)                                   # another snapshot's plan, records and bins
+    out = torch.zeros((2, wl.n_pix, wl.n_pix), dtype=torch.float32, device="cuda")
+    im.image_batch([db, db], out)
+    loss.backward()
+    op = A.SnapshotOperator(snap_a, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=8)
+    gv_ref, gg_ref = A.vis_gradients(snap_a, op.res.samples, op.adjoint(y))
+    e_v = np.abs(vis.grad.cpu().numpy() - gv_ref).max() / np.abs(gv_ref).max()
+    e_g = np.abs(gains.grad.cpu().numpy() - gg_ref).max() / np.abs(gg_ref).max()
+    print(f"[stale] grad_vis err {e_v:.3e}  grad_gains err {e_g:.3e}", flush=True)
+    assert e_v < 1e-4 and e_g < 1e-4
+    im.close()
