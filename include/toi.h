@@ -228,18 +228,20 @@ toi_status toi_image_batch(toi_ctx* ctx, const toi_snapshot* snaps, int32_t n,
 toi_status toi_ingest(toi_ctx* ctx, const toi_snapshot* host_snaps, int32_t n,
                       float* images_out, float* tlisi_out);
 
-/* Autotuning of the gridder (batched use): the variants differ in the
- * accumulation unit (bit 0: matrix cores -- one v_mfma outer product per
- * sample and 8 x 8 grid tile, accumulators in registers; else vector ALU with
- * the plane group in LDS), workgroup width of the vector-ALU kernel (bit 1:
- * 1024 threads, else 512) and the plane schedule (bit 2: 8 planes per pass
- * over a tile, else 16; a variant whose LDS would exceed 160 KB uses 8).  All
- * variants compute the same image up to FP32 rounding order.  toi_tune
- * synchronises, times grid + image of `sample` with every variant (HIP events,
- * after one warm-up), keeps the fastest in the context and returns it in
- * *variant_out; ms_out (host, TOI_TUNE_VARIANTS entries, nullable) receives
- * each variant's time.  It overwrites the context's workspaces.
- * toi_set_tuning selects a variant directly (default 1, matrix cores). */
+/* Autotuning of the gridder (batched use).  The gridder accumulates each
+ * 8 x 8 grid tile of a plane group in one wavefront's matrix-core
+ * accumulators, over a work unit of the tile's item list; the variants differ
+ * in the work-unit size (bits 0-1: bins are split into units of at most
+ * 32 << bits items -- the subgrid work granularity) and the plane schedule
+ * (bit 2: 8 planes per pass over a tile on the FP32 matrix cores, else 16
+ * planes per pass on the bf16 matrix cores with operands split as hi + lo).
+ * Every variant computes the same image up to FP32 rounding order, and each
+ * variant's image is the same from run to run.  toi_tune synchronises, times
+ * grid + image of `sample` with every variant (HIP events, after one
+ * warm-up), keeps the fastest in the context and returns it in *variant_out;
+ * ms_out (host, TOI_TUNE_VARIANTS entries, nullable) receives each variant's
+ * time.  It overwrites the context's workspaces.  toi_set_tuning selects a
+ * variant directly (default 1: 64-item units, 16 planes per pass). */
 #define TOI_TUNE_VARIANTS 8
 toi_status toi_tune(toi_ctx* ctx, const toi_snapshot* sample, int32_t* variant_out, float* ms_out);
 toi_status toi_set_tuning(toi_ctx* ctx, int32_t variant);
@@ -249,6 +251,16 @@ toi_status toi_set_tuning(toi_ctx* ctx, int32_t variant);
  * word.  Diagnostics only: the imaging loop never calls it. */
 toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* wsum,
                          int32_t* n_slab, int32_t* cheb_k, uint32_t* status);
+
+/* Synchronise and report the gridding work of the last gridded snapshot (host
+ * outputs, each nullable; diagnostics for measurement, never called by the
+ * imaging loop): entries = (work item, 8 x 8 tile, plane group) entries of
+ * the bin lists; tiles = (plane group, tile) pairs holding samples (the grid
+ * tiles the gridder writes and the row pass reads, per plane of the group);
+ * tile_rows = (plane group, tile row) pairs holding samples (the row pass
+ * writes 8 grid rows of N kept bins per plane of the group for each);
+ * units = work units of split bins. */
+toi_status toi_bin_info(toi_ctx* ctx, int64_t* entries, int64_t* tiles, int64_t* tile_rows, int64_t* units);
 
 /* Measurement support.  Stages timed with HIP events on the context's stream:
  * TOI_STAGE_PREP (sample statistics, basis, plan), TOI_STAGE_BIN (work

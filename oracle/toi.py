@@ -296,21 +296,23 @@ def moments(r, x, plan: Plan, n_pix, cell_deg, j1=None, j2=None):
     columns j1 and rows j2 (all pixels by default); shape (n_slab, K, len(j2), len(j1)).
 
     The sum over samples runs in chunks; each chunk's phasors are formed once
-    and contracted with every order k (a matrix product over the samples)."""
+    and contracted with every order k in one matrix product over the samples
+    (the orders side by side in the columns)."""
     t1, t2 = pixel_subgrid(n_pix, cell_deg, j1, j2)
     p, s = slab_of(r[:, 2], plan)
     T = cheb_T(plan.K, s)
-    out = np.zeros((plan.n_slab, plan.K, t2.size, t1.size), dtype=np.complex128)
-    chunk = max(512, 4_000_000 // max(t1.size, t2.size))
+    K, n1, n2 = plan.K, t1.size, t2.size
+    out = np.zeros((plan.n_slab, n2, n1, K), dtype=np.complex128)
+    chunk = max(256, (1 << 22) // (n1 * K))
     for ps in range(plan.n_slab):
         sel = np.nonzero(p == ps)[0]
         for q0 in range(0, sel.size, chunk):
             q = sel[q0:q0 + chunk]
             e1 = _phasor_matrix(r[q, 0], t1)                         # (nq, columns)
             e2t = _phasor_matrix(r[q, 1], t2).T                      # (rows, nq)
-            for k in range(plan.K):
-                out[ps, k] += e2t @ (e1 * (x[q] * T[q, k])[:, None])
-    return out
+            xt = x[q, None] * T[q]                                   # (nq, K)
+            out[ps] += (e2t @ (e1[:, :, None] * xt[:, None, :]).reshape(q.size, n1 * K)).reshape(n2, n1, K)
+    return np.ascontiguousarray(out.transpose(0, 3, 1, 2))
 
 
 def image_3d_cheb(r, x, W, omega, V, plan: Plan, n_pix, cell_deg, M=None, j1=None, j2=None):

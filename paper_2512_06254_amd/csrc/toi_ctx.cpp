@@ -209,8 +209,6 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
             return delete c, fail(nullptr, TOI_EINVAL, "toi_create: n_slab * cheb_k exceeds max_planes");
         c->P_cap = cap;
     }
-    const int k = c->forced_K;
-    c->kmax = (k == 1) ? 1 : (k > 0 && k <= 4) ? 4 : (k > 0 && k <= 8) ? 8 : (k > 0 && k <= 16) ? 16 : 32;
     c->tuning = kTuneDefault;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -422,6 +420,35 @@ toi_status toi_plan_info(toi_ctx* c, double V_out[9], double* omega, double* wsu
     if (n_slab) *n_slab = h.n_slab;
     if (cheb_k) *cheb_k = h.K;
     if (status) *status = h.status;
+    return TOI_OK;
+}
+
+toi_status toi_bin_info(toi_ctx* c, int64_t* entries, int64_t* tiles, int64_t* tile_rows, int64_t* units) {
+    if (!c) return fail(nullptr, TOI_EINVAL, "toi_bin_info: ctx is NULL");
+    DevPlan h{};
+    const int NT = c->NT, words = (NT + 31) / 32;
+    const size_t n_bins = (size_t)c->NG_max * NT * NT;
+    int32_t total = 0, cnt[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(&h, c->plan, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&total, c->bin_off + n_bins, sizeof(total), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt, c->scratch_i, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "toi_bin_info");
+    const int ng = std::max(0, std::min(h.ng, c->NG_max));
+    std::vector<uint32_t> tb((size_t)ng * NT * words), rb((size_t)ng * words);
+    if (ng > 0) {
+        e = hipMemcpy(tb.data(), c->tile_bits, tb.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(rb.data(), c->row_bits, rb.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_check(c, e, "toi_bin_info");
+    }
+    int64_t nt = 0, nr = 0;
+    for (uint32_t w : tb) nt += __builtin_popcount(w);
+    for (uint32_t w : rb) nr += __builtin_popcount(w);
+    if (entries) *entries = total;
+    if (tiles) *tiles = nt;
+    if (tile_rows) *tile_rows = nr;
+    if (units) *units = cnt[1];
     return TOI_OK;
 }
 

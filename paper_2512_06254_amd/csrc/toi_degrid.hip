@@ -365,7 +365,7 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
         const int g = bid / tiles, tile = bid % tiles;
         if (g >= P->ng) continue;
         int b0, b1;
-        work_unit_items(un, bin_off, bin_cap, b0, b1);
+        work_unit_items(un, bin_off, bin_cap, P->unit_shift, b0, b1);
         if (b1 <= b0) continue;
         int s0, s1, k0, k1;
         group_range(g, P, s0, s1, k0, k1);   // one slab per group

@@ -106,7 +106,7 @@ __device__ inline void group_range(int g, const DevPlan* __restrict__ P, int& s0
 
 // Work unit ob of the matrix-core tile passes (toi_grid, toi_degrid).  The
 // first cnt[1] units come from the bins listed unit by unit (the heaviest
-// cnt[2] non-empty bins, kUnitItems items per unit); the rest are the other
+// cnt[2] non-empty bins, 2^unit_shift items per unit); the rest are the other
 // non-empty bins, whole, in their launch order.  Item range [b0, b1) of the
 // bin's list; parts > 1 marks a split bin whose part 0 is unit slot0.
 struct WorkUnit {
@@ -122,13 +122,13 @@ __device__ inline WorkUnit work_unit(int ob, const int4* __restrict__ units, con
     }
     return WorkUnit{order[cnt[2] + ob - n_split], 0, 1, -1};
 }
-__device__ inline void work_unit_items(const WorkUnit& u, const int32_t* __restrict__ bin_off, int bin_cap, int& b0,
-                                       int& b1) {
+__device__ inline void work_unit_items(const WorkUnit& u, const int32_t* __restrict__ bin_off, int bin_cap,
+                                       int unit_shift, int& b0, int& b1) {
     const int e = min(bin_off[u.bin + 1], bin_cap);
     b0 = bin_off[u.bin];
     if (u.parts > 1) {
-        b0 += u.part * kUnitItems;
-        b1 = min(b0 + kUnitItems, e);
+        b0 += u.part << unit_shift;
+        b1 = min(b0 + (1 << unit_shift), e);
     } else {
         b1 = e;
     }

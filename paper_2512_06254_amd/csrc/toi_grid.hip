@@ -9,17 +9,13 @@
 //     writes each sample's gridding record (cell, offsets, slab, value).
 //  2. k_scan_local / k_scan_top / k_scan_apply turn the counts into list
 //     offsets, a heaviest-first launch order and occupancy bit masks; k_units
-//     splits the heaviest bins into work units of at most kUnitItems items;
+//     splits the heaviest bins into work units of at most 2^unit_shift items;
 //     k_bin_fill writes the item lists and k_bin_sort_* put every list in
 //     increasing item order, so that the accumulation order, and the image,
 //     is the same on every run.
-//  3. k_grid_tiles_mfma (default): one wavefront per work unit keeps the whole
-//     tile in matrix-core accumulators and writes it to HBM once (the units of
-//     a split bin add their partial tiles in a fixed order first).
-//     k_grid_tiles (vector ALU): one workgroup per bin accumulates the tile's
-//     planes in LDS; each wavefront walks one item at a time with lane (i, j)
-//     owning the cells x = i, y = j (mod 8) of the footprints (Romein, ICS
-//     2012).
+//  3. k_grid_tiles_mfma: one wavefront per work unit keeps the whole tile in
+//     matrix-core accumulators and writes it to HBM once (the units of a split
+//     bin add their partial tiles in a fixed order first).
 // Tiles without samples are never written; the FFT passes read the
 // occupancy masks and treat them as zero.
 //
@@ -183,6 +179,7 @@ __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__
         hist[threadIdx.x] = 0;
         hunits[threadIdx.x] = 0;
     }
+    const int ushift = P->unit_shift;
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
     int c[kScanPer], sum = 0;
 #pragma unroll
@@ -199,7 +196,7 @@ __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__
         if (c[j] > 0) {
             const int k = 31 - __clz(c[j]);
             atomicAdd(&hist[k], 1);
-            atomicAdd(&hunits[k], (c[j] + kUnitItems - 1) >> kUnitShift);
+            atomicAdd(&hunits[k], (c[j] + (1 << ushift) - 1) >> ushift);
         }
     }
     __syncthreads();
@@ -294,19 +291,21 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
 }
 
 // Work units of the matrix-core passes (one workgroup).  The bins of the
-// heaviest buckets are listed unit by unit, ceil(count / kUnitItems) units
-// each: every bucket from the top down to kUnitShift (at least kUnitItems
-// items per bin) while the units of the buckets taken fit in kSplitSlots.
+// heaviest buckets are listed unit by unit, ceil(count / U) units each
+// (U = 2^unit_shift items, from the tuning): every bucket from the top down to
+// unit_shift (at least U items per bin) while the units of the buckets taken
+// fit in kSplitSlots.
 // The cut falls between whole buckets, so which bins are split depends only on
 // the bin counts, not on the order of the bins inside a bucket; the bins of
 // the buckets below the cut run whole.  The split bins are the first entries
 // of the launch order (heaviest bucket first).  cnt[1] = units listed,
 // cnt[2] = bins they cover.
-__global__ __launch_bounds__(1024) void k_units(const int32_t* __restrict__ count, const int32_t* __restrict__ order,
-                                                const int32_t* __restrict__ aux, int4* __restrict__ units,
-                                                int32_t* __restrict__ cnt) {
+__global__ __launch_bounds__(1024) void k_units(const DevPlan* __restrict__ P, const int32_t* __restrict__ count,
+                                                const int32_t* __restrict__ order, const int32_t* __restrict__ aux,
+                                                int4* __restrict__ units, int32_t* __restrict__ cnt) {
+    const int ushift = P->unit_shift, U = 1 << ushift;
     int n_big = 0, n_units = 0;
-    for (int k = 31; k >= kUnitShift; --k) {   // uniform over the workgroup
+    for (int k = 31; k >= ushift; --k) {       // uniform over the workgroup
         const int u = aux[kAuxUnits + k];
         if (n_units + u > kSplitSlots) break;
         n_units += u;
@@ -318,7 +317,7 @@ __global__ __launch_bounds__(1024) void k_units(const int32_t* __restrict__ coun
         int bin = 0, u = 0;
         if (i < n_big) {
             bin = order[i];
-            u = (count[bin] + kUnitItems - 1) / kUnitItems;
+            u = (count[bin] + U - 1) >> ushift;
         }
         int total;
         const int p0 = carry + block_exclusive_scan(u, total);   // barriers inside
@@ -354,8 +353,8 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
 // ---------------------------------------------------------------- 2c. order
 // The fill leaves each bin's items in the order of the atomic cursor; these
 // kernels sort every bin's list into increasing item order (the items of a
-// bin are distinct).  Bins of buckets below kUnitShift (fewer than kUnitItems
-// items; the launch order's entries from the heavy buckets' total on) are
+// bin are distinct).  Bins of buckets below kSortShift (fewer than 64 items;
+// the launch order's entries from the heavy buckets' total on) are
 // sorted by one wavefront each, by a bitonic network across the lanes.  The
 // others (the first entries of the launch order) by one workgroup each: a
 // bitonic network whose every comparison puts the smaller value at the lower
@@ -366,7 +365,7 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
 // over the list, the workgroup's barrier between passes).
 __device__ inline int heavy_bins(const int32_t* __restrict__ aux) {
     int n = 0;
-    for (int k = kUnitShift; k < 32; ++k) n += aux[kAuxBuckets + k];
+    for (int k = kSortShift; k < 32; ++k) n += aux[kAuxBuckets + k];
     return n;
 }
 
@@ -380,7 +379,7 @@ __global__ __launch_bounds__(256) void k_bin_sort_wave(const DevPlan* __restrict
     const int n_act = *n_active;
     for (int ob = heavy_bins(aux) + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ob < n_act; ob += waves) {
         const int bin = order[ob];
-        const int b0 = off[bin], n = off[bin + 1] - b0;   // n < kUnitItems = 64
+        const int b0 = off[bin], n = off[bin + 1] - b0;   // n < 2^kSortShift = 64
         int v = lane < n ? list[b0 + lane] : INT_MAX;
 #pragma unroll
         for (int k = 2; k <= 64; k <<= 1) {
@@ -447,234 +446,7 @@ __global__ __launch_bounds__(1024) void k_bin_sort_block(const DevPlan* __restri
     }
 }
 
-// ---------------------------------------------------------------- 3. tiles
-// Shared by both tile kernels.  Lane l prepares channel c0 + l of an item for
-// tile (tx, ty): its footprint start (ix, iy) (first of the 8 x 8 cells, in
-// [0, M) after wrapping), slab sp, Chebyshev argument ss, value g x and the
-// offsets (ox, oy) of the sample from the start, in (3, 4].  act: the sample
-// is kept, its slab is in [s0, s1) and its footprint overlaps the tile.
-struct Prep {
-    int ix, iy, sp;
-    float ss, vr, vi, ox, oy;
-    bool act;
-};
-__device__ inline Prep prepare_sample(const double* __restrict__ uvw, const float2* __restrict__ vis,
-                                      const float* __restrict__ weight, const uint8_t* __restrict__ flag,
-                                      const double* __restrict__ freq, int n_chan, int n_corr, uint32_t mask,
-                                      const DevPlan* __restrict__ P, int M, bool cheb, const Track& trk, float2 gr,
-                                      int r, int c, int c1, int tx, int ty, int s0, int s1) {
-    Prep q;
-    q.ix = 0; q.iy = 0; q.sp = 0;
-    q.ss = 0.f; q.vr = 0.f; q.vi = 0.f; q.ox = 4.f; q.oy = 4.f;
-    q.act = false;
-    if (c >= c1) return q;
-    float xr, xi;
-    const float w = sample_value(vis, weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask, xr, xi);
-    if (!(w > 0.f)) return q;
-    const double nu = freq[c];   // FP64 coordinates once per sample
-    if (cheb) {
-        const double r3 = trk.a3 * nu;
-        q.sp = slab_index(r3, P);
-        q.ss = (float)div_by(r3 - (P->r3min + (2 * q.sp + 1) * P->dr3), P->dr3, P->inv_dr3);
-    }
-    const double hM = 0.5 * M;
-    const double X = hM + trk.ax * nu, Y = hM + trk.ay * nu;
-    const double fx0 = ceil(X - 4.0), fy0 = ceil(Y - 4.0);
-    const int ix = (int)fx0, iy = (int)fy0;
-    q.ox = (float)(X - fx0);
-    q.oy = (float)(Y - fy0);
-    const int ddx = (ix - tx * kTile) & (M - 1), ddy = (iy - ty * kTile) & (M - 1);
-    q.act = (q.sp >= s0 && q.sp < s1) && (ddx < kTile || ddx >= M - 7) && (ddy < kTile || ddy >= M - 7);
-    q.ix = ix & (M - 1);
-    q.iy = iy & (M - 1);
-    q.vr = xr * gr.x - xi * gr.y;
-    q.vi = xr * gr.y + xi * gr.x;
-    return q;
-}
-
-// The eight x and eight y kernel weights of a footprint with offsets (ox, oy).
-__device__ inline void footprint_weights(float ox, float oy, float* wv) {
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        wv[d] = es_kernel(((float)d - ox) * 0.25f);
-        wv[8 + d] = es_kernel(((float)d - oy) * 0.25f);
-    }
-}
-
-__device__ inline void store16(float* dst, const float* v) {
-    float4* d4 = reinterpret_cast<float4*>(dst);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) d4[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
-}
-
-// ------------------------------------------------- 3a. tiles, vector ALU
-// LDS tile layout: planar real and imaginary parts, [plane][ly][swizzled lx],
-// the column rotated by 8 (ly / 2 mod 4) so that the 64 cells of one 8 x 8
-// footprint fall in distinct banks when they are added together.
-__device__ inline int tile_index(int ly, int lx) { return ly * kTile + ((lx + 8 * ((ly >> 1) & 3)) & (kTile - 1)); }
-
-// Each wavefront walks one item at a time.  Lane l first prepares channel
-// c0 + l and writes the eight x and eight y kernel weights of its footprint
-// to the wave's LDS staging area.  The walk then takes the item's samples
-// that touch this tile and plane group in channel order: lane (i, j) owns the
-// footprint cell with x = i, y = j (mod 8) and reads its weight wx[dx] wy[dy]
-// from the staging area; the plane values of that cell (Chebyshev recurrence
-// per sample) stay in registers until the track moves the cell (Romein, ICS
-// 2012), then they are added to LDS.
-template <int KACC>
-__global__ __launch_bounds__(1024) void k_grid_tiles(
-    const double* __restrict__ uvw, const float2* __restrict__ vis, const float* __restrict__ weight,
-    const uint8_t* __restrict__ flag, const double* __restrict__ freq, const int32_t* __restrict__ ant1,
-    const int32_t* __restrict__ ant2, const float2* __restrict__ gains, int n_ant, int n_chan, int n_corr,
-    uint32_t mask, int mode, const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
-    const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
-    const int32_t* __restrict__ order, const int32_t* __restrict__ n_active, float2* __restrict__ grid) {
-    extern __shared__ float lds[];   // re[gp][TT], im[gp][TT], then per wave: w[64][16]
-    constexpr int TT = kTile * kTile;
-    const int tiles = NT * NT;
-    // Non-empty bins in decreasing order of work, dealt round-robin over the
-    // workgroups (the dispatcher spreads consecutive workgroups over the
-    // XCDs; tiles with samples cluster around the uv centre, so contiguous
-    // ranges per XCD would leave most XCDs idle).
-    if (P->status & kStatusFatal) return;
-    const int n_bins_active = *n_active;
-    for (int ob = blockIdx.x; ob < n_bins_active; ob += gridDim.x) {
-    const int bid = order[ob];
-    const int g = bid / tiles, tile = bid % tiles;
-    if (g >= P->ng) continue;
-    const int b0 = bin_off[(size_t)g * tiles + tile];
-    const int b1 = min(bin_off[(size_t)g * tiles + tile + 1], bin_cap);
-    if (b1 <= b0) continue;
-    int s0, s1, k0, k1;
-    group_range(g, P, s0, s1, k0, k1);
-    const int nk = k1 - k0;
-    const int n_planes = (s1 - s0) * nk;
-    float* lre = lds;
-    float* lim = lds + P->gp * TT;
-    for (int i = threadIdx.x; i < n_planes * TT; i += blockDim.x) { lre[i] = 0.f; lim[i] = 0.f; }
-    __syncthreads();
-
-    const int tx = tile % NT, ty = tile / NT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
-    const int li = lane & 7, lj = lane >> 3;
-    float* sw = lds + 2 * P->gp * TT + wave * 64 * 16;   // [64][16]: wx[0..7], wy[0..7]
-    const bool cheb = (mode == 3) && (P->dr3 > 0.0);
-    const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
-
-    for (int it = b0 + wave; it < b1; it += n_waves) {
-        const int item = list[it];
-        const int r = item / n_chunks;
-        const int c0 = (item % n_chunks) * kItemChans, c1 = min(n_chan, c0 + kItemChans);
-        const Track trk = row_track(uvw, r, P, M, cell_rad);
-        const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
-        const Prep pr = prepare_sample(uvw, vis, weight, flag, freq, n_chan, n_corr, mask, P, M, cheb, trk, gr, r,
-                                       c0 + lane, c1, tx, ty, s0, s1);
-        uint64_t pending = __ballot(pr.act);
-        if (pending == 0) continue;
-        {
-            float wv[16];
-            footprint_weights(pr.ox, pr.oy, wv);
-            store16(sw + lane * 16, wv);
-        }
-        lds_order();                       // staging writes precede the walk's reads
-        int cur_x = 0, cur_y = 0, cur_p = -1;
-        bool in = false;
-        float ar[KACC], ai[KACC];
-#pragma unroll
-        for (int k = 0; k < KACC; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
-
-        auto flush = [&]() {
-            if (!in) return;
-            const int ci = (cur_p - s0) * nk * TT + tile_index(cur_y & (kTile - 1), cur_x & (kTile - 1));
-            if (nk == KACC) {
-#pragma unroll
-                for (int k = 0; k < KACC; ++k) {
-                    atomicAdd(lre + ci + k * TT, ar[k]);
-                    atomicAdd(lim + ci + k * TT, ai[k]);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < KACC; ++k) {
-                    if (k < nk) {
-                        atomicAdd(lre + ci + k * TT, ar[k]);
-                        atomicAdd(lim + ci + k * TT, ai[k]);
-                    }
-                }
-            }
-        };
-        // Software-pipelined walk (wave-uniform, one sample per step): the
-        // staged weights of the next sample are read from LDS while the
-        // current sample's planes are accumulated.
-        struct Smp {
-            int cx, cy, p;
-            float wx, wy, vr, vi, s;
-        };
-        auto fetch = [&](Smp& m) {
-            const int q = __ffsll((unsigned long long)pending) - 1;
-            pending &= pending - 1;
-            const int qx = __builtin_amdgcn_readlane(pr.ix, q), qy = __builtin_amdgcn_readlane(pr.iy, q);
-            m.p = __builtin_amdgcn_readlane(pr.sp, q);
-            m.vr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.vr), q));
-            m.vi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.vi), q));
-            m.s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pr.ss), q));
-            const int dx = (li - qx) & 7, dy = (lj - qy) & 7;
-            m.cx = qx + dx;
-            m.cy = qy + dy;
-            m.wx = sw[q * 16 + dx];
-            m.wy = sw[q * 16 + 8 + dy];
-        };
-        auto process = [&](const Smp& m) {
-            if (m.cx != cur_x || m.cy != cur_y || m.p != cur_p) {
-                flush();
-                cur_x = m.cx; cur_y = m.cy; cur_p = m.p;
-                in = (((m.cy & (M - 1)) >> kTileShift) == ty) && (((m.cx & (M - 1)) >> kTileShift) == tx);
-#pragma unroll
-                for (int k = 0; k < KACC; ++k) { ar[k] = 0.f; ai[k] = 0.f; }
-            }
-            if (!in) return;
-            const float w = m.wx * m.wy;
-            const float vr = w * m.vr, vi = w * m.vi;
-            float t, tm1;
-            cheb_start(m.s, k0, t, tm1);                // t = T_{k0}(s), tm1 = T_{k0 - 1}(s)
-#pragma unroll
-            for (int k = 0; k < KACC; ++k) {
-                ar[k] += t * vr;
-                ai[k] += t * vi;
-                const float tn = 2.f * m.s * t - tm1;
-                tm1 = t;
-                t = tn;
-            }
-        };
-        Smp sa, sb;
-        fetch(sa);                                      // pending is non-zero here
-        while (true) {
-            const bool m1 = pending != 0;
-            if (m1) fetch(sb);
-            process(sa);
-            if (!m1) break;
-            const bool m2 = pending != 0;
-            if (m2) fetch(sa);
-            process(sb);
-            if (!m2) break;
-        }
-        flush();
-        lds_order();                       // the walk's reads precede the next item's staging writes
-    }
-    __syncthreads();
-    // write the tile's planes (only the planes of this group)
-    for (int i = threadIdx.x; i < n_planes * TT; i += blockDim.x) {
-        const int pl = i / TT, cell = i % TT;
-        const int ly = cell / kTile, lx = cell % kTile;
-        const int pg = (s0 + pl / nk) * P->K + k0 + pl % nk;   // global plane index
-        const int li2 = pl * TT + tile_index(ly, lx);
-        grid[((size_t)pg * M + ty * kTile + ly) * M + tx * kTile + lx] = make_float2(lre[li2], lim[li2]);
-    }
-    __syncthreads();   // the write-out reads precede the next tile's clear
-    }
-}
-
-// ------------------------------------------------- 3b. tiles, matrix cores
-constexpr int kValuWorkgroups = 2048;   // 8 workgroups per CU
+// ---------------------------------------------------------------- 3. tiles, matrix cores
 
 // Matrix-core gridder.  Tiles are 8 x 8 cells: the tile's 64 cells are the
 // rows, the group's planes (order, slab) x {Re, Im} the columns.  The
@@ -745,7 +517,7 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
     const int g = bid / tiles, tile = bid % tiles;
     if (g >= P->ng) continue;
     int b0, b1;
-    work_unit_items(un, bin_off, bin_cap, b0, b1);
+    work_unit_items(un, bin_off, bin_cap, P->unit_shift, b0, b1);
     if (b1 <= b0 && un.parts == 1) continue;   // every unit of a split bin reports in
     int s0, s1, k0, k1;
     group_range(g, P, s0, s1, k0, k1);         // one slab per group (max_sg = 1)
@@ -990,8 +762,8 @@ hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
         hipLaunchKernelGGL(k_scan_apply, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, NT,
                            c->bin_off, c->bin_cursor, c->bin_order, c->bin_aux, c->tile_bits, c->row_bits,
                            c->plan);
-        hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->bin_count, c->bin_order, c->bin_aux,
-                           c->units, c->scratch_i);
+        hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->plan, c->bin_count, c->bin_order,
+                           c->bin_aux, c->units, c->scratch_i);
         if (n_items > 0) {
             hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, c->items, n_items, NT,
                                c->bin_cap, c->bin_cursor, c->bin_list);
@@ -1007,42 +779,24 @@ hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
 hipError_t launch_gridder(toi_ctx* c, const toi_snapshot& s) {
     const toi_params& p = c->p;
     const int M = c->M, NT = c->NT;
-    const double cell = p.cell_deg * kPi / 180.0;
     const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;
     const int n_items = s.n_row * n_chunks;
     const int n_bins = c->NG_max * NT * NT;
     if (n_items == 0) return hipGetLastError();
     StageTimer timer(c, TOI_STAGE_GRID);
-    const GridShape gs = grid_shape(c->tuning, c->kmax);
-    const int blocks = std::min(n_bins, kValuWorkgroups);
-#define TOI_TILE_ARGS                                                                                         \
-    dim3(blocks), dim3(gs.threads), gs.lds_bytes, c->stream, s.uvw, (const float2*)s.vis, s.weight, s.flag,    \
-        s.freq, s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode,       \
-        c->plan, M, NT, cell, c->bin_off, c->bin_list, c->bin_cap, c->bin_order, c->scratch_i, c->grid
-#define TOI_TILE_LAUNCH(KA) hipLaunchKernelGGL((k_grid_tiles<KA>), TOI_TILE_ARGS)
-    if (gs.mfma) {   // a fixed grid of single-wave workgroups takes the non-empty bins in turn
-        const int mblocks = unit_workgroups(n_items, n_bins);
+    const GridShape gs = grid_shape(c->tuning);
+    // a fixed grid of single-wave workgroups takes the work units in turn
+    const int mblocks = unit_workgroups(n_items, n_bins);
 #define TOI_MFMA_ARGS                                                                                      \
     dim3(mblocks), dim3(64), gs.lds_bytes, c->stream, c->recs, p.n_chan, c->plan, M, NT, c->bin_off, c->bin_list, \
         c->bin_cap, c->bin_order, c->scratch_i, c->units, c->split_part, c->grid
-        if (gs.gp > 8)
-            hipLaunchKernelGGL((k_grid_tiles_mfma<32>), TOI_MFMA_ARGS);
-        else
-            hipLaunchKernelGGL((k_grid_tiles_mfma<16>), TOI_MFMA_ARGS);
+    if (gs.gp > 8)
+        hipLaunchKernelGGL((k_grid_tiles_mfma<32>), TOI_MFMA_ARGS);
+    else
+        hipLaunchKernelGGL((k_grid_tiles_mfma<16>), TOI_MFMA_ARGS);
 #undef TOI_MFMA_ARGS
-        hipLaunchKernelGGL(k_split_sum, dim3(kSplitSumWorkgroups), dim3(256), 0, c->stream, c->plan, M, NT, c->units,
-                           c->scratch_i, c->split_part, c->grid);
-    } else if (gs.kacc <= 1) {
-        TOI_TILE_LAUNCH(1);
-    } else if (gs.kacc <= 4) {
-        TOI_TILE_LAUNCH(4);
-    } else if (gs.kacc <= 8) {
-        TOI_TILE_LAUNCH(8);
-    } else {
-        TOI_TILE_LAUNCH(16);
-    }
-#undef TOI_TILE_LAUNCH
-#undef TOI_TILE_ARGS
+    hipLaunchKernelGGL(k_split_sum, dim3(kSplitSumWorkgroups), dim3(256), 0, c->stream, c->plan, M, NT, c->units,
+                       c->scratch_i, c->split_part, c->grid);
     return hipGetLastError();
 }
 

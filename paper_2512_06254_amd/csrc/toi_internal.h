@@ -41,7 +41,8 @@ struct DevPlan {
     int32_t parts;        // groups per slab when K > gp (1 otherwise)
     int32_t gp;           // planes per group (LDS pass of the gridder)
     int32_t max_sg;       // at most this many slabs share a group (1: the gridders and the adjoint rely on it)
-    int32_t pad2_[2];
+    int32_t unit_shift;   // work units of split bins hold at most 2^unit_shift items (from the tuning)
+    int32_t pad2_;
 };
 
 // Binned gridding: grid tiles of kTile x kTile cells, work items of kItemChans
@@ -50,66 +51,47 @@ constexpr int kTile = 8, kTileShift = 3;
 constexpr int kItemChans = 64;
 constexpr int kGroupPlanes = 16;   // largest plane group held in LDS
 constexpr int kScanBlock = 4096;   // bins per workgroup of the bin scan
-// Work units of the matrix-core tile passes: a bin of more than kUnitItems
-// items is split into units of at most kUnitItems items (bins of bucket
-// kUnitShift and above are listed unit by unit); the units of one bin add
-// their partial tiles in a fixed order.  At most kSplitSlots listed units per
-// snapshot (bins past that run whole).
-constexpr int kUnitShift = 6, kUnitItems = 1 << kUnitShift;
+// Work units of the matrix-core tile passes: a bin of at least U = 2^unit_shift
+// items (U from the tuning: 32 .. 256) is split into units of at most U items
+// (bins of bucket unit_shift and above are listed unit by unit); the units of
+// one bin add their partial tiles in a fixed order.  At most kSplitSlots
+// listed units per snapshot (the heaviest buckets first; the rest run whole).
 constexpr int kSplitSlots = 16384;
 // Layout of the bin scan's auxiliary array: per floor(log2(count)) bucket the
 // number of non-empty bins, the launch-order cursor and the work units of its
-// bins (ceil(count / kUnitItems) each), then one total per scan workgroup.
+// bins (ceil(count / 2^unit_shift) each), then one total per scan workgroup.
 constexpr int kAuxBuckets = 0, kAuxCursors = 32, kAuxUnits = 64, kAuxTotals = 96;
 // After the list fill, every bin's items are put in increasing item order:
-// bins of fewer than kUnitItems items by one wavefront, larger ones by a
+// bins of fewer than 2^kSortShift items by one wavefront, larger ones by a
 // workgroup in LDS up to kSortLds items, beyond that in place in HBM.
-constexpr int kSortLds = 16384;
+constexpr int kSortShift = 6, kSortLds = 16384;
 constexpr int kPartFloats = 64 * 32;   // one partial tile: 64 cells x up to 16 complex planes
 
 // Gridder variant chosen by the autotuner (toi_tune / toi_set_tuning):
-// bit 0: matrix-core accumulation (v_mfma; one slab per plane group), else the
-// vector-ALU kernel; bit 1: 1024-thread workgroups for the vector-ALU kernel
-// (else 512); bit 2: 8 planes per pass over a tile (else 16).
-constexpr int kTuneMfma = 1, kTuneWide = 2, kTuneEightPlanes = 4;
-constexpr int kTuneDefault = kTuneMfma;
+// bits 0-1: work-unit size U = 32 << bits items (split bins are gridded by one
+// wavefront per U items; fewer, longer units write fewer partial tiles, more,
+// shorter ones balance the heaviest tiles across more wavefronts);
+// bit 2: the plane schedule, 8 planes per pass over a tile on the FP32 matrix
+// cores (v_mfma_f32_16x16x1f32, one instruction per sample) instead of 16
+// planes per pass on the bf16 matrix cores with split operands.
+constexpr int kTuneUnitMask = 3, kTuneEightPlanes = 4;
+constexpr int kTuneDefault = 1;   // 64-item units, 16 planes per pass
 constexpr size_t kLdsBytes = 160 * 1024;   // per workgroup on gfx950
 
-// Launch shape of the tile gridder for a variant.  The matrix-core kernel
-// runs one wavefront per 8 x 8 tile with LDS for staging only; the vector-ALU
-// kernel holds the plane group (gp planes of kTile x kTile complex cells) in
-// LDS plus 64 samples x 16 kernel weights per wavefront.  A variant whose LDS
-// would exceed a workgroup's 160 KB runs with 8 planes per pass.
+// Launch shape of the tile gridder for a variant: one wavefront per work unit,
+// LDS for staging (rows 8 x 68, 8 x 64, 2 x 64, gp x 68) and then the
+// write-out buffer [64][2 gp + 1].
 struct GridShape {
-    int gp, threads, kacc, max_sg;
-    bool mfma;
+    int gp, max_sg, unit_shift;
     size_t lds_bytes;
 };
-inline int gridder_kacc(int kmax, int gp) {
-    const int k = kmax < gp ? kmax : gp;
-    return k <= 1 ? 1 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
-}
-inline size_t gridder_lds(int gp, int threads, int kacc, bool mfma) {
-    if (mfma) {   // staging rows (8 x 68, 8 x 64, 2 x 64, gp x 68), then the write-out buffer [64][2 gp + 1]
-        const size_t stage = (size_t)8 * 68 + 8 * 64 + 2 * 64 + (size_t)gp * 68, wout = (size_t)64 * (2 * gp + 1);
-        return (stage > wout ? stage : wout) * sizeof(float);
-    }
-    (void)kacc;
-    return (size_t)gp * kTile * kTile * 2 * sizeof(float) + (size_t)(threads / 64) * 64 * 16 * sizeof(float);
-}
-inline GridShape grid_shape(int tuning, int kmax) {
+inline GridShape grid_shape(int tuning) {
     GridShape g;
-    g.threads = (tuning & kTuneMfma) ? 64 : (tuning & kTuneWide) ? 1024 : 512;
     g.gp = (tuning & kTuneEightPlanes) ? 8 : kGroupPlanes;
-    g.kacc = gridder_kacc(kmax, g.gp);
-    g.mfma = (tuning & kTuneMfma) != 0;
-    if (gridder_lds(g.gp, g.threads, g.kacc, g.mfma) > kLdsBytes) {
-        g.gp = 8;
-        g.kacc = gridder_kacc(kmax, g.gp);
-    }
-    if (!g.mfma && g.threads == 64) g.threads = (tuning & kTuneWide) ? 1024 : 512;
-    g.max_sg = 1;   // one slab per plane group (the adjoint gather relies on it)
-    g.lds_bytes = gridder_lds(g.gp, g.threads, g.kacc, g.mfma);
+    g.max_sg = 1;   // one slab per plane group (the gridder and the adjoint gather rely on it)
+    g.unit_shift = 5 + (tuning & kTuneUnitMask);
+    const size_t stage = (size_t)8 * 68 + 8 * 64 + 2 * 64 + (size_t)g.gp * 68, wout = (size_t)64 * (2 * g.gp + 1);
+    g.lds_bytes = (stage > wout ? stage : wout) * sizeof(float);
     return g;
 }
 
@@ -172,7 +154,6 @@ struct toi_ctx {
     int N, M, T;          // image side, grid side, tLISI tiles per axis
     int P_cap;            // plane capacity
     int forced_K;         // 0 when chosen on the device
-    int kmax;             // accumulator width of the gridder (>= K)
     int tuning;           // gridder variant (kTune* bits)
     std::string err;
 

@@ -94,7 +94,8 @@ __device__ inline void positive_major(double e[3]) {
 }
 
 __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, const RowStat* __restrict__ rows,
-                                               int n_row, int mode, int gp, int max_sg, DevPlan* __restrict__ plan) {
+                                               int n_row, int mode, int gp, int max_sg, int unit_shift,
+                                               DevPlan* __restrict__ plan) {
     __shared__ double red[16][4];
     __shared__ double V_s[9];
     __shared__ uint32_t status_s;
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, c
         P.parts = 1;
         P.gp = gp;
         P.max_sg = max_sg;
+        P.unit_shift = unit_shift;
         P.status = st;
         *plan = P;
         for (int i = 0; i < 9; ++i) V_s[i] = P.V[i];
@@ -321,8 +323,9 @@ hipError_t launch_prep(toi_ctx* c, const toi_snapshot& s) {
     if (s.n_row > 0)
         hipLaunchKernelGGL(k_row_stats, dim3(s.n_row), dim3(256), 0, c->stream, s.weight, s.flag, s.freq,
                            p.n_chan, p.n_corr, p.corr_mask, c->rows);
-    const GridShape gs = grid_shape(c->tuning, c->kmax);
+    const GridShape gs = grid_shape(c->tuning);
     hipLaunchKernelGGL(k_basis, dim3(1), dim3(256), 0, c->stream, s.uvw, c->rows, s.n_row, p.mode, gs.gp, gs.max_sg,
+                       gs.unit_shift,
                        c->plan);
     if (p.mode == 3) {
         const double cell = p.cell_deg * kPi / 180.0;

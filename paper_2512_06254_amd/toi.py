@@ -75,6 +75,7 @@ _SIGS = {
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_uint32)]),
+    "toi_bin_info": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 4),
     "toi_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "toi_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int32)]),
@@ -321,6 +322,14 @@ class Imager:
 
     def set_tuning(self, variant: int):
         _check(lib().toi_set_tuning(self.ctx, variant), self.ctx)
+
+    def bin_info(self) -> dict:
+        """Synchronise; the last gridded snapshot's bin-list entries, occupied
+        (plane group, tile) pairs, occupied (plane group, tile row) pairs and work units."""
+        v = [ctypes.c_int64() for _ in range(4)]
+        self._sync_stream()
+        _check(lib().toi_bin_info(self.ctx, *[ctypes.byref(x) for x in v]), self.ctx)
+        return dict(zip(("entries", "tiles", "tile_rows", "units"), (x.value for x in v)))
 
     def plan_info(self) -> dict:
         V = (ctypes.c_double * 9)()

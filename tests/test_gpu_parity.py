@@ -136,8 +136,9 @@ def test_every_gridder_variant_matches_oracle(ns, k):
 
 
 def test_dense_bins_split_into_work_units():
-    # bins of up to ~190 items: the matrix-core gridder splits them into
-    # units of 64 items whose partial tiles are added in a fixed order
+    # bins of up to ~190 items: the gridder splits them into units of 32, 64,
+    # 128 (or 256: whole) items, per tuning, whose partial tiles are added in
+    # a fixed order; every variant, then the default again (counters reset)
     from paper_2512_06254_amd import toi as T
     wl = S.scaled(S.WORKLOADS["tiny"], **DENSE)
     assert items_per_bin(wl).max() > 2 * 64
@@ -145,13 +146,15 @@ def test_dense_bins_split_into_work_units():
     ref = O.image_snapshot(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=16)
     im = T.Imager(wl.n_pix, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=1, cheb_k=16)
     d = T.to_device(snap)
-    for v in (1, 0, 1):   # matrix cores, vector ALU (whole bins), matrix cores again (unit counters reset)
+    for v in list(range(T.TUNE_VARIANTS)) + [1]:
         im.set_tuning(v)
         im.grid(d)
         img, tp = im.image(tplane=True)
         e = max_rel_err(tp.cpu().numpy(), ref.tplane)
-        print(f"[dense bins, variant {v}] t-plane err {e:.3e}", flush=True)
+        units = im.bin_info()["units"]
+        print(f"[dense bins, variant {v}] t-plane err {e:.3e}, {units} work units", flush=True)
         assert e <= IMAGE_TOL
+        assert (units > 0) == ((32 << (v & 3)) <= 185)
     im.close()
 
 
