@@ -34,13 +34,16 @@ def log(*a):
 
 
 def make_pool(wl, n_pool, device):
-    """n_pool distinct snapshots of the workload, generated on the device."""
-    import numpy as np
+    """n_pool distinct snapshots of the workload: visibilities predicted on the device,
+    thermal noise and flags from the seeded host generator of synth_inputs (the same
+    per-snapshot streams as ``synth_inputs.make_snapshot``), so that the oracle can
+    regenerate any snapshot the benchmark images from its index alone."""
     import torch
 
     import synth_inputs as S
     enu, sky = S.antenna_enu(wl), S.make_sky(wl)
-    freq = torch.from_numpy(S.channel_freqs(wl)).to(device)
+    freq_h = S.channel_freqs(wl)
+    freq = torch.from_numpy(freq_h).to(device)
     a1, a2 = S.baseline_pairs(wl.n_ant)
     ant1, ant2 = torch.from_numpy(a1).to(device), torch.from_numpy(a2).to(device)
     g = S.gains(wl)
@@ -49,15 +52,11 @@ def make_pool(wl, n_pool, device):
     for t in range(n_pool):
         uvw = S.snapshot_uvw(wl, t, enu)
         l, m, s = S.sources_at(sky, t)
-        vis = S.predict(uvw, S.channel_freqs(wl), l, m, s, wl.n_corr, device=device, chunk_rows=32)
-        gen = torch.Generator(device=device).manual_seed(1000003 * wl.seed + t)
-        nz = torch.randn(vis.shape + (2,), generator=gen, device=device, dtype=torch.float32) * wl.noise_sigma
-        vis += torch.view_as_complex(nz)
-        flag = None
-        if wl.flag_frac_max > 0:
-            frac = float(np.random.default_rng([wl.seed, 3, t]).uniform(0, wl.flag_frac_max))
-            f2 = (torch.rand((wl.n_row, wl.n_chan), generator=gen, device=device) < frac).to(torch.uint8)
-            flag = f2[:, :, None].expand(-1, -1, wl.n_corr).contiguous()
+        vis = S.predict(uvw, freq_h, l, m, s, wl.n_corr, device=device, chunk_rows=32)
+        if wl.noise_sigma > 0:
+            vis += torch.from_numpy(S.noise(wl, t, tuple(vis.shape))).to(device)
+        f = S.flags(wl, t)
+        flag = None if f is None else torch.from_numpy(f).to(device)
         pool.append(dict(uvw=torch.from_numpy(uvw).to(device), vis=vis.contiguous(), flag=flag, weight=None,
                          freq=freq, ant1=ant1, ant2=ant2, gains=gains))
     torch.cuda.synchronize()
@@ -66,6 +65,7 @@ def make_pool(wl, n_pool, device):
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (dense)
 FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X FP32 matrix cores (dense)
+BF16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X bf16 matrix cores (dense)
 
 
 def grid_flops(wl, P):
@@ -74,24 +74,52 @@ def grid_flops(wl, P):
     return wl.n_vis * 64 * P * 4
 
 
-def stage_bytes(wl, P, with_flags):
-    """Algorithmic HBM bytes per launch of each stage (each array read or written once)."""
-    N, M = wl.n_pix, 2 * wl.n_pix
+def planes_per_group(K, gp=16):
+    """Planes gridded and transformed together (one plane group): a slab's orders,
+    split into ceil(K / gp) groups when K > gp."""
+    parts = -(-K // gp)
+    return -(-K // parts)
+
+
+def stage_bytes(wl, K, with_flags, occ):
+    """HBM bytes per launch of each stage, counting each array a stage must touch once and,
+    for the grid planes and the row-pass output, only what holds samples: ``occ`` is
+    ``Imager.bin_info()`` of the snapshot (occupied (plane group, tile) pairs, each 8 x 8
+    cells of every plane of its group; occupied tile rows, each 8 grid rows of N kept bins
+    per plane of its group)."""
+    N = wl.n_pix
+    ppg = planes_per_group(K)
     vis = wl.n_row * wl.n_chan * wl.n_corr * 8
     flags = wl.n_row * wl.n_chan * wl.n_corr if with_flags else 0
-    grid = P * M * M * 8
-    h = P * N * M * 8
-    img = N * N * 4
     recs = wl.n_row * wl.n_chan * 32            # one 32-byte gridding record per sample
+    tiles = occ["tiles"] * 64 * 8 * ppg
+    rows = occ["tile_rows"] * 8 * N * 8 * ppg
+    img = N * N * 4
     return {
         "prep": flags + wl.n_chan * 8 + wl.n_row * 24,
         "bin": vis + flags + recs,
-        "grid": recs + grid,
-        "fft_rows": grid + h,
-        "fft_cols": h + img,
+        "grid": recs + tiles,
+        "fft_rows": tiles + rows,
+        "fft_cols": rows + img,
         "reproject": 2 * img,
         "tlisi": 3 * img,
     }
+
+
+def method_bytes(wl, P, with_flags, adjoint=False):
+    """Algorithmic HBM bytes of one snapshot under the method's own decomposition, with
+    gridding fused into the row pass and the combination into the column pass: the input
+    (visibilities, flags) or, for the adjoint, the gradient written, once; each plane's
+    M x N row-pass intermediate written and read once; about six N x N images (t-plane
+    written, re-projection read and written, the three tLISI reads) or four for the
+    adjoint (image gradient read, t-plane gradient written and read, ...)."""
+    N, M = wl.n_pix, 2 * wl.n_pix
+    data = wl.n_row * wl.n_chan * wl.n_corr * 8 + (wl.n_row * wl.n_chan * wl.n_corr if with_flags else 0)
+    return data + P * 2 * M * N * 8 + (4 if adjoint else 6) * N * N * 4
+
+
+def hbm_frac(nbytes, ms):
+    return round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
 
 
 GRIDDER_SOURCES = ("toi_grid.hip", "toi_grid.h", "toi_device.h")
@@ -106,56 +134,119 @@ def sources_digest(names=GRIDDER_SOURCES):
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel="k_grid_tiles", sources=GRIDDER_SOURCES, workload="meerkat"):
-    """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (profiles/), or None
-    when the kernel's sources have changed since the counters were taken."""
+ALL_SOURCES = tuple(sorted(n for n in os.listdir(os.path.join(ROOT, "paper_2512_06254_amd", "csrc"))
+                           if n.endswith((".hip", ".h", ".cpp"))))
+
+
+def recorded_traffic(key, sources=GRIDDER_SOURCES, workload="meerkat"):
+    """HBM bytes measured by rocprofv3 FETCH_SIZE/WRITE_SIZE (profiles/): the line
+    ``traffic_bytes <key>``, or None when the sources it depends on have changed since the
+    counters were taken (the digest line ``source_sha256 <names>`` no longer matches)."""
     path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     rec = {}
     for line in open(path):
         if line.startswith(("traffic_bytes ", "source_sha256 ")):
-            key, val = line.split(":", 1)
-            rec[key.strip()] = val.strip()
-    key = "source_sha256 " + "+".join(sources)
-    if rec.get(key) != sources_digest(sources) or f"traffic_bytes {kernel}" not in rec:
+            k, val = line.split(":", 1)
+            rec[k.strip()] = val.strip()
+    names = "all" if sources == ALL_SOURCES else "+".join(sources)
+    if rec.get("source_sha256 " + names) != sources_digest(sources) or f"traffic_bytes {key}" not in rec:
         return None
-    return int(rec[f"traffic_bytes {kernel}"])
+    return int(rec[f"traffic_bytes {key}"])
 
 
-def cpu_baseline(wl, snap_dev, n_slab, K, n_pixels=6):
-    """The FP64 oracle on a bounded sample of one snapshot, extrapolated to ms/snapshot."""
+def cpu_info():
+    """CPU model and the threads the oracle's steps use (numpy element-wise steps and
+    FFTs run on one thread; matrix products on the BLAS pool)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = None
+    try:
+        import threadpoolctl
+        pools = [p for p in threadpoolctl.threadpool_info() if p.get("user_api") == "blas"]
+        blas = max((p["num_threads"] for p in pools), default=None)
+    except Exception:
+        pass
+    return model, os.cpu_count(), blas
+
+
+def cpu_baseline(wl, snap_dev, n_slab, K, n_side=16, grid_rows=8, fft_planes=2, comb_rows=256):
+    """The FP64 oracle timed on bounded samples of one snapshot of the workload, scaled to a
+    whole snapshot (labelled extrapolated):
+      * gridded mode (oracle/gridded.py, the path the GPU computes): ES gridding of the
+        samples of ``grid_rows`` rows, scaled by rows; inverse FFT and grid correction of
+        ``fft_planes`` full planes, scaled by planes; the Chebyshev/slab combination on
+        ``comb_rows`` image rows, scaled by rows; re-projection and tLISI on full images;
+      * the direct sum (eq. 10 via the moments) on an n_side x n_side pixel sub-grid,
+        scaled by pixels.
+    Sample selection, basis and plan run on all samples."""
     import numpy as np
 
     from oracle import fitrig as F
+    from oracle import gridded as G
     from oracle import toi as O
     host = {k: (None if v is None else v.cpu().numpy()) for k, v in snap_dev.items()}
+    N, M, P = wl.n_pix, 2 * wl.n_pix, n_slab * K
+    wall0 = time.perf_counter()
     t0 = time.perf_counter()
     smp = O.select_samples(host)
     bas = O.snapshot_basis(smp.b)
     r = O.rotate(bas.V, smp.b)
-    plan = O.make_plan(r[:, 2], bas.V, wl.n_pix, wl.cell_deg, n_slab=n_slab, K=K)
+    plan = O.make_plan(r[:, 2], bas.V, N, wl.cell_deg, n_slab=n_slab, K=K)
     t_fixed = time.perf_counter() - t0
+    # gridded mode
+    p, sq = O.slab_of(r[:, 2], plan)
+    T_ = O.cheb_T(plan.K, sq)
+    X, Y = G.grid_coords(r[:, 0], r[:, 1], M, wl.cell_deg)
+    sel = smp.row < grid_rows
+    t0 = time.perf_counter()
+    grid = G.grid_values((T_[sel] * smp.x[sel, None]).T, X[sel], Y[sel], M)
+    t_grid = (time.perf_counter() - t0) * wl.n_row / grid_rows
+    t0 = time.perf_counter()
+    G.grid_to_image(grid[:fft_planes], N)
+    t_fft = (time.perf_counter() - t0) * P / fft_planes
+    del grid
+    rows = np.linspace(0, N - 1, comb_rows).astype(np.int64)
+    mom = np.zeros((plan.n_slab, plan.K, rows.size, N), dtype=np.complex128)
+    t0 = time.perf_counter()
+    tp_rows = O.image_3d_cheb(r, smp.x, smp.W, bas.omega, bas.V, plan, N, wl.cell_deg, M=mom, j2=rows)
+    t_comb = (time.perf_counter() - t0) * N / comb_rows
+    tp = np.zeros((N, N))
+    tp[rows] = tp_rows
+    t0 = time.perf_counter()
+    img, _ = O.reproject(tp, bas.V, N, wl.cell_deg)
+    F.tlisi(img, img + 1.0, img, tile=32)
+    t_post = time.perf_counter() - t0
+    gridded_s = t_fixed + t_grid + t_fft + t_comb + t_post
+    # direct sum
     rng = np.random.default_rng(0)
-    j1 = rng.choice(wl.n_pix, n_pixels, replace=False)
-    j2 = rng.choice(wl.n_pix, 1, replace=False)
-    t1 = time.perf_counter()
-    O.image_3d_cheb(r, smp.x, smp.W, bas.omega, bas.V, plan, wl.n_pix, wl.cell_deg, j1=j1, j2=j2)
-    t_pix = (time.perf_counter() - t1) / n_pixels
-    tp = np.zeros((wl.n_pix, wl.n_pix))
-    t2 = time.perf_counter()
-    O.reproject(tp, bas.V, wl.n_pix, wl.cell_deg)
-    F.tlisi(tp, tp + 1.0, tp, tile=32)
-    t_post = time.perf_counter() - t2
-    total_s = t_fixed + t_pix * wl.n_pix ** 2 + t_post
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    j1 = np.sort(rng.choice(N, n_side, replace=False))
+    j2 = np.sort(rng.choice(N, n_side, replace=False))
+    t0 = time.perf_counter()
+    O.image_3d_cheb(r, smp.x, smp.W, bas.omega, bas.V, plan, N, wl.cell_deg, j1=j1, j2=j2)
+    t_pix = (time.perf_counter() - t0) / (n_side * n_side)
+    direct_s = t_fixed + t_pix * N * N + t_post
+    model, ncpu, blas = cpu_info()
     return {
-        "value": round(total_s * 1e3, 1), "unit": "ms/snapshot", "cores": cores, "kind": "oracle",
-        "sample": (f"FP64 oracle: sample selection, SVD basis and plan on all {smp.n} samples "
-                   f"({t_fixed:.1f} s), the Chebyshev t-plane sum at {n_pixels} random pixels "
-                   f"({t_pix:.2f} s/pixel, extrapolated to {wl.n_pix}^2 pixels), re-projection and tLISI "
-                   f"on full {wl.n_pix}^2 arrays ({t_post:.1f} s); wall time of the sample "
-                   f"{time.perf_counter() - t0:.1f} s"),
+        "value": round(gridded_s * 1e3, 1), "unit": "ms/snapshot", "cores": blas or 1, "kind": "oracle",
+        "extrapolated": True, "cpu_model": model, "host_cpus": ncpu,
+        "threads": f"BLAS products on {blas} threads; numpy element-wise steps, np.add.at and FFTs on 1",
+        "direct_sum_ms_per_snapshot": round(direct_s * 1e3, 1),
+        "sample": (f"FP64 oracle on one {wl.name} snapshot ({smp.n} samples): selection, SVD basis and plan on "
+                   f"all samples {t_fixed:.1f} s; gridded mode (oracle/gridded.py): ES gridding of the "
+                   f"{int(sel.sum())} samples of {grid_rows} rows scaled to {wl.n_row} rows {t_grid:.1f} s, inverse "
+                   f"FFT + correction of {fft_planes} of {P} {M}^2 planes scaled to {P} {t_fft:.1f} s, "
+                   f"Chebyshev/slab combination on {comb_rows} of {N} rows scaled {t_comb:.1f} s, re-projection "
+                   f"and tLISI on full images {t_post:.1f} s -> value; direct sum of eq. 10 at "
+                   f"{n_side}x{n_side} pixels ({t_pix:.3f} s/pixel) scaled to {N}^2 pixels -> "
+                   f"direct_sum_ms_per_snapshot; wall time of the samples {time.perf_counter() - wall0:.1f} s"),
     }
 
 
@@ -206,8 +297,11 @@ def batched_leg(n_batch, reps, device):
     ms_batch = time_events(batched, reps) / n_batch
     kept = [float(1.0 - p["flag"][:, :, 0].float().mean()) for p in pool]
     im.close()
+    alg = method_bytes(wl, n_slab * K, True)
     return {"workload": wl.name, "snapshots_per_launch": n_batch, "launches_timed": reps,
             "ms_per_snapshot_batched": round(ms_batch, 4), "ms_per_snapshot_plain": round(ms_plain, 4),
+            "hbm_roofline_frac_batched": hbm_frac(alg, ms_batch), "hbm_roofline_frac_plain": hbm_frac(alg, ms_plain),
+            "algorithmic_bytes_per_snapshot": alg,
             "first_launch_with_capture_s": round(capture_s, 3), "tuned_variant": variant,
             "kept_sample_fraction": [round(k, 3) for k in kept]}
 
@@ -286,9 +380,52 @@ def many_slab_leg(n_snap, reps, device):
     im.profile(False)
     info = im.plan_info()
     im.close()
+    alg = method_bytes(wl, n_slab * K, False)
     return {"workload": "aa2", "baselines": wl.n_row, "channels": wl.n_chan, "correlations": wl.n_corr,
             "image": f"{N}x{N}", "planes": f"{info['n_slab']} slabs x K={info['K']}", "ms_per_snapshot": round(ms, 4),
+            "hbm_roofline_frac": hbm_frac(alg, ms), "algorithmic_bytes": alg,
             "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]}}
+
+
+def full_leg(n_snap, reps, device):
+    """The full run's snapshot shape: 2016 baselines x 4096 channels x 4 correlations imaged
+    at 4096^2 (8192^2 grid, 16 planes) with the tLISI map of 128 x 128 tiles; ms/snapshot of
+    the plain path, its stages and its fraction of the HBM roofline."""
+    import torch
+
+    import synth_inputs as S
+    from paper_2512_06254_amd import toi as T
+    wl = S.WORKLOADS["full"]
+    n_slab, K = wl.forced_planes
+    pool = make_pool(wl, 2, device)
+    N = wl.n_pix
+    im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K, tile=32)
+    ring = [torch.zeros((N, N), dtype=torch.float32, device=device) for _ in range(3)]
+    tl = torch.zeros((N // 32, N // 32), dtype=torch.float32, device=device)
+    state = {"i": 0}
+
+    def run():
+        for _ in range(n_snap):
+            i = state["i"]
+            im.grid(pool[i % 2])
+            im.image(out=ring[i % 3])
+            if i >= 2:
+                im.tlisi(ring[(i - 2) % 3], ring[(i - 1) % 3], ring[i % 3], out=tl)
+            state["i"] = i + 1
+
+    run()
+    ms = time_events(run, reps) / n_snap
+    im.profile(True)
+    run()
+    prof = im.profile_read()
+    im.profile(False)
+    info = im.plan_info()
+    im.close()
+    alg = method_bytes(wl, n_slab * K, False)
+    return {"workload": wl.name, "baselines": wl.n_row, "channels": wl.n_chan, "correlations": wl.n_corr,
+            "image": f"{N}x{N}", "grid": f"{2 * N}x{2 * N}", "planes": f"{info['n_slab']} slab x K={info['K']}",
+            "status": info["status"], "ms_per_snapshot": round(ms, 4), "hbm_roofline_frac": hbm_frac(alg, ms),
+            "algorithmic_bytes": alg, "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]}}
 
 
 def detect_cube_leg(n_maps, T, reps, device):
@@ -366,8 +503,11 @@ def adjoint_leg(reps, device):
     fwd()
     ms_b = time_events(bwd, reps)
     im.close()
+    P = n_slab * K
+    alg_f, alg_b = method_bytes(wl, P, False), method_bytes(wl, P, False, adjoint=True)
     return {"workload": wl.name, "baselines": wl.n_row, "channels": wl.n_chan, "image": f"{N}x{N}",
             "ms_forward": round(ms_f, 4), "ms_adjoint": round(ms_b, 4),
+            "hbm_roofline_frac_forward": hbm_frac(alg_f, ms_f), "hbm_roofline_frac_adjoint": hbm_frac(alg_b, ms_b),
             "gradients": "vis (complex64, all correlations) and 64 antenna gains"}
 
 
@@ -383,6 +523,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--ingest", type=int, default=8, help="host-resident snapshots per toi_ingest call (0 = skip)")
     ap.add_argument("--many-slab", type=int, default=4, help="AA2-like 272-plane snapshots timed (0 = skip)")
+    ap.add_argument("--full", type=int, default=4, help="4096^2 full-run-shape snapshots per timing (0 = skip)")
     ap.add_argument("--detect-cube", type=int, default=1500, help="maps of the whole-run detection cube (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
@@ -441,16 +582,23 @@ def main():
         step(i)
     prof_all = im.profile_read()
     im.profile(False)
-    sb = stage_bytes(wl, P, wl.flag_frac_max > 0)
+    occ = im.bin_info()
+    sb = stage_bytes(wl, K, wl.flag_frac_max > 0, occ)
     stages = {}
     for name, (tot, n) in prof_all.items():
         if n:
             avg = tot / n
-            stages[name] = {"avg_ms": round(avg, 4), "launches": n,
-                            "GBps": round(sb.get(name, 0) / (avg * 1e-3) / 1e9, 1) if name in sb else None}
+            stages[name] = {"avg_ms": round(avg, 4), "launches": n, "bytes": sb.get(name),
+                            "GBps": round(sb[name] / (avg * 1e-3) / 1e9, 1) if name in sb else None}
+            measured = recorded_traffic(f"stage {name}", ALL_SOURCES) if wl.name == "meerkat" else None
+            stages[name]["measured_bytes"] = measured
+            stages[name]["measured_GBps"] = None if measured is None else round(measured / (avg * 1e-3) / 1e9, 1)
+    for name, st in stages.items():   # every byte count is one the stage really moves: never above peak
+        for key in ("GBps", "measured_GBps"):
+            if st.get(key) is not None and st[key] > HBM_PEAK_GBPS:
+                log(f"[bench] WARNING stage {name} {key} {st[key]} above the HBM peak")
     if "grid" in stages:
         stages["grid"]["TFLOPs"] = round(grid_flops(wl, P) / (stages["grid"]["avg_ms"] * 1e-3) / 1e12, 2)
-        stages["grid"]["GBps"] = None
     dom = max((s for s in stages if s in sb), key=lambda s: stages[s]["avg_ms"] * stages[s]["launches"])
     log(f"[bench] warmup done ({args.warmup} + {n_stage} stage-timed steps; dominant stage {dom}); "
         f"timing {args.steps} steps")
@@ -472,22 +620,22 @@ def main():
     log(f"[bench] {ms:.3f} ms/snapshot; {dom} {dom_ms:.3f} ms per launch; plan n_slab={info['n_slab']} "
         f"K={info['K']} status={info['status']}")
 
-    if dom == "grid":   # the gridder is bound by FP32 arithmetic (matrix cores or vector ALU), not by HBM
+    bf16 = not (variant & 4)
+    if dom == "grid":
+        # 16 planes per pass: products on the bf16 matrix cores beside the vector
+        # ALU, the kernel bound by vector-ALU issue (staging, operand splits):
+        # "alu" against the FP32 vector peak.  8 planes per pass: FP32 matrix
+        # instructions, which share the vector ALU on gfx950.
         ach = grid_flops(wl, P) / (dom_ms * 1e-3) / 1e12
-        mfma = bool(variant & 1) and K >= 8
-        kname = "k_grid_tiles_mfma" if mfma else "k_grid_tiles"
-        # 16 planes per pass: the products run on the bf16 matrix cores beside the
-        # vector ALU, and the kernel is bound by vector-ALU issue (staging, operand
-        # splits): "alu" against the FP32 vector peak.  8 planes per pass: FP32
-        # matrix instructions, which share the vector ALU on gfx950.
-        bf16 = mfma and not (variant & 4)
-        bound = "alu" if (bf16 or not mfma) else "mfma"
-        peak = FP32_MFMA_PEAK_TFLOPS if bound == "mfma" else FP32_VECTOR_PEAK_TFLOPS
+        kname = "k_grid_tiles_mfma"
+        bound = "alu" if bf16 else "mfma"
+        peak = FP32_VECTOR_PEAK_TFLOPS if bf16 else FP32_MFMA_PEAK_TFLOPS
         roofline = {"bound": bound, "achieved": round(ach, 2), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(ach / peak, 4),
                     "traffic": recorded_traffic(kname) if wl.name == "meerkat" else None,
                     "kernel": kname, "algorithmic_flops": grid_flops(wl, P),
                     "avg_launch_ms": round(dom_ms, 4), "launches_timed": n,
+                    "frac_of_bf16_matrix_peak": round(ach / BF16_MFMA_PEAK_TFLOPS, 4) if bf16 else None,
                     "note": ("products on the bf16 matrix cores (3-term splits, FP32 accumulation) beside the "
                              "vector ALU; bound by vector-ALU issue" if bf16 else None)}
     else:
@@ -495,7 +643,18 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": dom,
                     "algorithmic_bytes": sb[dom], "avg_launch_ms": round(dom_ms, 4), "launches_timed": n}
-    step_bytes = sum(sb.values())
+    alg = method_bytes(wl, P, wl.flag_frac_max > 0)
+    impl = recorded_traffic("step", ALL_SOURCES) if wl.name == "meerkat" else None
+    roofline_step = {"bound": "hbm", "algorithmic_bytes": alg, "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": hbm_frac(alg, ms),
+                     "implementation_bytes": impl,
+                     "implementation_GBps": None if impl is None else round(impl / (ms * 1e-3) / 1e9, 1),
+                     "note": "algorithmic bytes of the method's fused decomposition (input once, each plane's "
+                             "M x N row-pass intermediate written and read once, ~6 images) over the whole "
+                             "step; implementation bytes: rocprofv3 FETCH_SIZE + WRITE_SIZE of every kernel "
+                             "of one step, null when any kernel source changed since they were taken"}
+    fp32 = [tune_ms[v] for v in range(len(tune_ms)) if v & 4]
+    b16 = [tune_ms[v] for v in range(len(tune_ms)) if not v & 4]
     out = {
         "metric": METRIC, "value": round(ms, 4), "unit": "ms/snapshot", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": False, "scaling": "weak",
@@ -504,13 +663,21 @@ def main():
                    "image": f"{N}x{N}", "cell_arcsec": wl.cell_arcsec, "planes": f"{n_slab} slab x K={K}",
                    "grid": f"{2 * N}x{2 * N} ES support 8", "tlisi_tile": 32, "path": "plain per-snapshot",
                    "pool": args.pool,
-                   "arithmetic": "FP32 values and sums; gridder products from 3-term bf16 splits, FP32 accumulation"},
+                   "arithmetic": ("FP32 values and sums; gridder products from 3-term bf16 splits, FP32 "
+                                  "accumulation" if bf16 else "FP32 values, products and sums")},
         "roofline": roofline,
+        "roofline_step": roofline_step,
         "stages": stages,
-        "stages_note": f"every stage timed on {n_stage} steps before the timed region",
-        "step_effective_GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+        "stages_note": (f"every stage timed on {n_stage} steps before the timed region; bytes: what the stage "
+                        f"must move, grid planes and row-pass output counted only where they hold samples "
+                        f"({occ['tiles']} occupied (plane group, tile) pairs, {occ['tile_rows']} tile rows, "
+                        f"{occ['entries']} bin entries, {occ['units']} split units); measured: rocprofv3 "
+                        f"FETCH_SIZE + WRITE_SIZE (profiles/), null when stale"),
         "tuning": {"variant": variant, "grid_plus_image_ms_per_variant": [round(m, 3) for m in tune_ms],
-                   "variants": "bit0 matrix cores (v_mfma), bit1 1024-thread groups, bit2 8 planes per LDS pass"},
+                   "variants": "bits 0-1 work-unit size 32 << bits items; bit 2 8 planes per pass on the FP32 "
+                               "matrix cores instead of 16 on the bf16 matrix cores (split operands)",
+                   "best_ms_bf16x3_16_planes": round(min(b16), 3),
+                   "best_ms_fp32_8_planes": round(min(fp32), 3)},
     }
     im.close()
     if args.batch > 0:
@@ -522,6 +689,9 @@ def main():
     if args.many_slab > 0:
         log(f"[bench] many-slab leg (AA2-like, 272 planes): {args.many_slab} snapshots")
         out["many_slab"] = many_slab_leg(args.many_slab, 2, device)
+    if args.full > 0:
+        log(f"[bench] full-run shape leg (4096^2 images): {args.full} snapshots per timing")
+        out["full"] = full_leg(args.full, 2, device)
     if args.detect_cube > 0:
         log(f"[bench] whole-run detection leg: {args.detect_cube} tLISI maps of 128 x 128 tiles")
         out["detect_cube"] = detect_cube_leg(args.detect_cube, 128, 3, device)
