@@ -219,7 +219,11 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
     c->NT = c->M / kTile;
     c->NG_max = std::max(1, c->P_cap);   // every group holds at least one plane
     c->n_items_max = std::max(1, p.n_row_max * ((p.n_chan + kItemChans - 1) / kItemChans));
-    c->bin_cap = p.bin_cap > 0 ? p.bin_cap : c->n_items_max * 32 + 4096;
+    // default: 128 (tile, plane group) entries per work item on average; an
+    // item's box of tiles grows with the track length its 64 channels span
+    // (about 5 entries per item at 4096 channels over 856-1712 MHz, some 60-100
+    // at 512 channels over the same band on a 8192^2 grid)
+    c->bin_cap = p.bin_cap > 0 ? p.bin_cap : c->n_items_max * 128 + 65536;
     size_t fb[14];
     front_bytes(c, fb);
     struct Alloc { void** ptr; size_t bytes; };

@@ -110,7 +110,7 @@ __device__ inline double miller_norm(double alpha, int L) {
 
 // 2. column pass of the adjoint
 template <int M, int E>
-__global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__ gtp, float2* __restrict__ gh,
+__global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_cols(const float* __restrict__ gtp, float2* __restrict__ gh,
                                                        const float2* __restrict__ tw, const float* __restrict__ corr,
                                                        const DevPlan* __restrict__ plan, float cell_rad, int mode,
                                                        const uint32_t* __restrict__ row_bits) {
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(M / E, 2) void k_adj_cols(const float* __restrict__
 // 3. row pass of the adjoint (rows of tile rows that hold samples; only the
 // tiles that hold samples are written, the only ones the gather reads)
 template <int M, int E, int B>
-__global__ __launch_bounds__(M / E, 2) void k_adj_rows(const float2* __restrict__ gh, float2* __restrict__ gg,
+__global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_rows(const float2* __restrict__ gh, float2* __restrict__ gg,
                                                        const float2* __restrict__ tw,
                                                        const DevPlan* __restrict__ plan, int nbands,
                                                        const uint32_t* __restrict__ tile_bits,
@@ -578,8 +578,8 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
         case 512: launch_adj_ffts<512, 16, 16>(c); break;
         case 1024: launch_adj_ffts<1024, 16, 16>(c); break;
         case 2048: launch_adj_ffts<2048, 16, 16>(c); break;
-        case 4096: launch_adj_ffts<4096, 16, 16>(c); break;
-        case 8192: launch_adj_ffts<8192, 32, 32>(c); break;
+        case 4096: launch_adj_ffts<4096, 16, 8>(c); break;
+        case 8192: launch_adj_ffts<8192, 16, 8>(c); break;
         default: return hipErrorInvalidValue;
     }
     const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;

@@ -32,8 +32,11 @@ __device__ inline size_t hbuf_index(int plane, int j1, int y) {
     return (((size_t)plane * (N / kHbufGroup) + j1 / kHbufGroup) * M + y) * kHbufGroup + j1 % kHbufGroup;
 }
 
+// Launch bounds: two workgroups per CU while a workgroup has at most 256
+// (rows) or 512 (columns) threads; larger ones keep the full register budget
+// of one (their LDS allows only one per CU anyway).
 template <int M, int E, int B>
-__global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict__ grid, float2* __restrict__ hbuf,
+__global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_fft_rows(const float2* __restrict__ grid, float2* __restrict__ hbuf,
                                                     const float2* __restrict__ tw,
                                                     const DevPlan* __restrict__ plan, int nbands,
                                                     const uint32_t* __restrict__ tile_bits,
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(M / E, 2) void k_fft_rows(const float2* __restrict_
 // J_0 + 2 sum_m J_{2m} = 1 applied once at the end; small |alpha| uses the
 // power series.
 template <int M, int E>
-__global__ __launch_bounds__(M / E, 2) void k_fft_cols(const float2* __restrict__ hbuf, float* __restrict__ tplane_t,
+__global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(const float2* __restrict__ hbuf, float* __restrict__ tplane_t,
                                                     const float2* __restrict__ tw, const float* __restrict__ corr,
                                                     const DevPlan* __restrict__ plan, float cell_rad, int mode,
                                                     const uint32_t* __restrict__ row_bits, int ng_cap) {
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src
 
 template <int M, int E, int EC>   // row-pass and column-pass radices
 static hipError_t launch_fft_passes(toi_ctx* c) {
-    constexpr int B = (M >= 8192) ? 2 : 4;
+    constexpr int B = 4;
     const int nbands = M / B;
     const int P = c->P_cap;
     {
@@ -281,7 +284,7 @@ hipError_t launch_image(toi_ctx* c, float* image_out, float* tplane_out) {
         case 1024: e = launch_fft_passes<1024, 16, 16>(c); break;
         case 2048: e = launch_fft_passes<2048, 16, 16>(c); break;
         case 4096: e = launch_fft_passes<4096, 16, 8>(c); break;
-        case 8192: e = launch_fft_passes<8192, 32, 32>(c); break;
+        case 8192: e = launch_fft_passes<8192, 16, 8>(c); break;
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;

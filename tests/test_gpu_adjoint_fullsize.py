@@ -105,3 +105,35 @@ def test_adjoint_full_shape_sampled_parity_dot_product_and_gains():
         assert abs(fd - an) <= 1e-2 * abs(an)
     dev["gains"] = g0
     im.close()
+
+
+def test_adjoint_dot_product_identity_at_the_4096_image():
+    """The 4096^2 image (8192^2 grid) of the full run's shape, 256 channels over the
+    same band: the dot-product identity <G x, y> = Re <x, G^H y> through the C ABI
+    for random visibilities x and a random image gradient y (a property that holds
+    at any size; the adjoint passes run at their 8192-point instantiation)."""
+    import torch
+    from paper_2512_06254_amd import toi as T
+    base = S.WORKLOADS["full"]
+    wl = S.scaled(base, n_chan=256, dfreq_hz=base.n_chan * base.dfreq_hz / 256, with_gains=True)
+    enu = S.antenna_enu(wl)
+    a1, a2 = S.baseline_pairs(wl.n_ant)
+    rng = np.random.default_rng(31)
+    shape = (wl.n_row, wl.n_chan, wl.n_corr)
+    host = dict(uvw=S.snapshot_uvw(wl, 0, enu),
+                vis=(rng.normal(size=shape) + 1j * rng.normal(size=shape)).astype(np.complex64),
+                flag=None, weight=None, freq=S.channel_freqs(wl), ant1=a1, ant2=a2, gains=S.gains(wl))
+    dev = T.to_device(host)
+    im = T.Imager(wl.n_pix, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=1, cheb_k=16, n_ant=wl.n_ant)
+    im.grid(dev)
+    img = im.image()
+    y = torch.from_numpy(rng.normal(size=(wl.n_pix, wl.n_pix)).astype(np.float32)).cuda()
+    gv, gg = im.degrid(y, dev, want_vis=True, want_gains=True)
+    assert im.plan_info()["status"] == 0
+    lhs = float((img.double() * y.double()).sum())
+    rhs = float((torch.conj(gv.to(torch.complex128)) * dev["vis"].to(torch.complex128)).real.sum())
+    print(f"[adjoint 4096^2] <Gx,y> = {lhs:.9e}  Re<x,G^H y> = {rhs:.9e}  rel {abs(lhs - rhs) / abs(lhs):.2e}",
+          flush=True)
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+    assert torch.isfinite(gg).all()
+    im.close()

@@ -39,12 +39,12 @@ def _run(wl, snaps, n_slab, K, tile=16):
 @pytest.mark.parametrize("case", ["dense_split_bins", "three_slabs"])
 def test_repeat_runs_are_bitwise_identical(case):
     if case == "dense_split_bins":
-        wl = S.scaled(S.WORKLOADS["tiny"], n_steady=4, **DENSE)
+        wl = S.scaled(S.WORKLOADS["tiny"], n_steady=4, n_snap=4, **DENSE)
         n_slab, K = 1, 16
         assert items_per_bin(wl).max() > 2 * 64          # bins sorted by a workgroup, split into units
     else:
         wl = S.scaled(S.WORKLOADS["tiny"], n_ant=12, n_chan=96, n_pix=64, cell_arcsec=60.0, sigma_h_m=60.0,
-                      n_steady=4)
+                      n_steady=4, n_snap=4)
         n_slab, K = 3, 8
     snaps = [S.make_snapshot(wl, t) for t in range(4)]
     a = _run(wl, snaps, n_slab, K)
