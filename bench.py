@@ -65,7 +65,7 @@ def make_pool(wl, n_pool, device):
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (dense)
 FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X FP32 matrix cores (dense)
-BF16_MFMA_PEAK_TFLOPS = 2500.0    # MI355X bf16 matrix cores (dense)
+F16_MFMA_PEAK_TFLOPS = 2500.0     # MI355X fp16 / bf16 matrix cores (dense)
 
 
 def grid_flops(wl, P):
@@ -620,24 +620,25 @@ def main():
     log(f"[bench] {ms:.3f} ms/snapshot; {dom} {dom_ms:.3f} ms per launch; plan n_slab={info['n_slab']} "
         f"K={info['K']} status={info['status']}")
 
-    bf16 = not (variant & 4)
+    split16 = not (variant & 4)      # 16 planes per pass: fp16 matrix cores with split operands
     if dom == "grid":
-        # 16 planes per pass: products on the bf16 matrix cores beside the vector
+        # 16 planes per pass: products on the fp16 matrix cores beside the vector
         # ALU, the kernel bound by vector-ALU issue (staging, operand splits):
         # "alu" against the FP32 vector peak.  8 planes per pass: FP32 matrix
         # instructions, which share the vector ALU on gfx950.
         ach = grid_flops(wl, P) / (dom_ms * 1e-3) / 1e12
         kname = "k_grid_tiles_mfma"
-        bound = "alu" if bf16 else "mfma"
-        peak = FP32_VECTOR_PEAK_TFLOPS if bf16 else FP32_MFMA_PEAK_TFLOPS
+        bound = "alu" if split16 else "mfma"
+        peak = FP32_VECTOR_PEAK_TFLOPS if split16 else FP32_MFMA_PEAK_TFLOPS
         roofline = {"bound": bound, "achieved": round(ach, 2), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(ach / peak, 4),
                     "traffic": recorded_traffic(kname) if wl.name == "meerkat" else None,
                     "kernel": kname, "algorithmic_flops": grid_flops(wl, P),
                     "avg_launch_ms": round(dom_ms, 4), "launches_timed": n,
-                    "frac_of_bf16_matrix_peak": round(ach / BF16_MFMA_PEAK_TFLOPS, 4) if bf16 else None,
-                    "note": ("products on the bf16 matrix cores (3-term splits, FP32 accumulation) beside the "
-                             "vector ALU; bound by vector-ALU issue" if bf16 else None)}
+                    "frac_of_f16_matrix_peak": round(ach / F16_MFMA_PEAK_TFLOPS, 4) if split16 else None,
+                    "note": ("products on the fp16 matrix cores (operands split as hi + lo in fp16, 3 terms, "
+                             "FP32 accumulation) beside the vector ALU; bound by vector-ALU issue"
+                             if split16 else None)}
     else:
         ach = sb[dom] / (dom_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -663,8 +664,9 @@ def main():
                    "image": f"{N}x{N}", "cell_arcsec": wl.cell_arcsec, "planes": f"{n_slab} slab x K={K}",
                    "grid": f"{2 * N}x{2 * N} ES support 8", "tlisi_tile": 32, "path": "plain per-snapshot",
                    "pool": args.pool,
-                   "arithmetic": ("FP32 values and sums; gridder products from 3-term bf16 splits, FP32 "
-                                  "accumulation" if bf16 else "FP32 values, products and sums")},
+                   "arithmetic": ("FP32 values and sums; gridder products from FP32 operands split as hi + lo "
+                                  "in fp16 (about 22 significant bits), 3 terms, FP32 accumulation"
+                                  if split16 else "FP32 values, products and sums")},
         "roofline": roofline,
         "roofline_step": roofline_step,
         "stages": stages,
@@ -675,8 +677,8 @@ def main():
                         f"FETCH_SIZE + WRITE_SIZE (profiles/), null when stale"),
         "tuning": {"variant": variant, "grid_plus_image_ms_per_variant": [round(m, 3) for m in tune_ms],
                    "variants": "bits 0-1 work-unit size 32 << bits items; bit 2 8 planes per pass on the FP32 "
-                               "matrix cores instead of 16 on the bf16 matrix cores (split operands)",
-                   "best_ms_bf16x3_16_planes": round(min(b16), 3),
+                               "matrix cores instead of 16 on the fp16 matrix cores (split operands)",
+                   "best_ms_f16x3_16_planes": round(min(b16), 3),
                    "best_ms_fp32_8_planes": round(min(fp32), 3)},
     }
     im.close()

@@ -44,6 +44,43 @@ __device__ inline void split_bf16x8(const float* x, bf16x8_t& hi, bf16x8_t& lo) 
     lo = __builtin_bit_cast(bf16x8_t, l);
 }
 
+// Products a_i b_i (i = 0, 1) of FP32 values as fp16 pairs a b = hi + lo:
+// hi = f16(a b) and lo = f16(a b - hi), each from one fused multiply-add in
+// FP32 with the result rounded to fp16 (v_fma_mixlo_f16 / v_fma_mixhi_f16
+// write the low / high half of the packed word; for lo the third operand is
+// the fp16 hi read from its half of the packed word).  The residual a b - hi
+// is exact in the FMA, so hi + lo carries about 22 significant bits of a b
+// (lo keeps 11 of the residual's).  Values must lie in fp16's range
+// (|a b| < 65504).  The two instructions of each word write disjoint halves,
+// so the word is fully defined.
+__device__ inline void split_prod_f16x2(float a0, float b0, float a1, float b1, uint32_t& hi, uint32_t& lo) {
+    uint32_t h, l;
+    asm("v_fma_mixlo_f16 %0, %1, %2, 0\n\t"
+        "v_fma_mixhi_f16 %0, %3, %4, 0"
+        : "=&v"(h)
+        : "v"(a0), "v"(b0), "v"(a1), "v"(b1));
+    asm("v_fma_mixlo_f16 %0, %1, %2, -%5 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %0, %3, %4, -%5 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "=&v"(l)
+        : "v"(a0), "v"(b0), "v"(a1), "v"(b1), "v"(h));
+    hi = h;
+    lo = l;
+}
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+__device__ inline void split_prod_f16x8(const float* a, const float* b, f16x8_t& hi, f16x8_t& lo) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    u4 h, l;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        uint32_t hw, lw;
+        split_prod_f16x2(a[2 * w], b[2 * w], a[2 * w + 1], b[2 * w + 1], hw, lw);
+        h[w] = hw;
+        l[w] = lw;
+    }
+    hi = __builtin_bit_cast(f16x8_t, h);
+    lo = __builtin_bit_cast(f16x8_t, l);
+}
+
 // Sum over a 64-lane wavefront with DPP row shifts and row broadcasts (fixed
 // order); the total is returned to every lane (from lane 63).
 template <int CTRL, int ROWS>

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
                                                const double* __restrict__ freq, const int32_t* __restrict__ ant1,
                                                const int32_t* __restrict__ ant2, const float2* __restrict__ gains,
                                                int n_ant, int n_chan, int n_corr, uint32_t mask, int mode,
-                                               const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
+                                               DevPlan* __restrict__ P, int M, int NT, double cell_rad,
                                                int n_items, ItemBox* __restrict__ items, SampleRec* __restrict__ recs,
                                                int32_t* __restrict__ bin_count) {
     const int lane = threadIdx.x & 63;
@@ -57,6 +57,7 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     const Track tr = row_track(uvw, r, P, M, cell_rad);
     // gridding record of this lane's sample
     bool kept = false;
+    float vabs = 0.f;                  // max(|Re|, |Im|) of g x (the gridder's fp16 operand scale)
     if (c < n_chan) {
         float xr, xi;
         const float w = sample_value(vis, weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask, xr, xi);
@@ -81,6 +82,7 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
             const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
             rec.vr = xr * gr.x - xi * gr.y;
             rec.vi = xr * gr.y + xi * gr.x;
+            vabs = fmaxf(fabsf(rec.vr), fabsf(rec.vi));
         }
         float4* dst = reinterpret_cast<float4*>(recs + (size_t)r * n_chan + c);
         dst[0] = make_float4(__int_as_float(rec.pk), __int_as_float(rec.sp), rec.ox, rec.oy);
@@ -88,6 +90,8 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     }
     // X, Y and r3 are linear in nu along the row: their extremes over the kept
     // channels sit at the extreme kept frequencies
+    vabs = wave_max(vabs);             // non-negative floats order like their bit patterns
+    if (lane == 0 && vabs > 0.f) atomicMax(&P->vmax_bits, __float_as_uint(vabs));
     double nlo = 1e300, nhi = -1e300;
     if (kept) nlo = nhi = freq[c];
     nlo = wave_min(nlo);
@@ -455,11 +459,16 @@ __global__ __launch_bounds__(1024) void k_bin_sort_block(const DevPlan* __restri
 // T_k(s) Re(g x), T_k(s) Im(g x) of the planes of its slab (zero for the
 // group's other planes); the tile is the product A B of the weights A (64
 // cells x samples) and the values B (samples x NCOL).  NCOL = 32 (16
-// planes): v_mfma_f32_32x32x16_bf16 on two 32-row halves, 16 samples per
-// instruction, each operand split as x = hi + lo in bf16 and A B formed as
-// Ah Bh + Ah Bl + Al Bh (products exact, the dropped Al Bl and the splits
-// about 2^-17 relative), accumulated in FP32; the bf16 matrix cores run
-// beside the vector ALU, where FP32 matrix instructions would share it.
+// planes): v_mfma_f32_32x32x16_f16 on two 32-row halves, 16 samples per
+// instruction, each operand an FP32 product split as hi + lo in fp16 by
+// fused multiply-adds that round to fp16 (hi = f16(a b), lo = f16(a b - hi),
+// about 22 significant bits), and A B formed as Ah Bh + Ah Bl + Al Bh
+// (products exact in FP32, the dropped Al Bl about 2^-22 relative),
+// accumulated in FP32; the values g x are scaled by an exact power of two
+// that puts the snapshot's largest |Re|, |Im| in [2^13, 2^14) (fp16 range;
+// the weights lie in [0, 1]) and the tile is scaled back at the write-out.
+// The half-precision matrix cores run beside the vector ALU, where FP32
+// matrix instructions would share it.
 // NCOL = 16 (8 planes): one v_mfma_f32_16x16x1f32 (four 16 x 16 blocks) per
 // sample.  The accumulators hold the whole tile in registers: no LDS
 // accumulation, no atomics, nothing to flush.  Lane l
@@ -488,7 +497,6 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
     constexpr int kQuad = NCOL == 32 ? 16 : 4; // samples per step of the walk
     typedef float acc_t __attribute__((ext_vector_type(NREG)));
     typedef float f32x16 __attribute__((ext_vector_type(16)));
-    typedef bf16x8_t bf16x8;
     auto ld8 = [](const float* p, float* o) __attribute__((always_inline)) {
         const float4 u = reinterpret_cast<const float4*>(p)[0], w = reinterpret_cast<const float4*>(p)[1];
         o[0] = u.x; o[1] = u.y; o[2] = u.z; o[3] = u.w; o[4] = w.x; o[5] = w.y; o[6] = w.z; o[7] = w.w;
@@ -508,6 +516,19 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
     const int lane = threadIdx.x;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & (NCOL - 1);
+    // fp16 scale of the values (NCOL = 32): 2^(14 - e) for max |g x| = m 2^e,
+    // m in [0.5, 1); exact in both directions
+    float vs = 1.f, ivs = 1.f;
+    if constexpr (NCOL == 32) {
+        const float vmax = __uint_as_float(P->vmax_bits);
+        if (vmax > 0.f) {
+            int ex;
+            (void)frexpf(vmax, &ex);
+            ex = min(max(ex, -100), 127);
+            vs = ldexpf(1.f, 14 - ex);
+            ivs = ldexpf(1.f, ex - 14);
+        }
+    }
     // work units (heavy bins split) in decreasing order of work; normally one
     // per workgroup, handed out by the dispatcher as waves finish
     const int n_units = work_unit_count(cnt);
@@ -584,15 +605,15 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
                 tm1 = t;
                 t = tn;
             }
-            sV[q] = act ? vr : 0.f;
-            sV[64 + q] = act ? vi : 0.f;
+            sV[q] = act ? vr * vs : 0.f;
+            sV[64 + q] = act ? vi * vs : 0.f;
         }
         lds_order();                                        // staging writes precede the walk's reads
         // this lane's operands: A = weight of cell (lane mod 8, lane / 8);
         // B = column c = lane mod NCOL: order k0 + c mod NPL, Re (c < NPL) or Im
         if constexpr (NCOL == 32) {
-            // bf16 matrix cores, 16 samples per instruction: x = hi + lo in
-            // bf16, and A B = Ah Bh + Ah Bl + Al Bh (about 2^-17 relative).
+            // fp16 matrix cores, 16 samples per instruction: each product a b
+            // = hi + lo in fp16, and A B = Ah Bh + Ah Bl + Al Bh.
             // Lane l: rows (cells) l mod 32 and 32 + l mod 32 of A, column
             // l mod 32 of B, samples 8 (l / 32) .. + 7 of the group.
             const int h = lane >> 5, c = lane & 31;
@@ -607,23 +628,16 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
                 ld8(py + 4 * 64 + q0, y1);
                 ld8(pt + q0, t);
                 ld8(pv + q0, v);
-                float a0[8], a1[8], b[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    a0[e] = x[e] * y0[e];
-                    a1[e] = x[e] * y1[e];
-                    b[e] = t[e] * v[e];
-                }
-                bf16x8 a0h, a0l, a1h, a1l, bh, bl;
-                split_bf16x8(a0, a0h, a0l);
-                split_bf16x8(a1, a1h, a1l);
-                split_bf16x8(b, bh, bl);
-                acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, bh, acc_lo, 0, 0, 0);
-                acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, bh, acc_hi, 0, 0, 0);
-                acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, bl, acc_lo, 0, 0, 0);
-                acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, bl, acc_hi, 0, 0, 0);
-                acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, bh, acc_lo, 0, 0, 0);
-                acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, bh, acc_hi, 0, 0, 0);
+                f16x8_t a0h, a0l, a1h, a1l, bh, bl;
+                split_prod_f16x8(x, y0, a0h, a0l);
+                split_prod_f16x8(x, y1, a1h, a1l);
+                split_prod_f16x8(t, v, bh, bl);
+                acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0l, bh, acc_lo, 0, 0, 0);
+                acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1l, bh, acc_hi, 0, 0, 0);
+                acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0h, bl, acc_lo, 0, 0, 0);
+                acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1h, bl, acc_hi, 0, 0, 0);
+                acc_lo = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0h, bh, acc_lo, 0, 0, 0);
+                acc_hi = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1h, bh, acc_hi, 0, 0, 0);
             }
         } else {
             const float* pa = sx + (lane & 7) * 68;
@@ -677,7 +691,7 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
     for (int rg = 0; rg < NREG; ++rg) {
         const int cx = hx + (rg & 3);
         const int cy = NCOL == 32 ? (rg >> 2) : 2 * (rg >> 2) + hy;
-        wo[(cy * kTile + cx) * (NCOL + 1) + col] = acc[rg];
+        wo[(cy * kTile + cx) * (NCOL + 1) + col] = acc[rg] * ivs;
     }
     lds_order();
     if (un.parts > 1) {   // a split bin's partial tile [plane][cell], added up by k_split_sum

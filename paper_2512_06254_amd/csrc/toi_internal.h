@@ -42,7 +42,7 @@ struct DevPlan {
     int32_t gp;           // planes per group (LDS pass of the gridder)
     int32_t max_sg;       // at most this many slabs share a group (1: the gridders and the adjoint rely on it)
     int32_t unit_shift;   // work units of split bins hold at most 2^unit_shift items (from the tuning)
-    int32_t pad2_;
+    uint32_t vmax_bits;   // bits of max(|Re|, |Im|) of g x over the kept samples (non-negative float)
 };
 
 // Binned gridding: grid tiles of kTile x kTile cells, work items of kItemChans

@@ -172,3 +172,26 @@ def test_many_slab_aa2_like_automatic_plan():
     wl = S.scaled(S.WORKLOADS["aa2"], n_ant=16, n_chan=32, n_pix=128, n_steady=4, sigma_h_m=400.0)
     res, *_ = check_snapshot(S.make_snapshot(wl, 0), wl.n_pix, wl.cell_deg, mode=3, label="aa2 auto")
     assert res.plan.n_slab > 1
+
+
+@pytest.mark.parametrize("flux", [1.75, 3.0e4, 2.0e-6])
+def test_gridder_precision_few_samples(flux):
+    """A point source at the phase centre seen by 6 antennas x 8 channels (120
+    samples): no averaging over many samples hides the error of a single
+    product, so the t-plane is compared with the oracle at 2e-6 of its peak
+    (the split products carry about 22 significant bits).  Fluxes far from 1
+    check that the values' power-of-two scale keeps them in fp16 range."""
+    from paper_2512_06254_amd import toi as T
+    wl = S.scaled(S.WORKLOADS["tiny"], n_ant=6, n_chan=8, n_pix=64, cell_arcsec=60.0, n_corr=4, sigma_h_m=20.0)
+    snap = S.make_snapshot(wl, 0, with_noise=False)
+    snap["vis"] = np.zeros(snap["vis"].shape, dtype=np.complex64)
+    snap["vis"][:, :, 0] = snap["vis"][:, :, 3] = flux
+    res = O.image_snapshot(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=16)
+    img, tp, info = run_gpu(snap, wl.n_pix, wl.cell_deg, n_slab=1, cheb_k=16)
+    assert info["status"] == 0
+    c = wl.n_pix // 2
+    e = max_rel_err(tp, res.tplane)
+    print(f"[precision flux {flux:g}] t-plane err {e:.3e} of peak; centre {tp[c, c]:.7e} vs S/omega "
+          f"{flux / res.basis.omega:.7e}", flush=True)
+    assert abs(tp[c, c] - flux / res.basis.omega) <= 2e-6 * flux / res.basis.omega
+    assert e <= 2e-6
