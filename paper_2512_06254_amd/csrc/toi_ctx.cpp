@@ -107,7 +107,7 @@ void front_bytes(const toi_ctx* c, size_t out[14]) {
     out[6] = NG * NT * NT * sizeof(int32_t);                                              // bin_cursor
     out[7] = (size_t)c->bin_cap * sizeof(int32_t);                                        // bin_list
     out[8] = NG * NT * NT * sizeof(int32_t);                                              // bin_order
-    out[9] = (kAuxTotals + (NG * NT * NT + kScanBlock - 1) / kScanBlock) * sizeof(int32_t); // bin_aux
+    out[9] = (kAuxTotals + 2 * ((NG * NT * NT + kScanBlock - 1) / kScanBlock)) * sizeof(int32_t); // bin_aux
     out[10] = (size_t)kSplitSlots * sizeof(int4);                                         // units
     out[11] = NG * NT * words * sizeof(uint32_t);                                         // tile_bits
     out[12] = NG * words * sizeof(uint32_t);                                              // row_bits

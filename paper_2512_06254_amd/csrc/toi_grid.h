@@ -134,6 +134,35 @@ __device__ inline void work_unit_items(const WorkUnit& u, const int32_t* __restr
     }
 }
 
+// Tiles of tile row ty that the footprints of an item's kept samples can
+// touch: [tx0, tx1] (unwrapped; empty when tx1 < tx0).  A footprint starting
+// at row ceil(Y - 4) overlaps the tile row's cells [8 ty, 8 ty + 7] exactly
+// when Y lies in (8 ty - 4, 8 ty + 11]; along the track that is an interval
+// of the parameter l in [0, 1] (X, Y = start + l (end - start)), over which
+// the footprint start columns ceil(X - 4) give the tiles.  Both windows are
+// widened by 1e-6 cells, so that a sample whose coordinates were rounded
+// differently is never left out; a tile too many only costs a visit that
+// finds no sample.  At most nt tiles (one full turn of the periodic grid).
+__device__ inline void item_row_tiles(const ItemBox& b, int ty, int nt, int& tx0, int& tx1) {
+    constexpr double eps = 1e-6;
+    const double dy = b.y1 - b.y0, dx = b.x1 - b.x0;
+    double l0 = 0.0, l1 = 1.0;
+    if (dy != 0.0) {
+        const double la = (8.0 * ty - 4.0 - eps - b.y0) / dy, lb = (8.0 * ty + 11.0 + eps - b.y0) / dy;
+        l0 = fmax(0.0, fmin(la, lb));
+        l1 = fmin(1.0, fmax(la, lb));
+    }
+    if (!(l0 <= l1)) {
+        tx0 = 1;
+        tx1 = 0;
+        return;
+    }
+    const double xa = b.x0 + l0 * dx, xb = b.x0 + l1 * dx;
+    tx0 = ((int)ceil(fmin(xa, xb) - eps - 4.0)) >> kTileShift;
+    tx1 = ((int)ceil(fmax(xa, xb) + eps - 4.0) + 7) >> kTileShift;
+    tx1 = min(tx1, tx0 + nt - 1);
+}
+
 // Chebyshev recurrence T_{k+1} = 2 s T_k - T_{k-1} started at order k0:
 // returns t = T_{k0}(s) and tm1 = T_{k0-1}(s) (T_{-1} = T_1).
 __device__ inline void cheb_start(float s, int k0, float& t, float& tm1) {

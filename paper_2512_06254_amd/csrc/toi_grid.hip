@@ -48,8 +48,10 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     const int r = item / n_chunks;
     const int c = (item % n_chunks) * kItemChans + lane;
     ItemBox box;
-    box.tx0 = 1; box.tx1 = 0; box.ty0 = 1; box.ty1 = 0; box.g0 = 1; box.g1 = 0;
-    box.pad_[0] = box.pad_[1] = 0;
+    box.x0 = box.y0 = box.x1 = box.y1 = 0.0;
+    box.ty0 = 1; box.ty1 = 0; box.g0 = 1; box.g1 = 0;
+    box.vmax = 0.f;
+    box.pad_[0] = box.pad_[1] = box.pad_[2] = 0;
     if (P->status) {
         if (lane == 0) items[item] = box;
         return;
@@ -88,10 +90,11 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
         dst[0] = make_float4(__int_as_float(rec.pk), __int_as_float(rec.sp), rec.ox, rec.oy);
         dst[1] = make_float4(rec.ss, rec.vr, rec.vi, 0.f);
     }
+    // the item's largest value (reduced over all items by the bin scan: no
+    // atomic on one address per item)
+    box.vmax = wave_max(vabs);
     // X, Y and r3 are linear in nu along the row: their extremes over the kept
     // channels sit at the extreme kept frequencies
-    vabs = wave_max(vabs);             // non-negative floats order like their bit patterns
-    if (lane == 0 && vabs > 0.f) atomicMax(&P->vmax_bits, __float_as_uint(vabs));
     double nlo = 1e300, nhi = -1e300;
     if (kept) nlo = nhi = freq[c];
     nlo = wave_min(nlo);
@@ -100,28 +103,29 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
         if (lane == 0) items[item] = box;
         return;
     }
-    const double xa = 0.5 * M + tr.ax * nlo, xb = 0.5 * M + tr.ax * nhi;
-    const double ya = 0.5 * M + tr.ay * nlo, yb = 0.5 * M + tr.ay * nhi;
+    box.x0 = 0.5 * M + tr.ax * nlo;
+    box.x1 = 0.5 * M + tr.ax * nhi;
+    box.y0 = 0.5 * M + tr.ay * nlo;
+    box.y1 = 0.5 * M + tr.ay * nhi;
     const double ra = tr.a3 * nlo, rb = tr.a3 * nhi;
-    const double xlo = fmin(xa, xb), xhi = fmax(xa, xb), ylo = fmin(ya, yb), yhi = fmax(ya, yb);
-    const double rlo = fmin(ra, rb), rhi = fmax(ra, rb);
-    // footprint cells [ceil(X - 4), ceil(X - 4) + 7] -> tiles (floor division)
-    box.tx0 = ((int)ceil(xlo - 4.0)) >> kTileShift;
-    box.tx1 = ((int)ceil(xhi - 4.0) + 7) >> kTileShift;
-    box.ty0 = ((int)ceil(ylo - 4.0)) >> kTileShift;
-    box.ty1 = ((int)ceil(yhi - 4.0) + 7) >> kTileShift;
-    const int p0 = mode == 3 ? slab_index(rlo, P) : 0, p1 = mode == 3 ? slab_index(rhi, P) : 0;
-    box.g0 = group_of_slab(min(p0, p1), P);
-    box.g1 = group_of_slab(max(p0, p1), P) + (P->K > P->gp ? P->parts - 1 : 0);
+    const double ylo = fmin(box.y0, box.y1), yhi = fmax(box.y0, box.y1);
+    // footprint rows [ceil(Y - 4), ceil(Y - 4) + 7] -> tile rows (floor division)
+    box.ty0 = ((int)ceil(ylo - 1e-6 - 4.0)) >> kTileShift;
+    box.ty1 = ((int)ceil(yhi + 1e-6 - 4.0) + 7) >> kTileShift;
+    box.ty1 = min(box.ty1, box.ty0 + NT - 1);
+    const int p0 = mode == 3 ? slab_index(fmin(ra, rb), P) : 0, p1 = mode == 3 ? slab_index(fmax(ra, rb), P) : 0;
+    box.g0 = group_of_slab(p0, P);
+    box.g1 = group_of_slab(p1, P) + (P->K > P->gp ? P->parts - 1 : 0);
     if (lane == 0) items[item] = box;
-    // count into bins, lanes spread over the (group, tile) combinations
-    const int nx = box.tx1 - box.tx0 + 1, ny = box.ty1 - box.ty0 + 1, ng = box.g1 - box.g0 + 1;
-    const int tiles = NT * NT;
-    for (int e = lane; e < nx * ny * ng; e += 64) {
-        const int tx = (box.tx0 + e % nx) & (NT - 1);
-        const int ty = (box.ty0 + (e / nx) % ny) & (NT - 1);
-        const int g = box.g0 + e / (nx * ny);
-        atomicAdd(&bin_count[(size_t)g * tiles + ty * NT + tx], 1);
+    // count into bins: lanes take the tile rows, each row's tiles from the track
+    const int tiles = NT * NT, ny = box.ty1 - box.ty0 + 1;
+    for (int e = lane; e < ny; e += 64) {
+        const int ty = box.ty0 + e;
+        int tx0, tx1;
+        item_row_tiles(box, ty, NT, tx0, tx1);
+        for (int tx = tx0; tx <= tx1; ++tx)
+            for (int g = box.g0; g <= box.g1; ++g)
+                atomicAdd(&bin_count[(size_t)g * tiles + (ty & (NT - 1)) * NT + (tx & (NT - 1))], 1);
     }
 }
 
@@ -173,8 +177,18 @@ __device__ inline int block_exclusive_scan(int v, int& total) {
 
 __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__ count, int n_bins,
                                                      const DevPlan* __restrict__ P, int tiles,
+                                                     const ItemBox* __restrict__ items, int n_items,
                                                      int32_t* __restrict__ off, int32_t* __restrict__ aux) {
     __shared__ int32_t hist[32], hunits[32];
+    __shared__ float red[16];
+    {   // largest item value of this workgroup's share of the items
+        const int per = (n_items + gridDim.x - 1) / gridDim.x;
+        const int i0 = blockIdx.x * per, i1 = min(n_items, i0 + per);
+        float v = 0.f;
+        for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) v = fmaxf(v, items[i].vmax);
+        v = block_max(v, red);
+        if (threadIdx.x == 0) aux[kAuxTotals + gridDim.x + blockIdx.x] = __float_as_int(v);
+    }
     if (blockIdx.x * kScanBlock >= P->ng * tiles) {   // bins of unused plane groups hold no items
         if (threadIdx.x == 0) aux[kAuxTotals + blockIdx.x] = 0;
         return;
@@ -223,7 +237,12 @@ __global__ __launch_bounds__(1024) void k_scan_top(int n_blocks, int n_bins, int
         if (b < n_blocks) aux[kAuxTotals + b] = carry + ex;
         carry += total;
     }
+    __shared__ float red[16];
+    float v = 0.f;   // the snapshot's largest value, from the scan workgroups' partial maxima
+    for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) v = fmaxf(v, __int_as_float(aux[kAuxTotals + n_blocks + b]));
+    v = block_max(v, red);
     if (threadIdx.x == 0) {
+        P->vmax_bits = __float_as_uint(v);
         off[n_bins] = carry;
         if (carry > bin_cap) atomicOr(&P->status, (uint32_t)TOI_STATUS_OVERFLOW);
         int acc = 0;
@@ -342,15 +361,17 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
     const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (item >= n_items) return;
     const ItemBox box = items[item];
-    if (box.tx0 > box.tx1) return;
-    const int nx = box.tx1 - box.tx0 + 1, ny = box.ty1 - box.ty0 + 1, ng = box.g1 - box.g0 + 1;
-    const int tiles = NT * NT;
-    for (int e = lane; e < nx * ny * ng; e += 64) {
-        const int tx = (box.tx0 + e % nx) & (NT - 1);
-        const int ty = (box.ty0 + (e / nx) % ny) & (NT - 1);
-        const int g = box.g0 + e / (nx * ny);
-        const int pos = atomicAdd(&cursor[(size_t)g * tiles + ty * NT + tx], 1);
-        if (pos < bin_cap) list[pos] = item;
+    if (box.ty0 > box.ty1) return;
+    const int tiles = NT * NT, ny = box.ty1 - box.ty0 + 1;
+    for (int e = lane; e < ny; e += 64) {   // the same enumeration as the count in k_items
+        const int ty = box.ty0 + e;
+        int tx0, tx1;
+        item_row_tiles(box, ty, NT, tx0, tx1);
+        for (int tx = tx0; tx <= tx1; ++tx)
+            for (int g = box.g0; g <= box.g1; ++g) {
+                const int pos = atomicAdd(&cursor[(size_t)g * tiles + (ty & (NT - 1)) * NT + (tx & (NT - 1))], 1);
+                if (pos < bin_cap) list[pos] = item;
+            }
     }
 }
 
@@ -770,7 +791,7 @@ hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
                                (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M,
                                NT, cell, n_items, c->items, c->recs, c->bin_count);
         hipLaunchKernelGGL(k_scan_local, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, c->plan,
-                           NT * NT, c->bin_off, c->bin_aux);
+                           NT * NT, c->items, n_items, c->bin_off, c->bin_aux);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, n_scan, n_bins, c->bin_cap, c->plan,
                            c->bin_aux, c->bin_off, c->scratch_i);
         hipLaunchKernelGGL(k_scan_apply, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, NT,

@@ -59,7 +59,8 @@ constexpr int kScanBlock = 4096;   // bins per workgroup of the bin scan
 constexpr int kSplitSlots = 16384;
 // Layout of the bin scan's auxiliary array: per floor(log2(count)) bucket the
 // number of non-empty bins, the launch-order cursor and the work units of its
-// bins (ceil(count / 2^unit_shift) each), then one total per scan workgroup.
+// bins (ceil(count / 2^unit_shift) each), then one total per scan workgroup,
+// then one partial max(|Re|, |Im|) of g x per scan workgroup (float bits).
 constexpr int kAuxBuckets = 0, kAuxCursors = 32, kAuxUnits = 64, kAuxTotals = 96;
 // After the list fill, every bin's items are put in increasing item order:
 // bins of fewer than 2^kSortShift items by one wavefront, larger ones by a
@@ -95,10 +96,17 @@ inline GridShape grid_shape(int tuning) {
     return g;
 }
 
-// Bin of one work item: tile and group ranges it touches (unwrapped tile
-// indices; wrapped modulo the tiles per axis when used).
+// Bin of one work item: the track of its kept samples (grid coordinates X, Y
+// at the lowest and the highest kept frequency; both are linear in the
+// frequency along a row), the tile rows and plane groups it touches
+// (unwrapped tile indices, wrapped modulo the tiles per axis when used; empty
+// when ty1 < ty0), and max(|Re|, |Im|) of g x over its kept samples.  The
+// tiles of each tile row follow from the track (item_row_tiles, toi_grid.h).
 struct ItemBox {
-    int32_t tx0, tx1, ty0, ty1, g0, g1, pad_[2];
+    double x0, y0, x1, y1;
+    int32_t ty0, ty1, g0, g1;
+    float vmax;
+    int32_t pad_[3];
 };
 
 // One sample prepared for gridding (written by k_items, read by the
