@@ -136,6 +136,26 @@ toi_status toi_degrid(toi_ctx* ctx, const float* grad_image, const toi_snapshot*
 toi_status fitrig_tlisi(toi_ctx* ctx, const float* img_tm2, const float* img_tm1,
                         const float* img_t, float* tlisi_out);
 
+/* fitrig_tlisi without a context and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same kernels and results as
+ * fitrig_tlisi (bit for bit) on three caller-owned device images
+ * f32[n_pix][n_pix] and a caller-owned f32[n_pix/tile][n_pix/tile] output,
+ * enqueued on hip_stream (a stream of the current device; NULL = its null
+ * stream).  The per-tile statistics live in a static device array of
+ * TOI_TLISI_STATIC_TILES entries (64 bytes each, 4 MiB) that every device the
+ * library runs on holds until the process ends; its device address is looked
+ * up once per device on that device's first call.  Every call on one device
+ * shares that array and overwrites it completely before reading it, so
+ * nothing needs clearing, but calls that overlap on one device (concurrent
+ * streams or threads) race and give undefined results: serialise them.
+ * Errors (NULL pointers, tile not dividing n_pix, more than
+ * TOI_TLISI_STATIC_TILES tiles) return TOI_EINVAL without launching anything;
+ * toi_last_error(NULL) gives the message. */
+#define TOI_TLISI_STATIC_TILES 65536
+toi_status fitrig_tlisi_noalloc(const float* img_tm2, const float* img_tm1, const float* img_t,
+                                int32_t n_pix, int32_t tile, float* tlisi_out, void* hip_stream);
+
 /* FITrig detection (Section 2) over a sliding window of the 16 newest tLISI
  * maps: per tile, the harmonic-summed DFT power of the window and the
  * non-periodic score sum(1 - tLISI), z-scores over tiles, thresholds 5 and 4,

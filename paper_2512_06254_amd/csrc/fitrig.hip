@@ -10,6 +10,9 @@
 //   tLISI = clamp((1 + S) / 2, 0, 1)          (1 everywhere when L = 0).
 // Pass 1 (one workgroup per tile) forms FP64 sums, minimum and maximum;
 // pass 2 (one workgroup) combines the ranges and evaluates each tile.
+#include <mutex>
+#include <string>
+
 #include "toi_device.h"
 #include "toi_internal.h"
 
@@ -72,15 +75,70 @@ __global__ __launch_bounds__(1024) void k_tlisi_final(const TileStat* __restrict
     }
 }
 
+static void tlisi_kernels(hipStream_t stream, const float* a, const float* b, const float* d, int N, int tile,
+                          TileStat* stats, float* out) {
+    const int T = N / tile;
+    hipLaunchKernelGGL(k_tlisi_tiles, dim3(T * T), dim3(256), 0, stream, a, b, d, N, tile, stats);
+    hipLaunchKernelGGL(k_tlisi_final, dim3(1), dim3(1024), 0, stream, stats, T * T, tile, out);
+}
+
 hipError_t launch_tlisi(toi_ctx* c, const float* a, const float* b, const float* d, float* out) {
-    const int T = c->T;
     StageTimer timer(c, TOI_STAGE_TLISI);
-    hipLaunchKernelGGL(k_tlisi_tiles, dim3(T * T), dim3(256), 0, c->stream, a, b, d, c->N, c->p.tile, c->tiles);
-    hipLaunchKernelGGL(k_tlisi_final, dim3(1), dim3(1024), 0, c->stream, c->tiles, T * T, c->p.tile, out);
+    tlisi_kernels(c->stream, a, b, d, c->N, c->p.tile, c->tiles, out);
     return hipGetLastError();
 }
 
+// tLISI without a context: the per-tile statistics go to this file-scope
+// device array instead of a context's workspace.  Every device the library
+// runs on holds its own copy for the life of the process.  In host code the
+// array's name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device on its first call and kept in scratch_dev.
+static __device__ __align__(256) TileStat scratch[TOI_TLISI_STATIC_TILES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+TileStat* scratch_dev[kMaxDevices];
+
+toi_status scratch_address(int dev, TileStat** out) {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_check(nullptr, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                      "fitrig_tlisi_noalloc: hipGetSymbolAddress");
+        scratch_dev[dev] = static_cast<TileStat*>(ptr);
+    }
+    *out = scratch_dev[dev];
+    return TOI_OK;
+}
+}  // namespace
+
 }  // namespace toi
+
+extern "C" toi_status fitrig_tlisi_noalloc(const float* img_tm2, const float* img_tm1, const float* img_t,
+                                           int32_t n_pix, int32_t tile, float* tlisi_out, void* hip_stream) {
+    using namespace toi;
+    if (!img_tm2 || !img_tm1 || !img_t || !tlisi_out)
+        return fail(nullptr, TOI_EINVAL, "fitrig_tlisi_noalloc: NULL image or output");
+    if (n_pix <= 0 || tile <= 0 || n_pix % tile != 0)
+        return fail(nullptr, TOI_EINVAL, "fitrig_tlisi_noalloc: n_pix and tile must be > 0 and tile must divide n_pix");
+    const long T = n_pix / tile;
+    if (T * T > TOI_TLISI_STATIC_TILES)
+        return fail(nullptr, TOI_EINVAL,
+                    "fitrig_tlisi_noalloc: (n_pix / tile)^2 = " + std::to_string(T * T) +
+                        " tiles exceeds the static scratch of " + std::to_string(TOI_TLISI_STATIC_TILES));
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(nullptr, e, "fitrig_tlisi_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, TOI_EUNSUPPORTED, "fitrig_tlisi_noalloc: device index");
+    TileStat* stats = nullptr;
+    const toi_status st = scratch_address(dev, &stats);
+    if (st != TOI_OK) return st;
+    tlisi_kernels(static_cast<hipStream_t>(hip_stream), img_tm2, img_tm1, img_t, n_pix, tile, stats, tlisi_out);
+    return hip_check(nullptr, hipGetLastError(), "fitrig_tlisi_noalloc");
+}
 
 // ---------------------------------------------------------------- S9: window detection
 // One workgroup (the window is tile-grid sized): per tile the periodic score

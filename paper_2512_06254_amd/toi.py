@@ -58,6 +58,8 @@ _SIGS = {
     "toi_degrid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Snapshot),
                                   ctypes.c_void_p, ctypes.c_void_p]),
     "fitrig_tlisi": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "fitrig_tlisi_noalloc": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_int32,
+                                                                    ctypes.c_void_p, ctypes.c_void_p]),
     "fitrig_detect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_int32, ctypes.c_void_p]),
     "fitrig_detect_cube": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -342,6 +344,18 @@ class Imager:
         import numpy as np
         return dict(V=np.array(V[:]).reshape(3, 3), omega=om.value, wsum=ws.value, n_slab=ns.value,
                     K=k.value, status=st.value)
+
+
+def tlisi_noalloc(a, b, c, tile: int, out):
+    """fitrig_tlisi_noalloc: the tLISI map of three device images into the
+    caller's ``out`` (float32 [N/tile][N/tile]) on torch's current stream, with
+    no context and no allocation (the library's static per-device scratch)."""
+    import torch
+    n_pix = int(a.shape[-1])
+    stream = torch.cuda.current_stream(a.device).cuda_stream
+    _check(lib().fitrig_tlisi_noalloc(_ptr(a), _ptr(b), _ptr(c), n_pix, int(tile), _ptr(out),
+                                      ctypes.c_void_p(stream)))
+    return out
 
 
 def to_device(snap: dict, device="cuda") -> dict:

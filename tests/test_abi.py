@@ -60,6 +60,18 @@ def test_argument_validation_without_device(lib):
         assert code == (T.TOI_OK if fn == "toi_destroy" else T.TOI_EINVAL), fn
 
 
+def test_noalloc_tlisi_rejects_arguments_before_any_launch(lib):
+    from paper_2512_06254_amd import toi as T
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: every case fails its argument check
+    cases = [((None, fake, fake, 256, 32, fake, None), "NULL"),
+             ((fake, fake, fake, 256, 0, fake, None), "tile"),
+             ((fake, fake, fake, 250, 32, fake, None), "tile"),
+             ((fake, fake, fake, 16384, 32, fake, None), "static scratch")]   # 262144 tiles
+    for args, word in cases:
+        assert lib.fitrig_tlisi_noalloc(*args) == T.TOI_EINVAL
+        assert word in lib.toi_last_error(None).decode()
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     from paper_2512_06254_amd import toi as T
     monkeypatch.setattr(T, "LIB_PATH", str(tmp_path / "missing.so"))
