@@ -21,7 +21,7 @@ namespace toi {
 __global__ __launch_bounds__(256) void k_tlisi_tiles(const float* __restrict__ a, const float* __restrict__ b,
                                                      const float* __restrict__ c, int N, int tile,
                                                      TileStat* __restrict__ out) {
-    __shared__ double red[8][4];
+    __shared__ double red[5][16], redm[2][4];
     const int T = N / tile;
     const int ty = blockIdx.x / T, tx = blockIdx.x % T;
     double sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0, mn = 1e300, mx = -1e300;
@@ -34,16 +34,14 @@ __global__ __launch_bounds__(256) void k_tlisi_tiles(const float* __restrict__ a
         mn = fmin(mn, fmin(X, Y));
         mx = fmax(mx, fmax(X, Y));
     }
-    sx = block_sum(sx, red[0]);
-    sy = block_sum(sy, red[1]);
-    sxx = block_sum(sxx, red[2]);
-    syy = block_sum(syy, red[3]);
-    sxy = block_sum(sxy, red[4]);
-    mn = block_min(mn, red[5]);
-    mx = block_max(mx, red[6]);
+    double sums[5] = {sx, sy, sxx, syy, sxy};
+    block_sum_n(sums, red);
+    mn = block_min(mn, redm[0]);
+    mx = block_max(mx, redm[1]);
     if (threadIdx.x == 0) {
         TileStat s;
-        s.sx = sx; s.sy = sy; s.sxx = sxx; s.syy = syy; s.sxy = sxy; s.mn = mn; s.mx = mx; s.pad_ = 0;
+        s.sx = sums[0]; s.sy = sums[1]; s.sxx = sums[2]; s.syy = sums[3]; s.sxy = sums[4];
+        s.mn = mn; s.mx = mx; s.pad_ = 0;
         out[blockIdx.x] = s;
     }
 }

@@ -149,6 +149,29 @@ __device__ inline T block_min(T v, T* red) {
     return s;
 }
 
+// Sums of NV values over a block (blockDim.x a multiple of 64, <= 1024) in one
+// LDS round: each wavefront reduces its values (fixed butterfly order), the
+// waves' partial sums go to red[NV][16], and every thread adds them in wave
+// order.  v is replaced by the block totals.
+template <int NV>
+__device__ inline void block_sum_n(double (&v)[NV], double (*red)[16]) {
+    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[i][w] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < nw; ++j) s += red[i][j];
+        v[i] = s;
+    }
+    __syncthreads();
+}
+
 __device__ inline float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

@@ -15,10 +15,41 @@ constexpr uint32_t kStatusFatal =
     TOI_STATUS_NO_SAMPLES | TOI_STATUS_DEGENERATE | TOI_STATUS_PLANES | TOI_STATUS_OVERFLOW;
 
 // Weighted sum of the selected correlations of one (row, channel) sample with
-// flags as zero weight (Section 3.5).  Returns the sample weight w.
+// flags as zero weight (Section 3.5).  Returns the sample weight w.  With
+// vec4 (four correlations and arrays aligned for it: vis to 16 bytes, flags
+// to 4, weights to 16; see vec4_ok) the sample is read as two 16-byte loads
+// (and one word of flags, one 16-byte load of weights) instead of one load
+// per correlation; the sums are formed in the same order.
 __device__ inline float sample_value(const float2* __restrict__ vis, const float* __restrict__ weight,
                                      const uint8_t* __restrict__ flag, size_t base, int n_corr, uint32_t mask,
-                                     float& xr, float& xi) {
+                                     float& xr, float& xi, bool vec4 = false) {
+    if (vec4) {
+        const float4* v4 = reinterpret_cast<const float4*>(vis + base);
+        const float4 a = v4[0], b = v4[1];
+        float wk[4] = {1.f, 1.f, 1.f, 1.f};
+        if (weight) {
+            const float4 q = *reinterpret_cast<const float4*>(weight + base);
+            wk[0] = q.x; wk[1] = q.y; wk[2] = q.z; wk[3] = q.w;
+        }
+        if (flag) {
+            const uint32_t f = *reinterpret_cast<const uint32_t*>(flag + base);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if ((f >> (8 * k)) & 0xffu) wk[k] = 0.f;
+        }
+        const float vr[4] = {a.x, a.z, b.x, b.z}, vi[4] = {a.y, a.w, b.y, b.w};
+        float w = 0.f;
+        xr = 0.f;
+        xi = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!((mask >> k) & 1u)) continue;
+            w += wk[k];
+            xr += wk[k] * vr[k];
+            xi += wk[k] * vi[k];
+        }
+        return w;
+    }
     float w = 0.f;
     xr = 0.f;
     xi = 0.f;
@@ -32,6 +63,12 @@ __device__ inline float sample_value(const float2* __restrict__ vis, const float
         xi += wk * v.y;
     }
     return w;
+}
+
+// Whether sample_value may read a snapshot's samples with 16-byte loads.
+inline bool vec4_ok(const void* vis, const void* flag, const void* weight, int n_corr) {
+    return n_corr == 4 && (reinterpret_cast<uintptr_t>(vis) & 15) == 0 &&
+           (reinterpret_cast<uintptr_t>(flag) & 3) == 0 && (reinterpret_cast<uintptr_t>(weight) & 15) == 0;
 }
 
 __device__ inline bool sample_kept(const float* __restrict__ weight, const uint8_t* __restrict__ flag, size_t base,
@@ -141,14 +178,14 @@ __device__ inline void work_unit_items(const WorkUnit& u, const int32_t* __restr
 // of the parameter l in [0, 1] (X, Y = start + l (end - start)), over which
 // the footprint start columns ceil(X - 4) give the tiles.  Both windows are
 // widened by 1e-6 cells, so that a sample whose coordinates were rounded
-// differently is never left out; a tile too many only costs a visit that
-// finds no sample.  At most nt tiles (one full turn of the periodic grid).
+// differently (or the interval's ends by the reciprocal of the extent) is
+// never left out; a tile too many only costs a visit that finds no sample.  At most nt tiles (one full turn of the periodic grid).
 __device__ inline void item_row_tiles(const ItemBox& b, int ty, int nt, int& tx0, int& tx1) {
     constexpr double eps = 1e-6;
-    const double dy = b.y1 - b.y0, dx = b.x1 - b.x0;
+    const double dx = b.x1 - b.x0;
     double l0 = 0.0, l1 = 1.0;
-    if (dy != 0.0) {
-        const double la = (8.0 * ty - 4.0 - eps - b.y0) / dy, lb = (8.0 * ty + 11.0 + eps - b.y0) / dy;
+    if (b.inv_dy != 0.0) {
+        const double la = (8.0 * ty - 4.0 - eps - b.y0) * b.inv_dy, lb = (8.0 * ty + 11.0 + eps - b.y0) * b.inv_dy;
         l0 = fmax(0.0, fmin(la, lb));
         l1 = fmin(1.0, fmax(la, lb));
     }
@@ -161,6 +198,45 @@ __device__ inline void item_row_tiles(const ItemBox& b, int ty, int nt, int& tx0
     tx0 = ((int)ceil(fmin(xa, xb) - eps - 4.0)) >> kTileShift;
     tx1 = ((int)ceil(fmax(xa, xb) + eps - 4.0) + 7) >> kTileShift;
     tx1 = min(tx1, tx0 + nt - 1);
+}
+
+// Every (plane group, tile) bin of an item, spread over the 64 lanes of the
+// calling wavefront: f(g, ty, tx) is called once per bin (wrapped tile
+// indices).  Lane r first takes tile row ty0 + r and its tiles; a wave-wide
+// prefix sum of the per-row counts then deals the (row, tile, group) entries
+// round-robin over the lanes.  Items with more than 64 tile rows (long tracks
+// on large grids) take their rows in turn.  All lanes must call it.
+template <typename F>
+__device__ inline void for_item_bins(const ItemBox& b, int NT, F f) {
+    const int lane = threadIdx.x & 63;
+    const int ny = b.ty1 - b.ty0 + 1, ng = b.g1 - b.g0 + 1;
+    if (ny <= 0 || ng <= 0) return;
+    for (int r0 = 0; r0 < ny; r0 += 64) {
+        const int ty = b.ty0 + r0 + lane;
+        int tx0 = 1, tx1 = 0;
+        if (r0 + lane < ny) item_row_tiles(b, ty, NT, tx0, tx1);
+        const int cnt = max(0, tx1 - tx0 + 1);
+        int incl = cnt;   // inclusive prefix sum over the lanes
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        const int total = __shfl(incl, 63, 64);   // uniform: every lane runs every round
+        for (int e0 = 0; e0 < total * ng; e0 += 64) {
+            const int e = min(e0 + lane, total * ng - 1);
+            const int ti = e % total, g = b.g0 + e / total;
+            // the lane whose row holds tile entry ti: the first with incl > ti
+            int lo = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                const int probe = __shfl(incl, lo + step - 1, 64);
+                if (probe <= ti) lo += step;
+            }
+            const int start = __shfl(incl - cnt, lo, 64), rtx0 = __shfl(tx0, lo, 64);
+            if (e0 + lane < total * ng) f(g, (b.ty0 + r0 + lo) & (NT - 1), (rtx0 + ti - start) & (NT - 1));
+        }
+    }
 }
 
 // Chebyshev recurrence T_{k+1} = 2 s T_k - T_{k-1} started at order k0:

@@ -37,8 +37,8 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
                                                const float* __restrict__ weight, const uint8_t* __restrict__ flag,
                                                const double* __restrict__ freq, const int32_t* __restrict__ ant1,
                                                const int32_t* __restrict__ ant2, const float2* __restrict__ gains,
-                                               int n_ant, int n_chan, int n_corr, uint32_t mask, int mode,
-                                               DevPlan* __restrict__ P, int M, int NT, double cell_rad,
+                                               int n_ant, int n_chan, int n_corr, uint32_t mask, int vec4,
+                                               int mode, DevPlan* __restrict__ P, int M, int NT, double cell_rad,
                                                int n_items, ItemBox* __restrict__ items, SampleRec* __restrict__ recs,
                                                int32_t* __restrict__ bin_count) {
     const int lane = threadIdx.x & 63;
@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     box.x0 = box.y0 = box.x1 = box.y1 = 0.0;
     box.ty0 = 1; box.ty1 = 0; box.g0 = 1; box.g1 = 0;
     box.vmax = 0.f;
-    box.pad_[0] = box.pad_[1] = box.pad_[2] = 0;
+    box.pad_ = 0;
+    box.inv_dy = 0.0;
     if (P->status) {
         if (lane == 0) items[item] = box;
         return;
@@ -62,7 +63,8 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     float vabs = 0.f;                  // max(|Re|, |Im|) of g x (the gridder's fp16 operand scale)
     if (c < n_chan) {
         float xr, xi;
-        const float w = sample_value(vis, weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask, xr, xi);
+        const float w = sample_value(vis, weight, flag, ((size_t)r * n_chan + c) * n_corr, n_corr, mask, xr, xi,
+                                     vec4 != 0);
         SampleRec rec;
         rec.pk = -1;
         rec.sp = 0;
@@ -107,6 +109,8 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     box.x1 = 0.5 * M + tr.ax * nhi;
     box.y0 = 0.5 * M + tr.ay * nlo;
     box.y1 = 0.5 * M + tr.ay * nhi;
+    // (an extent below 1e-9 cells counts as none: every row then takes the whole X range)
+    box.inv_dy = fabs(box.y1 - box.y0) > 1e-9 ? 1.0 / (box.y1 - box.y0) : 0.0;
     const double ra = tr.a3 * nlo, rb = tr.a3 * nhi;
     const double ylo = fmin(box.y0, box.y1), yhi = fmax(box.y0, box.y1);
     // footprint rows [ceil(Y - 4), ceil(Y - 4) + 7] -> tile rows (floor division)
@@ -117,16 +121,9 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     box.g0 = group_of_slab(p0, P);
     box.g1 = group_of_slab(p1, P) + (P->K > P->gp ? P->parts - 1 : 0);
     if (lane == 0) items[item] = box;
-    // count into bins: lanes take the tile rows, each row's tiles from the track
-    const int tiles = NT * NT, ny = box.ty1 - box.ty0 + 1;
-    for (int e = lane; e < ny; e += 64) {
-        const int ty = box.ty0 + e;
-        int tx0, tx1;
-        item_row_tiles(box, ty, NT, tx0, tx1);
-        for (int tx = tx0; tx <= tx1; ++tx)
-            for (int g = box.g0; g <= box.g1; ++g)
-                atomicAdd(&bin_count[(size_t)g * tiles + (ty & (NT - 1)) * NT + (tx & (NT - 1))], 1);
-    }
+    // count into bins (each row's tiles from the track)
+    const int tiles = NT * NT;
+    for_item_bins(box, NT, [&](int g, int ty, int tx) { atomicAdd(&bin_count[(size_t)g * tiles + ty * NT + tx], 1); });
 }
 
 // ---------------------------------------------------------------- 2. scan
@@ -357,22 +354,14 @@ __global__ __launch_bounds__(1024) void k_units(const DevPlan* __restrict__ P, c
 __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ items, int n_items, int NT,
                                                   int bin_cap, int32_t* __restrict__ cursor,
                                                   int32_t* __restrict__ list) {
-    const int lane = threadIdx.x & 63;
     const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (item >= n_items) return;
     const ItemBox box = items[item];
-    if (box.ty0 > box.ty1) return;
-    const int tiles = NT * NT, ny = box.ty1 - box.ty0 + 1;
-    for (int e = lane; e < ny; e += 64) {   // the same enumeration as the count in k_items
-        const int ty = box.ty0 + e;
-        int tx0, tx1;
-        item_row_tiles(box, ty, NT, tx0, tx1);
-        for (int tx = tx0; tx <= tx1; ++tx)
-            for (int g = box.g0; g <= box.g1; ++g) {
-                const int pos = atomicAdd(&cursor[(size_t)g * tiles + (ty & (NT - 1)) * NT + (tx & (NT - 1))], 1);
-                if (pos < bin_cap) list[pos] = item;
-            }
-    }
+    const int tiles = NT * NT;
+    for_item_bins(box, NT, [&](int g, int ty, int tx) {   // the same bins as the count in k_items
+        const int pos = atomicAdd(&cursor[(size_t)g * tiles + ty * NT + tx], 1);
+        if (pos < bin_cap) list[pos] = item;
+    });
 }
 
 // ---------------------------------------------------------------- 2c. order
@@ -788,7 +777,8 @@ hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
         if (n_items > 0)
             hipLaunchKernelGGL(k_items, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw,
                                (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2,
-                               (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask, p.mode, c->plan, M,
+                               (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask,
+                               (int)vec4_ok(s.vis, s.flag, s.weight, p.n_corr), p.mode, c->plan, M,
                                NT, cell, n_items, c->items, c->recs, c->bin_count);
         hipLaunchKernelGGL(k_scan_local, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, c->plan,
                            NT * NT, c->items, n_items, c->bin_off, c->bin_aux);

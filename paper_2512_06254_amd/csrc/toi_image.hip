@@ -69,7 +69,7 @@ __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_fft_rows(cons
         fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) keep[rb][q] = v[fft_kept_slot<E>(q)];
-        __syncthreads();
+        // (the next row's first exchange starts with a barrier: no barrier here)
     }
 #pragma unroll
     for (int q = 0; q < KEEP; ++q) {
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
                         }
                     }
                 }
-                __syncthreads();
+                // (the next plane's first exchange starts with a barrier)
             }
             const float r3p = (float)(plan->r3min + (2 * p + 1) * plan->dr3);
 #pragma unroll

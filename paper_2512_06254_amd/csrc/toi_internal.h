@@ -100,13 +100,15 @@ inline GridShape grid_shape(int tuning) {
 // at the lowest and the highest kept frequency; both are linear in the
 // frequency along a row), the tile rows and plane groups it touches
 // (unwrapped tile indices, wrapped modulo the tiles per axis when used; empty
-// when ty1 < ty0), and max(|Re|, |Im|) of g x over its kept samples.  The
+// when ty1 < ty0), max(|Re|, |Im|) of g x over its kept samples, and the
+// reciprocal of the track's extent in Y.  The
 // tiles of each tile row follow from the track (item_row_tiles, toi_grid.h).
 struct ItemBox {
     double x0, y0, x1, y1;
     int32_t ty0, ty1, g0, g1;
     float vmax;
-    int32_t pad_[3];
+    int32_t pad_;
+    double inv_dy;   // 1 / (y1 - y0), 0 when |y1 - y0| <= 1e-9
 };
 
 // One sample prepared for gridding (written by k_items, read by the

@@ -36,16 +36,14 @@ __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ wei
             mx = fmax(mx, nu);
         }
     }
-    __shared__ double red[6][256 / 64];
-    cnt = block_sum(cnt, red[0]);
-    s1 = block_sum(s1, red[1]);
-    s2 = block_sum(s2, red[2]);
-    ws = block_sum(ws, red[3]);
-    mn = block_min(mn, red[4]);
-    mx = block_max(mx, red[5]);
+    __shared__ double red[4][16], redm[2][16];
+    double sums[4] = {cnt, s1, s2, ws};
+    block_sum_n(sums, red);
+    mn = block_min(mn, redm[0]);
+    mx = block_max(mx, redm[1]);
     if (threadIdx.x == 0) {
         RowStat o;
-        o.cnt = cnt; o.s1 = s1; o.s2 = s2; o.wsum = ws; o.numin = mn; o.numax = mx;
+        o.cnt = sums[0]; o.s1 = sums[1]; o.s2 = sums[2]; o.wsum = sums[3]; o.numin = mn; o.numax = mx;
         o.pad_[0] = o.pad_[1] = 0;
         rows[r] = o;
     }
@@ -96,7 +94,7 @@ __device__ inline void positive_major(double e[3]) {
 __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, const RowStat* __restrict__ rows,
                                                int n_row, int mode, int gp, int max_sg, int unit_shift,
                                                DevPlan* __restrict__ plan) {
-    __shared__ double red[16][4];
+    __shared__ double red[16][4], red11[11][16];
     __shared__ double V_s[9];
     __shared__ uint32_t status_s;
     double acc[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -110,7 +108,7 @@ __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, c
         acc[5] += u[0] * u[0] * s.s2; acc[6] += u[0] * u[1] * s.s2; acc[7] += u[0] * u[2] * s.s2;
         acc[8] += u[1] * u[1] * s.s2; acc[9] += u[1] * u[2] * s.s2; acc[10] += u[2] * u[2] * s.s2;
     }
-    for (int i = 0; i < 11; ++i) acc[i] = block_sum(acc[i], red[i]);
+    block_sum_n(acc, red11);
     if (threadIdx.x == 0) {
         DevPlan P{};
         P.nvis = acc[0];
@@ -194,11 +192,50 @@ __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ uvw, c
 }
 
 // ---------------------------------------------------------------- S3: t3max over the t-plane
+// |t3| = |sg sqrt(1 - rho^2) - V33| with rho^2 = (t1 + V13)^2 + (t2 + V23)^2
+// (eq. t3) depends on the pixel only through rho, falls to 0 at the phase
+// centre's rho0 = sqrt(V13^2 + V23^2) and grows with |rho - rho0| on either
+// side; rho^2 is a convex quadratic in (t1, t2), separable in j1 and j2.  Over
+// the pixel grid its maximum therefore sits at a corner and its minimum at
+// one of the four pixels around the point t = (-V13, -V23) (clamped to the
+// grid), so when all four corners are valid (then every pixel is), the
+// maximum of |t3| over all pixel centres is the maximum over those eight
+// pixels (the same expression as the scan, equal to it up to rounding).
+// Otherwise every pixel is scanned.
+__device__ inline double t3_abs(int j1, int j2, int N, double cell_rad, double V13, double V23, double V33,
+                                double sg, bool& valid) {
+    const double t1 = -cell_rad * (j1 - N / 2), t2 = cell_rad * (j2 - N / 2);
+    const double a = 1.0 - (t1 + V13) * (t1 + V13) - (t2 + V23) * (t2 + V23);
+    valid = a >= 0;
+    return valid ? fabs(-V33 + sg * sqrt(a)) : 0.0;
+}
+
 __global__ __launch_bounds__(256) void k_t3max(int N, double cell_rad, DevPlan* __restrict__ plan) {
     __shared__ double red[4];
     if (plan->status & TOI_STATUS_NO_SAMPLES) return;
     const double V13 = plan->V[2], V23 = plan->V[5], V33 = plan->V[8];
     const double sg = V33 >= 0 ? 1.0 : -1.0;
+    {
+        bool ok = true, v;
+        double m = 0.0;
+        const int cj[2] = {0, N - 1};
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                m = fmax(m, t3_abs(cj[a], cj[b], N, cell_rad, V13, V23, V33, sg, v));
+                ok = ok && v;
+            }
+        if (ok) {   // corners valid: the corners and the pixels around the stationary point
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                const double c1 = N / 2 + V13 / cell_rad, c2 = N / 2 - V23 / cell_rad;   // t1 = -V13, t2 = -V23
+                const int f1 = (int)fmin(fmax(floor(c1), 0.0), N - 1.0), f2 = (int)fmin(fmax(floor(c2), 0.0), N - 1.0);
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b)
+                        m = fmax(m, t3_abs(min(f1 + a, N - 1), min(f2 + b, N - 1), N, cell_rad, V13, V23, V33, sg, v));
+                plan->t3max = m;
+            }
+            return;
+        }
+    }
     double m = 0.0;
     const long total = (long)N * N;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
