@@ -61,11 +61,16 @@ __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_fft_rows(cons
     const uint32_t occ = fft_element_bits<M, E>(
         [&](int x) { return (tb[x >> (kTileShift + 5)] >> ((x >> kTileShift) & 31)) & 1u; });
     float2 keep[B][KEEP];
+    // the next row's loads are issued before this row's transform
+    float2 vn[E];
+    fft_load_bits<M, E>(vn, grid + ((size_t)plane * M + band * B) * M, occ);
 #pragma unroll
     for (int rb = 0; rb < B; ++rb) {
         const int y = band * B + rb;
         float2 v[E];
-        fft_load_bits<M, E>(v, grid + ((size_t)plane * M + y) * M, occ);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = vn[e];
+        if (rb + 1 < B) fft_load_bits<M, E>(vn, grid + ((size_t)plane * M + y + 1) * M, occ);
         fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) keep[rb][q] = v[fft_kept_slot<E>(q)];
@@ -148,7 +153,12 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
             float jp1[KEEP], jc[KEEP], nrm[KEEP], ar[KEEP], ai[KEEP];
 #pragma unroll
             for (int q = 0; q < KEEP; ++q) { jp1[q] = 0.f; jc[q] = 1.f; nrm[q] = 0.f; ar[q] = 0.f; ai[q] = 0.f; }
-            // orders L .. K: recurrence only
+            // orders L .. K: recurrence only (no plane yet, ar = ai = 0).
+            // The values grow by at most 2n / |alpha| <= 2e3 n per order
+            // (|alpha| >= 1e-3 here; small |alpha| has ialpha = 0 and does
+            // not grow), so a rescale by 2^-50 when |J| > 2^50, checked every
+            // second order, stays far inside FP32 for any start order below
+            // 10^8; the scale is exact and cancels in the normalisation.
             for (int n = L; n >= K; --n) {
 #pragma unroll
                 for (int q = 0; q < KEEP; ++q) {
@@ -156,9 +166,8 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
                     const float jm1 = (2.f * n) * ialpha[q] * jc[q] - jp1[q];
                     jp1[q] = jc[q];
                     jc[q] = jm1;
-                    if (fabsf(jc[q]) > 1e15f) {
-                        jc[q] *= 1e-15f; jp1[q] *= 1e-15f; nrm[q] *= 1e-15f;
-                        ar[q] *= 1e-15f; ai[q] *= 1e-15f;
+                    if ((n & 1) == 0 && fabsf(jc[q]) > 0x1p50f) {
+                        jc[q] *= 0x1p-50f; jp1[q] *= 0x1p-50f; nrm[q] *= 0x1p-50f;
                     }
                 }
             }
@@ -199,9 +208,9 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
                         const float jm1 = (2.f * k) * ialpha[q] * jc[q] - jp1[q];
                         jp1[q] = jc[q];
                         jc[q] = jm1;
-                        if (fabsf(jc[q]) > 1e15f) {
-                            jc[q] *= 1e-15f; jp1[q] *= 1e-15f; nrm[q] *= 1e-15f;
-                            ar[q] *= 1e-15f; ai[q] *= 1e-15f;
+                        if ((k & 1) == 0 && fabsf(jc[q]) > 0x1p50f) {
+                            jc[q] *= 0x1p-50f; jp1[q] *= 0x1p-50f; nrm[q] *= 0x1p-50f;
+                            ar[q] *= 0x1p-50f; ai[q] *= 0x1p-50f;
                         }
                     }
                 }
