@@ -230,6 +230,35 @@ toi_status fitrig_strongest_map(toi_ctx* ctx, const float* cube, int32_t n_maps,
 toi_status toi_image_batch(toi_ctx* ctx, const toi_snapshot* snaps, int32_t n,
                            float* images_out, float* tlisi_out);
 
+/* Input slots for a stream of batches (the ring of device buffers behind
+ * Section 4.1's pipeline): n context-owned sets of snapshot arrays in the
+ * layouts above, each sized for n_row_max rows (uvw, vis, freq, ant1, ant2,
+ * and flag / weight / gains when `arrays` has TOI_INPUT_FLAG /
+ * TOI_INPUT_WEIGHT / TOI_INPUT_GAINS; gains need n_ant > 0).  descs_out[i]
+ * (caller-owned host array of n) receives slot i's device pointers with
+ * n_row = n_row_max.  The slots are allocated on the first call and kept by
+ * the context; a later call with n no larger and the same `arrays` returns
+ * the same pointers, otherwise the slots are freed (after the context's
+ * stream drains) and reallocated, and earlier descriptors become invalid.
+ * Filling the slots (toi_batch_fill, or any copy or kernel ordered before the
+ * batch on the context's stream) and passing the same descriptors, outputs
+ * and n to toi_image_batch each time replays the captured graph: a stream of
+ * new data costs no new capture (a changed n_row in a descriptor does).
+ * TOI_ENOMEM if the slots cannot be allocated. */
+#define TOI_INPUT_FLAG 1u
+#define TOI_INPUT_WEIGHT 2u
+#define TOI_INPUT_GAINS 4u
+toi_status toi_batch_inputs(toi_ctx* ctx, int32_t n, uint32_t arrays, toi_snapshot* descs_out);
+
+/* Copy one snapshot (src: device or page-locked host arrays, n_row <= n_row_max,
+ * the same optional arrays as the slots) into input slot `slot` of
+ * toi_batch_inputs, asynchronously on the context's stream (rows beyond
+ * src->n_row are left as they were). */
+toi_status toi_batch_fill(toi_ctx* ctx, int32_t slot, const toi_snapshot* src);
+
+/* Diagnostics: graphs captured and launched by toi_image_batch so far on ctx. */
+toi_status toi_batch_info(toi_ctx* ctx, int64_t* captures, int64_t* launches);
+
 /* Streaming ingest (the paper's host pipeline, Section 4: data read and
  * copied to the device while the GPU images): host_snaps holds n snapshot
  * descriptors whose arrays are HOST pointers, in the layouts above.  For each

@@ -95,7 +95,7 @@ StageTimer::~StageTimer() {
     if (slot >= 0) (void)hipEventRecord(c->prof_ev[2 * slot + 1], c->stream);
 }
 
-void front_bytes(const toi_ctx* c, size_t out[14]) {
+void front_bytes(const toi_ctx* c, size_t out[kFrontBuffers]) {
     const toi_params& p = c->p;
     const size_t NT = c->NT, NG = c->NG_max, words = (NT + 31) / 32;
     out[0] = sizeof(DevPlan);
@@ -224,7 +224,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
     // (about 5 entries per item at 4096 channels over 856-1712 MHz, some 60-100
     // at 512 channels over the same band on a 8192^2 grid)
     c->bin_cap = p.bin_cap > 0 ? p.bin_cap : c->n_items_max * 128 + 65536;
-    size_t fb[14];
+    size_t fb[kFrontBuffers];
     front_bytes(c, fb);
     struct Alloc { void** ptr; size_t bytes; };
     Alloc allocs[] = {
@@ -300,6 +300,7 @@ toi_status toi_destroy(toi_ctx* c) {
     if (!c) return TOI_OK;
     (void)hipStreamSynchronize(c->stream);
     ingest_release(c);
+    ring_release(c);
     for (auto& e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -318,7 +319,7 @@ toi_status toi_destroy(toi_ctx* c) {
     void* ptrs[] = {c->items, c->recs, c->gx, c->bin_order, c->bin_aux, c->units, c->split_part,
                     c->bin_count, c->bin_off, c->bin_cursor, c->bin_list, c->tile_bits, c->row_bits,
                     c->adj_tp, c->item_gain, c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
-                    c->scratch_d, c->scratch_i, c->det_scores, c->det_boxes, c->batch_desc};
+                    c->scratch_d, c->scratch_i, c->det_scores, c->det_boxes};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete c;

@@ -139,7 +139,7 @@ struct TileStat {         // FITrig per-tile sums (FP64)
 // Per-snapshot state written by sample prep and binning and read by the
 // gridder and the FFT passes.  The context holds one set in its own fields;
 // batched execution adds a second (toi_ctx::alt) so that the prep and binning
-// of snapshot i + 1 can run while snapshot i is transformed.
+// of snapshot i + 1 can run while snapshot i is gridded and transformed.
 struct toi_front {
     toi::DevPlan* plan;
     toi::RowStat* rows;
@@ -214,7 +214,8 @@ struct toi_ctx {
     uint64_t batch_key;
     int batch_n;
     hipStream_t cap_stream;   // internal stream the batch is captured on (default priority)
-    void* batch_desc;
+    struct toi_batch_ring* ring;   // context-owned input slots (toi_batch_inputs), or null
+    int64_t batch_captures, batch_launches;
     hipStream_t cap_stream2;  // second capture stream: prep and binning of the next snapshot
     hipEvent_t batch_ev[4];   // capture-time fork/join and ordering events
     toi_front alt;            // second per-snapshot set (allocated on the first batch of >= 2)
@@ -268,10 +269,13 @@ inline int unit_workgroups(int n_items, int n_bins) {
 
 // streaming ingest state (toi_ingest.cpp), released by toi_destroy
 void ingest_release(toi_ctx* ctx);
+// batch input slots (toi_batch.cpp), released by toi_destroy
+void ring_release(toi_ctx* ctx);
 
 // Byte sizes of the per-snapshot set's buffers (same order as toi_front's
 // fields), and the swap of the context's set with ctx->alt (toi_ctx.cpp).
-void front_bytes(const toi_ctx* ctx, size_t out[14]);
+constexpr int kFrontBuffers = 14;
+void front_bytes(const toi_ctx* ctx, size_t out[kFrontBuffers]);
 void front_swap(toi_ctx* ctx);
 
 // host-side tables (toi_ctx.cpp)

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libtoi.so")
 
 TOI_OK, TOI_EINVAL, TOI_ENOMEM, TOI_EDEVICE, TOI_EUNSUPPORTED = range(5)
 STATUS_NO_SAMPLES, STATUS_DEGENERATE, STATUS_PLANES, STATUS_OVERFLOW = 1, 2, 4, 8
+INPUT_FLAG, INPUT_WEIGHT, INPUT_GAINS = 1, 2, 4
 
 
 class ToiError(RuntimeError):
@@ -73,6 +74,11 @@ _SIGS = {
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "toi_ingest": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Snapshot), ctypes.c_int32,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "toi_batch_inputs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
+                                        ctypes.POINTER(Snapshot)]),
+    "toi_batch_fill": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Snapshot)]),
+    "toi_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64)]),
     "toi_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -287,6 +293,33 @@ class Imager:
         self._gen += 1
         _check(lib().toi_image_batch(self.ctx, arr, len(snaps), _ptr(images_out), _ptr(tlisi_out)),
                self.ctx)
+
+    def batch_inputs(self, n: int, flags=False, weights=False, gains=False):
+        """Reserve n context-owned input slots (toi_batch_inputs); returns their
+        descriptors (kept by the Imager for image_batch_slots)."""
+        arrays = (INPUT_FLAG if flags else 0) | (INPUT_WEIGHT if weights else 0) | (INPUT_GAINS if gains else 0)
+        arr = (Snapshot * n)()
+        _check(lib().toi_batch_inputs(self.ctx, n, arrays, arr), self.ctx)
+        self._slots = arr
+        return arr
+
+    def batch_fill(self, slot: int, snap: dict):
+        """Copy a device snapshot into input slot `slot` on torch's current stream."""
+        s = snapshot_struct(snap)
+        self._sync_stream()
+        _check(lib().toi_batch_fill(self.ctx, slot, ctypes.byref(s)), self.ctx)
+
+    def image_batch_slots(self, n: int, images_out, tlisi_out=None):
+        """toi_image_batch on the first n input slots (the same descriptors each call)."""
+        self._sync_stream()
+        self._gen += 1
+        _check(lib().toi_image_batch(self.ctx, self._slots, n, _ptr(images_out), _ptr(tlisi_out)), self.ctx)
+
+    def batch_info(self):
+        """(graphs captured, graphs launched) by toi_image_batch on this context."""
+        cap, lau = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().toi_batch_info(self.ctx, ctypes.byref(cap), ctypes.byref(lau)), self.ctx)
+        return cap.value, lau.value
 
     def ingest(self, host_snaps, images_out, tlisi_out=None):
         """Image snapshots held in host memory, copies overlapped with the imaging."""

@@ -55,7 +55,9 @@ def test_argument_validation_without_device(lib):
                      ("toi_ingest", (None, None, 1, None, None)),
                      ("fitrig_detect_cube", (None, None, 16, 0, None, 0, None)),
                      ("fitrig_localise", (None, None, None, None, 1, 0.0, 0.0, 1, None)),
-                     ("fitrig_strongest_map", (None, None, 4, None, 1, None))):
+                     ("fitrig_strongest_map", (None, None, 4, None, 1, None)),
+                     ("toi_batch_inputs", (None, 1, 0, None)), ("toi_batch_fill", (None, 0, None)),
+                     ("toi_batch_info", (None, None, None))):
         code = getattr(lib, fn)(*args)
         assert code == (T.TOI_OK if fn == "toi_destroy" else T.TOI_EINVAL), fn
 

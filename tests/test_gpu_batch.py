@@ -81,3 +81,40 @@ def test_batched_lengths_match_eager(n):
     torch.cuda.synchronize()
     assert (again - eager[0]).abs().max().item() / eager[0].abs().max().item() < 1e-5
     im.close()
+
+
+def test_input_slots_replay_without_recapture():
+    """A stream of batches through the context's input slots (toi_batch_inputs /
+    toi_batch_fill): new data every call, the same descriptors, one capture;
+    every batch equals the eager images of the data it was filled with."""
+    import torch
+    from paper_2512_06254_amd import toi as T
+    wl = S.scaled(S.WORKLOADS["batched"], n_ant=9, n_chan=40, n_pix=64, n_steady=4, cell_arcsec=60.0,
+                  diameter_m=1500.0, n_snap=12)
+    sky, enu = S.make_sky(wl), S.antenna_enu(wl)
+    n, N, TT = 4, wl.n_pix, wl.n_pix // 32
+    im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=1, cheb_k=8, tile=32)
+    im.batch_inputs(n, flags=True)
+    imgs = torch.zeros((n, N, N), device="cuda")
+    tls = torch.zeros((n - 2, TT, TT), device="cuda")
+    for call in range(3):
+        dev = [T.to_device(S.make_snapshot(wl, call * n + t, sky=sky, enu=enu)) for t in range(n)]
+        eager = []
+        for d in dev:
+            im.grid(d)
+            eager.append(im.image().clone())
+        eager_tl = [im.tlisi(eager[i - 2], eager[i - 1], eager[i]).clone() for i in range(2, n)]
+        for t, d in enumerate(dev):
+            im.batch_fill(t, d)
+        imgs.zero_()
+        im.image_batch_slots(n, imgs, tls)
+        torch.cuda.synchronize()
+        for i in range(n):
+            peak = eager[i].abs().max().item()
+            assert (imgs[i] - eager[i]).abs().max().item() / peak < 1e-5, (call, i)
+        for i in range(n - 2):
+            assert (tls[i] - eager_tl[i]).abs().max().item() < 1e-5, (call, i)
+    captures, launches = im.batch_info()
+    print(f"[batch slots] captures {captures}, launches {launches}", flush=True)
+    assert (captures, launches) == (1, 3)
+    im.close()
