@@ -242,12 +242,13 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
         {(void**)&c->tile_bits, fb[11]},
         {(void**)&c->row_bits, fb[12]},
         {(void**)&c->scratch_i, fb[13]},
-        {(void**)&c->gx, std::max<size_t>(1, (size_t)p.n_row_max * p.n_chan) * sizeof(float2)},
+        {(void**)&c->gx, std::max<size_t>(1, (size_t)p.n_row_max * p.n_chan) * 2 * sizeof(uint64_t)},
         {(void**)&c->split_part, (size_t)kSplitSlots * kPartFloats * sizeof(float)},
         {(void**)&c->grid, P * M * M * sizeof(float2)},
         {(void**)&c->hbuf, P * N * M * sizeof(float2)},
         {(void**)&c->tplane_t, N * N * sizeof(float)},
-        {(void**)&c->adj_tp, N * N * sizeof(float)},
+        {(void**)&c->adj_tp, N * N * sizeof(uint64_t)},
+        {(void**)&c->adj_parts, std::max<size_t>(kAdjAbsmaxParts, M / 2 * P) * sizeof(float)},
         {(void**)&c->item_gain, (size_t)c->n_items_max * sizeof(double2)},
         {(void**)&c->corr, N * sizeof(float)},
         {(void**)&c->twiddle, (size_t)fft_twiddle_entries((int)M) * sizeof(float2)},
@@ -318,7 +319,7 @@ toi_status toi_destroy(toi_ctx* c) {
     if (c->batch_graph) (void)hipGraphDestroy(c->batch_graph);
     void* ptrs[] = {c->items, c->recs, c->gx, c->bin_order, c->bin_aux, c->units, c->split_part,
                     c->bin_count, c->bin_off, c->bin_cursor, c->bin_list, c->tile_bits, c->row_bits,
-                    c->adj_tp, c->item_gain, c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
+                    c->adj_tp, c->adj_parts, c->item_gain, c->grid, c->hbuf, c->tplane_t, c->plan, c->rows, c->corr, c->twiddle, c->tiles,
                     c->scratch_d, c->scratch_i, c->det_scores, c->det_boxes};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);

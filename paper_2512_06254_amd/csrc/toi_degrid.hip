@@ -15,6 +15,13 @@
 //   5. visibilities: grad V_k = conj(g_a1 conj(g_a2)) W_k (1 - F_k) grad x;
 //      gains: per work item sum_c conj(y_c) grad x_c (y = pre-gain weighted
 //      sum), reduced per antenna in FP64 in a fixed order.
+// The two scatter steps (1 and 4) add into their targets with 64-bit integer
+// atomics on fixed-point values: each sum gets a power-of-two scale from the
+// largest magnitude that can reach it (the image gradient's for step 1, the
+// plane gradients' for step 4, both measured on the device), so that no sum
+// exceeds 2^61, and integer addition makes the result independent of the
+// order in which the waves arrive: the gradients are bitwise repeatable.
+// The resolution is 2^-51 of the bound, far below FP32 rounding.
 // The grid and row-pass workspaces are reused, so toi_grid must run again
 // before the next toi_image.
 #include <algorithm>
@@ -31,6 +38,45 @@ __global__ __launch_bounds__(256) void k_zero_f32(float* __restrict__ p, size_t 
         p[i] = 0.f;
 }
 
+// Fixed-point sums: value v adds rint(v S) to a 64-bit integer; S = 2^(61 - e)
+// where the bound b (largest magnitude times the most terms that can meet in
+// one sum) is f 2^e, f in [0.5, 1), so every sum stays below 2^61.
+__device__ inline unsigned long long to_fixed(float v, double S) {
+    return (unsigned long long)(long long)rint((double)v * S);
+}
+__device__ inline float from_fixed(unsigned long long q, double inv_S) {
+    return (float)((double)(long long)q * inv_S);
+}
+// Per-workgroup largest |x| of n floats (parts[blockIdx.x]).
+__global__ __launch_bounds__(256) void k_absmax_parts(const float* __restrict__ x, size_t n, float* __restrict__ parts) {
+    __shared__ float red[4];
+    float m = 0.f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(x[i]));
+    m = block_max(m, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = m;
+}
+// scale[0] = S, scale[1] = 1 / S for the bound mult * max(parts).
+__global__ __launch_bounds__(1024) void k_fixed_scale(const float* __restrict__ parts, int n, double mult,
+                                                     double* __restrict__ scale) {
+    __shared__ float red[16];
+    float m = 0.f;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, parts[i]);
+    m = block_max(m, red);
+    if (threadIdx.x == 0) {
+        int e = 0;
+        if (m > 0.f) (void)frexp((double)m * mult, &e);
+        e = max(-900, min(900, e));
+        scale[0] = ldexp(1.0, 61 - e);
+        scale[1] = ldexp(1.0, e - 61);
+    }
+}
+// Most output pixels whose bilinear stencils can meet in one transformed-plane
+// pixel, and most (tile, order) terms of one sample's gradient (4 tiles x 64
+// cells x 32 orders), as bounds of the fixed-point sums (generous: the
+// resolution stays far below FP32 rounding).
+constexpr double kRaMaxTerms = 1024.0, kDegridMaxTerms = 8192.0;
+
 // 1. transpose of the bilinear re-projection (t-plane gradient, j1-major).
 // A workgroup takes 16 x 16 output pixels; their bilinear sources cover a
 // small box of the t-plane, which is accumulated in LDS and then added to HBM
@@ -38,11 +84,14 @@ __global__ __launch_bounds__(256) void k_zero_f32(float* __restrict__ p, size_t 
 // than kRaBox x kRaBox (an extreme stretch of the map) falls back to direct
 // global atomics.
 constexpr int kRaTile = 16, kRaBox = 48;
-__global__ __launch_bounds__(256) void k_reproject_adj(const float* __restrict__ gimg, float* __restrict__ gtp,
-                                                       const DevPlan* __restrict__ plan, int N, double cell_rad) {
-    __shared__ float box[kRaBox * kRaBox];
+__global__ __launch_bounds__(256) void k_reproject_adj(const float* __restrict__ gimg,
+                                                       unsigned long long* __restrict__ gtp,
+                                                       const DevPlan* __restrict__ plan, int N, double cell_rad,
+                                                       const double* __restrict__ scale) {
+    __shared__ unsigned long long box[kRaBox * kRaBox];
     __shared__ int red[4][4];
     if (plan->status & kStatusFatal) return;
+    const double S = scale[0];
     const int j1 = blockIdx.x * kRaTile + (threadIdx.x & (kRaTile - 1));
     const int j2 = blockIdx.y * kRaTile + (threadIdx.x / kRaTile);
     int i1 = 0, i2 = 0;
@@ -66,29 +115,29 @@ __global__ __launch_bounds__(256) void k_reproject_adj(const float* __restrict__
     const float a01 = (1.f - f1) * f2 * y, a11 = f1 * f2 * y;
     if (w1 > kRaBox || w2 > kRaBox) {                       // uniform fallback
         if (ok) {
-            float* c0 = gtp + (size_t)i1 * N + i2;
-            float* c1 = c0 + N;
-            unsafeAtomicAdd(c0, a00);
-            unsafeAtomicAdd(c1, a10);
-            unsafeAtomicAdd(c0 + 1, a01);
-            unsafeAtomicAdd(c1 + 1, a11);
+            unsigned long long* c0 = gtp + (size_t)i1 * N + i2;
+            unsigned long long* c1 = c0 + N;
+            atomicAdd(c0, to_fixed(a00, S));
+            atomicAdd(c1, to_fixed(a10, S));
+            atomicAdd(c0 + 1, to_fixed(a01, S));
+            atomicAdd(c1 + 1, to_fixed(a11, S));
         }
         return;
     }
-    for (int e = threadIdx.x; e < w1 * kRaBox; e += blockDim.x) box[e] = 0.f;
+    for (int e = threadIdx.x; e < w1 * kRaBox; e += blockDim.x) box[e] = 0ull;
     __syncthreads();
     if (ok) {
-        float* b0 = box + (i1 - lo1) * kRaBox + (i2 - lo2);
-        atomicAdd(b0, a00);
-        atomicAdd(b0 + kRaBox, a10);
-        atomicAdd(b0 + 1, a01);
-        atomicAdd(b0 + kRaBox + 1, a11);
+        unsigned long long* b0 = box + (i1 - lo1) * kRaBox + (i2 - lo2);
+        atomicAdd(b0, to_fixed(a00, S));
+        atomicAdd(b0 + kRaBox, to_fixed(a10, S));
+        atomicAdd(b0 + 1, to_fixed(a01, S));
+        atomicAdd(b0 + kRaBox + 1, to_fixed(a11, S));
     }
     __syncthreads();
     for (int e = threadIdx.x; e < w1 * w2; e += blockDim.x) {
         const int d1 = e / w2, d2 = e % w2;
-        const float v = box[d1 * kRaBox + d2];
-        if (v != 0.f) unsafeAtomicAdd(gtp + (size_t)(lo1 + d1) * N + lo2 + d2, v);
+        const unsigned long long v = box[d1 * kRaBox + d2];
+        if (v != 0ull) atomicAdd(gtp + (size_t)(lo1 + d1) * N + lo2 + d2, v);
     }
 }
 
@@ -110,10 +159,12 @@ __device__ inline double miller_norm(double alpha, int L) {
 
 // 2. column pass of the adjoint
 template <int M, int E>
-__global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_cols(const float* __restrict__ gtp, float2* __restrict__ gh,
+__global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_cols(const unsigned long long* __restrict__ gtp,
+                                                       float2* __restrict__ gh,
                                                        const float2* __restrict__ tw, const float* __restrict__ corr,
                                                        const DevPlan* __restrict__ plan, float cell_rad, int mode,
-                                                       const uint32_t* __restrict__ row_bits) {
+                                                       const uint32_t* __restrict__ row_bits,
+                                                       const double* __restrict__ scale) {
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
     constexpr int T = M / E;
@@ -127,10 +178,11 @@ __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_cols(cons
     int j2[KEEP];
     float y[KEEP];
     const float c1 = corr[j1] * (float)plan->norm;
+    const double inv_S = scale[1];
 #pragma unroll
     for (int q = 0; q < KEEP; ++q) {
         j2[q] = fft_kept_index<M, E>(q);
-        y[q] = gtp[(size_t)j1 * N + j2[q]] * c1 * corr[j2[q]];
+        y[q] = from_fixed(gtp[(size_t)j1 * N + j2[q]], inv_S) * c1 * corr[j2[q]];
     }
     // per-pixel geometry (FP64 here: the adjoint runs once per backward pass)
     // ia: 1 / alpha (0 where |alpha| < 1e-3: the power series, from af = alpha);
@@ -257,12 +309,16 @@ __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_cols(cons
 
 // 3. row pass of the adjoint (rows of tile rows that hold samples; only the
 // tiles that hold samples are written, the only ones the gather reads)
+// Each workgroup also records the largest magnitude it writes in
+// gmax_parts[blockIdx.x] (0 when it writes nothing), for the degridder's
+// fixed-point scale.
 template <int M, int E, int B>
 __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_rows(const float2* __restrict__ gh, float2* __restrict__ gg,
                                                        const float2* __restrict__ tw,
                                                        const DevPlan* __restrict__ plan, int nbands,
                                                        const uint32_t* __restrict__ tile_bits,
-                                                       const uint32_t* __restrict__ row_bits) {
+                                                       const uint32_t* __restrict__ row_bits,
+                                                       float* __restrict__ gmax_parts) {
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
     constexpr int T = M / E;
@@ -270,12 +326,19 @@ __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_rows(cons
     __shared__ float2 lds[fft_lds_size<M, E>()];
     __shared__ float2 tw_s[FftTw<M, E>::size()];
     __shared__ uint32_t tb[WORDS];
+    __shared__ float red[16];
     const int id = xcd_block_id(blockIdx.x, gridDim.x);
     const int plane = id / nbands, band = id % nbands;
-    if ((plan->status & kStatusFatal) || plane >= plan->planes) return;
+    if ((plan->status & kStatusFatal) || plane >= plan->planes) {
+        if (threadIdx.x == 0) gmax_parts[blockIdx.x] = 0.f;
+        return;
+    }
     const int g = group_of_plane(plane, plan);
     const int ty = (band * B) / kTile;
-    if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) return;
+    if (!((row_bits[g * WORDS + (ty >> 5)] >> (ty & 31)) & 1u)) {
+        if (threadIdx.x == 0) gmax_parts[blockIdx.x] = 0.f;
+        return;
+    }
     if (threadIdx.x < WORDS) tb[threadIdx.x] = tile_bits[((size_t)g * NT + ty) * WORDS + threadIdx.x];
     load_twiddles<M, E>(tw_s, tw);   // its barrier also publishes tb
     // output element r of this thread is column x = t + r T: written only
@@ -287,6 +350,7 @@ __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_rows(cons
         const int x = threadIdx.x + r * T;
         if ((tb[x >> (kTileShift + 5)] >> ((x >> kTileShift) & 31)) & 1u) wbits |= 1u << r;
     }
+    float vmax = 0.f;
     float2 in[B][KEEP];
 #pragma unroll
     for (int q = 0; q < KEEP; ++q) {
@@ -318,8 +382,13 @@ __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_rows(cons
         float2* dst = gg + ((size_t)plane * M + band * B + rb) * M;
 #pragma unroll
         for (int r = 0; r < E; ++r)
-            if ((wbits >> r) & 1u) dst[threadIdx.x + r * T] = make_float2(v[r].x, -v[r].y);
+            if ((wbits >> r) & 1u) {
+                dst[threadIdx.x + r * T] = make_float2(v[r].x, -v[r].y);
+                vmax = fmaxf(vmax, fmaxf(fabsf(v[r].x), fabsf(v[r].y)));
+            }
     }
+    vmax = block_max(vmax, red);
+    if (threadIdx.x == 0) gmax_parts[blockIdx.x] = vmax;
 }
 
 // 4. Gather degridding on the matrix cores, the transpose of the tile
@@ -337,7 +406,7 @@ __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_rows(cons
 // column l mod 32 of rows (r mod 4) + 8 (r / 4) + 4 (l / 32) (hardware
 // layout), multiplies by T and a DPP reduction over each 16-lane row sums the
 // orders; the row's last lane adds the result to the sample's gradient
-// (global float atomics: a sample meets 3.5 tiles on average).
+// (fixed-point 64-bit atomics: a sample meets 3.5 tiles on average).
 __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict__ recs, int n_chan,
                                                      const DevPlan* __restrict__ P, int M, int NT,
                                                      const int32_t* __restrict__ bin_off,
@@ -345,7 +414,9 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                                                      const int32_t* __restrict__ order,
                                                      const int32_t* __restrict__ cnt,
                                                      const int4* __restrict__ units,
-                                                     const float2* __restrict__ gg, float* __restrict__ gx) {
+                                                     const float2* __restrict__ gg,
+                                                     unsigned long long* __restrict__ gx,
+                                                     const double* __restrict__ scale) {
     typedef float v16 __attribute__((ext_vector_type(16)));
     typedef bf16x8_t bf16x8;
     __shared__ float sw[64 * 16];      // compacted samples: weights at tile columns 0..7, rows 0..7
@@ -356,6 +427,7 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
     if (P->status & kStatusFatal) return;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & 31, pl = col & 15, half = lane >> 5;
+    const double S = scale[0];
     // the forward's work units (heavy bins split), heaviest first; normally
     // one per workgroup, handed out by the dispatcher as waves finish
     const int n_units = work_unit_count(cnt);
@@ -467,7 +539,7 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                     v = dpp_add<0x112, 0xf>(v);
                     v = dpp_add<0x114, 0xf>(v);
                     v = dpp_add<0x118, 0xf>(v);             // lane 15 of each 16-lane row: the sum over the orders
-                    if (ok && (lane & 15) == 15) unsafeAtomicAdd(gx + 2 * sidx[q] + (col >> 4), v);
+                    if (ok && (lane & 15) == 15) atomicAdd(gx + 2 * sidx[q] + (col >> 4), to_fixed(v, S));
                 }
             }
             lds_order();                                   // the reads above precede the next staging writes
@@ -483,7 +555,8 @@ __global__ __launch_bounds__(256) void k_degrid_finish(const float2* __restrict_
                                                        const uint8_t* __restrict__ flag, const int32_t* __restrict__ ant1,
                                                        const int32_t* __restrict__ ant2, const float2* __restrict__ gains,
                                                        int n_ant, int n_chan, int n_corr, uint32_t mask, int n_items,
-                                                       const float2* __restrict__ gxv, float2* __restrict__ grad_vis,
+                                                       const unsigned long long* __restrict__ gxv,
+                                                       const double* __restrict__ scale, float2* __restrict__ grad_vis,
                                                        double2* __restrict__ item_gain) {
     const int lane = threadIdx.x & 63;
     const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -496,9 +569,9 @@ __global__ __launch_bounds__(256) void k_degrid_finish(const float2* __restrict_
     float yr = 0.f, yi = 0.f, gxr = 0.f, gxi = 0.f;
     if (live) {
         (void)sample_value(vis, weight, flag, base, n_corr, mask, yr, yi);
-        const float2 g = gxv[(size_t)r * n_chan + c];
-        gxr = g.x;
-        gxi = g.y;
+        const size_t smp = (size_t)r * n_chan + c;
+        gxr = from_fixed(gxv[2 * smp], scale[1]);
+        gxi = from_fixed(gxv[2 * smp + 1], scale[1]);
     }
     // visibility gradients: conj(g_row) W_k (1 - F_k) grad x on the selected correlations
     const float2 gr = row_gain(gains, ant1, ant2, n_ant, r);
@@ -555,11 +628,15 @@ template <int M, int E, int EC>   // row-pass and column-pass radices
 static void launch_adj_ffts(toi_ctx* c) {
     constexpr int B = (M >= 8192) ? 2 : 4;
     const float cell = (float)(c->p.cell_deg * kPi / 180.0);
-    hipLaunchKernelGGL((k_adj_cols<M, EC>), dim3(M / 2), dim3(M / EC), 0, c->stream, c->adj_tp, c->hbuf, c->twiddle,
-                       c->corr, c->plan, cell, c->p.mode, c->row_bits);
+    hipLaunchKernelGGL((k_adj_cols<M, EC>), dim3(M / 2), dim3(M / EC), 0, c->stream,
+                       reinterpret_cast<const unsigned long long*>(c->adj_tp), c->hbuf, c->twiddle, c->corr, c->plan,
+                       cell, c->p.mode, c->row_bits, c->scratch_d);
     const int nbands = M / B;
     hipLaunchKernelGGL((k_adj_rows<M, E, B>), dim3(nbands * c->P_cap), dim3(M / E), 0, c->stream, c->hbuf, c->grid,
-                       c->twiddle, c->plan, nbands, c->tile_bits, c->row_bits);
+                       c->twiddle, c->plan, nbands, c->tile_bits, c->row_bits, c->adj_parts);
+    // the degridder's fixed-point scale from the plane gradients written
+    hipLaunchKernelGGL(k_fixed_scale, dim3(1), dim3(1024), 0, c->stream, c->adj_parts, nbands * c->P_cap,
+                       kDegridMaxTerms, c->scratch_d + 2);
 }
 
 hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot& s, float2* grad_vis,
@@ -568,9 +645,16 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
     StageTimer timer(c, TOI_STAGE_DEGRID);
     const int N = c->N, M = c->M;
     const double cell = p.cell_deg * kPi / 180.0;
-    hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->adj_tp, (size_t)N * N);
+    // transformed-plane gradient as fixed point (2 x 32 bits per pixel), its
+    // scale from the largest image gradient
+    hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, c->adj_tp, 2 * (size_t)N * N);
+    hipLaunchKernelGGL(k_absmax_parts, dim3(kAdjAbsmaxParts), dim3(256), 0, c->stream, grad_image, (size_t)N * N,
+                       c->adj_parts);
+    hipLaunchKernelGGL(k_fixed_scale, dim3(1), dim3(1024), 0, c->stream, c->adj_parts, kAdjAbsmaxParts, kRaMaxTerms,
+                       c->scratch_d);
     hipLaunchKernelGGL(k_reproject_adj, dim3((N + kRaTile - 1) / kRaTile, (N + kRaTile - 1) / kRaTile), dim3(256), 0,
-                       c->stream, grad_image, c->adj_tp, c->plan, N, cell);
+                       c->stream, grad_image, reinterpret_cast<unsigned long long*>(c->adj_tp), c->plan, N, cell,
+                       c->scratch_d);
     switch (M) {
         case 64: launch_adj_ffts<64, 8, 8>(c); break;
         case 128: launch_adj_ffts<128, 8, 8>(c); break;
@@ -588,14 +672,16 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
         const int NT = c->NT;
         const size_t n_samp = (size_t)s.n_row * p.n_chan;
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, reinterpret_cast<float*>(c->gx),
-                           2 * n_samp);
+                           4 * n_samp);
         const int blocks = unit_workgroups(n_items, c->NG_max * NT * NT);
         hipLaunchKernelGGL(k_degrid_tiles, dim3(blocks), dim3(64), 0,
                            c->stream, c->recs, p.n_chan, c->plan, M, NT, c->bin_off, c->bin_list, c->bin_cap,
-                           c->bin_order, c->scratch_i, c->units, c->grid, reinterpret_cast<float*>(c->gx));
+                           c->bin_order, c->scratch_i, c->units, c->grid,
+                           reinterpret_cast<unsigned long long*>(c->gx), c->scratch_d + 2);
         hipLaunchKernelGGL(k_degrid_finish, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, (const float2*)s.vis,
                            s.weight, s.flag, s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr,
-                           p.corr_mask, n_items, c->gx, grad_vis, grad_gains ? c->item_gain : nullptr);
+                           p.corr_mask, n_items, reinterpret_cast<const unsigned long long*>(c->gx), c->scratch_d + 2,
+                           grad_vis, grad_gains ? c->item_gain : nullptr);
     }
     if (grad_gains)
         hipLaunchKernelGGL(k_gain_grad, dim3(p.n_ant), dim3(256), 0, c->stream, c->item_gain, n_items, n_chunks,

@@ -67,6 +67,7 @@ constexpr int kAuxBuckets = 0, kAuxCursors = 32, kAuxUnits = 64, kAuxTotals = 96
 // workgroup in LDS up to kSortLds items, beyond that in place in HBM.
 constexpr int kSortShift = 6, kSortLds = 16384;
 constexpr int kPartFloats = 64 * 32;   // one partial tile: 64 cells x up to 16 complex planes
+constexpr int kAdjAbsmaxParts = 1024;  // workgroups of the adjoint's image-gradient maximum
 
 // Gridder variant chosen by the autotuner (toi_tune / toi_set_tuning):
 // bits 0-1: work-unit size U = 32 << bits items (split bins are gridded by one
@@ -174,7 +175,8 @@ struct toi_ctx {
     int n_items_max;      // work items capacity (n_row_max * chunks)
     toi::ItemBox* items;  // [n_items_max]
     toi::SampleRec* recs; // [n_row_max][n_chan] gridding records
-    float2* gx;           // [n_row_max][n_chan] adjoint: gradient of each sample's value
+    float2* gx;           // [n_row_max][n_chan][2] adjoint: gradient of each sample's value (Re, Im as
+                          // 64-bit fixed point; 16 bytes per sample)
     int32_t* bin_count;   // [NG_max][NT*NT]
     int32_t* bin_off;     // [NG_max][NT*NT + 1]
     int32_t* bin_cursor;  // [NG_max][NT*NT]
@@ -190,7 +192,9 @@ struct toi_ctx {
     float2* hbuf;         // [P_cap][N/4][M][4] row-pass output: column major per plane in groups of 4 columns
                           // (the adjoint uses it as [P_cap][N][M])
     float* tplane_t;      // [N][N]          transformed-plane image, j1 major
-    float* adj_tp;        // [N][N]          adjoint: transformed-plane gradient, j1 major
+    float* adj_tp;        // [N][N]          adjoint: transformed-plane gradient, j1 major, 64-bit fixed
+                          // point (8 bytes per pixel; the autotuner uses it as an f32 image)
+    float* adj_parts;     // adjoint: per-workgroup largest magnitudes for the fixed-point scales
     double2* item_gain;   // [n_items_max]   adjoint: per-item gain partial sums
     toi::DevPlan* plan;
     toi::RowStat* rows;   // [n_row_max]
