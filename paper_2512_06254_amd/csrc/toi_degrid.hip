@@ -394,19 +394,21 @@ __global__ __launch_bounds__(M / E, (M / E) <= 256 ? 2 : 1) void k_adj_rows(cons
 // 4. Gather degridding on the matrix cores, the transpose of the tile
 // gridder, over the forward's bins and gridding records (toi_grid of the same
 // snapshot).  One wavefront per 8 x 8 tile holds the tile's plane gradients G
-// (64 cells x 32 columns: the group's orders x Re/Im) as B operands of
-// v_mfma_f32_32x32x16_bf16, split as G = Gh + Gl in bf16 (chunk c covers
-// cells 16 c .. 16 c + 15; lane l holds G[16 c + 8 (l / 32) + e][l mod 32],
+// (64 cells x 32 columns: the group's orders x Re/Im) as A operands of
+// v_mfma_f32_32x32x16_f16, split as G sc = Gh + Gl in fp16 (sc a power of two
+// that puts the largest plane gradient below 2^13; chunk c covers cells
+// 16 c .. 16 c + 15, lane l holds G[16 c + 8 (l / 32) + e][l mod 32],
 // e = 0..7).  The samples an item has in the tile are compacted into LDS
 // (weights at the tile's 8 columns and 8 rows, T_k(s)); per batch of 32 of
-// them H = A G = sum over the chunks of Ah Gh + Ah Gl + Al Gh, A[q][cell] the
-// weight of sample q at the cell (from lane q mod 32, split the same way;
-// the bf16 matrix cores run beside the vector ALU).  Then
-// grad x_q += sum_k T_k(s_q) (H[q][k, Re] + i H[q][k, Im]): lane l holds
-// column l mod 32 of rows (r mod 4) + 8 (r / 4) + 4 (l / 32) (hardware
-// layout), multiplies by T and a DPP reduction over each 16-lane row sums the
-// orders; the row's last lane adds the result to the sample's gradient
-// (fixed-point 64-bit atomics: a sample meets 3.5 tiles on average).
+// them the B operands are the weights W[cell][q] (sample q from lane
+// q mod 32, products split the same way) and H^T = G^T W = sum over the
+// chunks of Gh Wh + Gh Wl + Gl Wh, so that lane l holds sample q = l mod 32
+// in all its registers (rows, i.e. columns of G: (r mod 4) + 8 (r / 4) +
+// 4 (l / 32), hardware layout).  Then grad x_q += sum_k T_k(s_q)
+// (H[q][k, Re] + i H[q][k, Im]): each lane sums its 8 orders in registers, one
+// exchange with lane l xor 32 adds the other 8, and the lane adds the result
+// to the sample's gradient (fixed-point 64-bit atomics: a sample meets 3.5
+// tiles on average).
 __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict__ recs, int n_chan,
                                                      const DevPlan* __restrict__ P, int M, int NT,
                                                      const int32_t* __restrict__ bin_off,
@@ -418,7 +420,6 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                                                      unsigned long long* __restrict__ gx,
                                                      const double* __restrict__ scale) {
     typedef float v16 __attribute__((ext_vector_type(16)));
-    typedef bf16x8_t bf16x8;
     __shared__ float sw[64 * 16];      // compacted samples: weights at tile columns 0..7, rows 0..7
     __shared__ float sT[64 * 16];      // T_{k0 + k}(s), zero for k >= nk
     __shared__ int sidx[64];           // sample index r * n_chan + c
@@ -427,7 +428,14 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
     if (P->status & kStatusFatal) return;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int col = lane & 31, pl = col & 15, half = lane >> 5;
-    const double S = scale[0];
+    // fp16 scale of the plane gradients: scale[1] = 2^(e - 61) with 2^e above
+    // 8192 times their largest magnitude, so sc = 2^(26 - e) keeps G sc below
+    // 2^13; the sums are scaled back inside the fixed-point conversion
+    int e_g;
+    (void)frexp(scale[1], &e_g);
+    e_g += 60;                                          // scale[1] = 0.5 2^(e - 60)
+    const float sc = ldexpf(1.f, max(-100, min(100, 26 - e_g)));
+    const double S = scale[0] / (double)sc;
     // the forward's work units (heavy bins split), heaviest first; normally
     // one per workgroup, handed out by the dispatcher as waves finish
     const int n_units = work_unit_count(cnt);
@@ -443,23 +451,24 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
         group_range(g, P, s0, s1, k0, k1);   // one slab per group
         const int nk = k1 - k0;
         const int tx = tile % NT, ty = tile / NT;
-        // the tile's plane gradients as B operands, split into bf16 hi + lo:
+        // the tile's plane gradients as A operands, split into fp16 hi + lo:
         // chunk c covers cells 16 c .. 16 c + 15, lane l elements e = 0..7 are
         // cells 16 c + 8 (l / 32) + e, i.e. tile row 2 c + l / 32, column e
-        bf16x8 gh[4], gl[4];
+        f16x8_t gh[4], gl[4];
 #pragma unroll
         for (int c4 = 0; c4 < 4; ++c4) {
-            float v[8];
+            float v[8], scv[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 v[e] = 0.f;
+                scv[e] = sc;
                 if (pl < nk) {
                     const float2 gv = gg[((size_t)(s0 * P->K + k0 + pl) * M + ty * kTile + 2 * c4 + half) * M +
                                          tx * kTile + e];
                     v[e] = col < 16 ? gv.x : gv.y;
                 }
             }
-            split_bf16x8(v, gh[c4], gl[c4]);
+            split_prod_f16x8(v, scv, gh[c4], gl[c4]);
         }
         for (int it = b0; it < b1; ++it) {
             const int item = list[it];
@@ -516,30 +525,33 @@ __global__ __launch_bounds__(64) void k_degrid_tiles(const SampleRec* __restrict
                 const float wy[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
                 v16 h = {};
 #pragma unroll
-                for (int c4 = 0; c4 < 4; ++c4) {            // A[q][cell] = w_x(column e) w_y(row 2 c + half)
-                    float a[8];
+                for (int c4 = 0; c4 < 4; ++c4) {            // W[cell][q] = w_x(column e) w_y(row 2 c + half)
+                    float wr8[8];
                     const float wr = oka ? wy[2 * c4 + half] : 0.f;
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) a[e] = wx[e] * wr;
-                    bf16x8 ah, al;
-                    split_bf16x8(a, ah, al);
-                    h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, gh[c4], h, 0, 0, 0);
-                    h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, gl[c4], h, 0, 0, 0);
-                    h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, gh[c4], h, 0, 0, 0);
+                    for (int e = 0; e < 8; ++e) wr8[e] = wr;
+                    f16x8_t ah, al;
+                    split_prod_f16x8(wx, wr8, ah, al);
+                    h = __builtin_amdgcn_mfma_f32_32x32x16_f16(gl[c4], ah, h, 0, 0, 0);
+                    h = __builtin_amdgcn_mfma_f32_32x32x16_f16(gh[c4], al, h, 0, 0, 0);
+                    h = __builtin_amdgcn_mfma_f32_32x32x16_f16(gh[c4], ah, h, 0, 0, 0);
                 }
+                // this lane's orders 4 half + 0..3 and 8 + 4 half + 0..3 of sample qa:
+                // registers r (Re) and r + 8 (Im), r < 8
+                const float4* tq = reinterpret_cast<const float4*>(sT + (oka ? qa : 0) * 16);
+                const float4 t0 = tq[half], t1 = tq[2 + half];
+                const float tk[8] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
+                float vr = 0.f, vi = 0.f;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    // registers 4 j .. 4 j + 3 hold rows 8 j .. 8 j + 7: none
-                    // past the last sample slot needs reducing (uniform branch)
-                    if (b + 8 * (r >> 2) >= n_act) break;
-                    const int q = b + (r & 3) + 8 * (r >> 2) + 4 * half;   // sample slot of this register's row
-                    const bool ok = q < n_act;
-                    float v = ok ? h[r] * sT[q * 16 + pl] : 0.f;
-                    v = dpp_add<0x111, 0xf>(v);
-                    v = dpp_add<0x112, 0xf>(v);
-                    v = dpp_add<0x114, 0xf>(v);
-                    v = dpp_add<0x118, 0xf>(v);             // lane 15 of each 16-lane row: the sum over the orders
-                    if (ok && (lane & 15) == 15) atomicAdd(gx + 2 * sidx[q] + (col >> 4), to_fixed(v, S));
+                for (int r = 0; r < 8; ++r) {
+                    vr += tk[r] * h[r];
+                    vi += tk[r] * h[r + 8];
+                }
+                vr += __shfl_xor(vr, 32, 64);
+                vi += __shfl_xor(vi, 32, 64);
+                if (oka && half == 0) {
+                    atomicAdd(gx + 2 * sidx[qa], to_fixed(vr, S));
+                    atomicAdd(gx + 2 * sidx[qa] + 1, to_fixed(vi, S));
                 }
             }
             lds_order();                                   // the reads above precede the next staging writes
