@@ -249,7 +249,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
         {(void**)&c->tplane_t, N * N * sizeof(float)},
         {(void**)&c->adj_tp, N * N * sizeof(uint64_t)},
         {(void**)&c->adj_parts, std::max<size_t>(kAdjAbsmaxParts, M / 2 * P) * sizeof(float)},
-        {(void**)&c->item_gain, (size_t)c->n_items_max * sizeof(double2)},
+        {(void**)&c->item_gain, ((size_t)c->n_items_max + std::max(1, p.n_row_max)) * sizeof(double2)},
         {(void**)&c->corr, N * sizeof(float)},
         {(void**)&c->twiddle, (size_t)fft_twiddle_entries((int)M) * sizeof(float2)},
         {(void**)&c->tiles, T * T * sizeof(TileStat)},

@@ -607,19 +607,36 @@ __global__ __launch_bounds__(256) void k_degrid_finish(const float2* __restrict_
     }
 }
 
-// grad g_a = sum_{rows with ant1 = a} g_ant2 S + sum_{rows with ant2 = a} g_ant1 conj(S), S per item
-__global__ __launch_bounds__(256) void k_gain_grad(const double2* __restrict__ item_gain, int n_items, int n_chunks,
+// Per-row sums of the items' gain partials (one wavefront per row, items in
+// order, a fixed butterfly over the lanes): row_gain[r] = sum_items S.
+__global__ __launch_bounds__(256) void k_row_gain(const double2* __restrict__ item_gain, int n_row, int n_chunks,
+                                                  double2* __restrict__ row_gain) {
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (r >= n_row) return;
+    double sr = 0.0, si = 0.0;
+    for (int c = lane; c < n_chunks; c += 64) {
+        const double2 S = item_gain[(size_t)r * n_chunks + c];
+        sr += S.x;
+        si += S.y;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) row_gain[r] = make_double2(sr, si);
+}
+
+// grad g_a = sum_{rows with ant1 = a} g_ant2 S + sum_{rows with ant2 = a} g_ant1 conj(S), S per row
+__global__ __launch_bounds__(256) void k_gain_grad(const double2* __restrict__ row_gain, int n_row,
                                                    const int32_t* __restrict__ ant1, const int32_t* __restrict__ ant2,
                                                    const float2* __restrict__ gains, int n_ant,
                                                    float2* __restrict__ grad_gains) {
     __shared__ double red[2][4];
     const int a = blockIdx.x;
     double sr = 0.0, si = 0.0;
-    for (int it = threadIdx.x; it < n_items; it += blockDim.x) {
-        const int r = it / n_chunks;
+    for (int r = threadIdx.x; r < n_row; r += blockDim.x) {
         const int a1 = ant1[r], a2 = ant2[r];
         if (a1 < 0 || a1 >= n_ant || a2 < 0 || a2 >= n_ant) continue;
-        const double2 S = item_gain[it];
+        const double2 S = row_gain[r];
         if (a1 == a) {
             const float2 g = gains[a2];
             sr += g.x * S.x - g.y * S.y;
@@ -695,9 +712,15 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
                            p.corr_mask, n_items, reinterpret_cast<const unsigned long long*>(c->gx), c->scratch_d + 2,
                            grad_vis, grad_gains ? c->item_gain : nullptr);
     }
-    if (grad_gains)
-        hipLaunchKernelGGL(k_gain_grad, dim3(p.n_ant), dim3(256), 0, c->stream, c->item_gain, n_items, n_chunks,
-                           s.ant1, s.ant2, (const float2*)s.gains, p.n_ant, grad_gains);
+    if (grad_gains) {
+        // per-row sums first (in the slots after the items' partials), then per antenna over the rows
+        double2* row_gain = c->item_gain + n_items;
+        if (s.n_row > 0)
+            hipLaunchKernelGGL(k_row_gain, dim3((s.n_row + 3) / 4), dim3(256), 0, c->stream, c->item_gain, s.n_row,
+                               n_chunks, row_gain);
+        hipLaunchKernelGGL(k_gain_grad, dim3(p.n_ant), dim3(256), 0, c->stream, row_gain, s.n_row, s.ant1, s.ant2,
+                           (const float2*)s.gains, p.n_ant, grad_gains);
+    }
     return hipGetLastError();
 }
 

@@ -195,7 +195,7 @@ struct toi_ctx {
     float* adj_tp;        // [N][N]          adjoint: transformed-plane gradient, j1 major, 64-bit fixed
                           // point (8 bytes per pixel; the autotuner uses it as an f32 image)
     float* adj_parts;     // adjoint: per-workgroup largest magnitudes for the fixed-point scales
-    double2* item_gain;   // [n_items_max]   adjoint: per-item gain partial sums
+    double2* item_gain;   // [n_items_max + n_row_max] adjoint: per-item, then per-row gain partial sums
     toi::DevPlan* plan;
     toi::RowStat* rows;   // [n_row_max]
     float* corr;          // [N]  (-1)^a / psi(a), a = j - N/2
