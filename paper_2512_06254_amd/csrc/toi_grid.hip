@@ -258,8 +258,10 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
                                                      uint32_t* __restrict__ row_bits,
                                                      const DevPlan* __restrict__ P) {
     __shared__ int32_t hist[32], start[32];
+    __shared__ uint32_t rbs[64];   // this workgroup's tile-row words of row_bits
     if (blockIdx.x * kScanBlock >= P->ng * NT * NT) return;   // unused plane groups: never read
     if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+    if (threadIdx.x < 64) rbs[threadIdx.x] = 0;
     __syncthreads();
     const int add = aux[kAuxTotals + blockIdx.x];
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
@@ -292,6 +294,13 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
     const int words = (NT + 31) / 32;
     const int row0 = (blockIdx.x * kScanBlock + NT - 1) / NT;
     const int row1 = min(n_bins, (blockIdx.x + 1) * kScanBlock + NT - 1) / NT;   // rows [row0, row1)
+    // The rows' row_bits words are gathered in LDS first and added with one
+    // global atomic per word: an atomic per non-empty tile word on a handful
+    // of shared words serialised the workgroups (33 us per snapshot).  The
+    // range spans at most 64 words: kScanBlock / NT <= 512 rows, 32 rows per
+    // word, or one word per plane group when NT < 32 (at most 64 groups).
+    static_assert(kScanBlock / 8 / 8 <= 64, "row words of one scan workgroup fit in rbs");
+    const int wbase = (row0 / NT) * words + ((row0 % NT) >> 5);
     // one word per half-wavefront: each lane tests one tile, a ballot packs them
     const int hw = (int)(threadIdx.x >> 5), hl = (int)(threadIdx.x & 31);
     for (int w = row0 * words + hw; w < row1 * words; w += blockDim.x >> 5) {
@@ -304,10 +313,12 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
             tile_bits[w] = bits;
             if (bits) {
                 const int g = row / NT, ty = row % NT;
-                atomicOr(&row_bits[g * words + (ty >> 5)], 1u << (ty & 31));
+                atomicOr(&rbs[g * words + (ty >> 5) - wbase], 1u << (ty & 31));
             }
         }
     }
+    __syncthreads();
+    if (threadIdx.x < 64 && rbs[threadIdx.x]) atomicOr(&row_bits[wbase + threadIdx.x], rbs[threadIdx.x]);
 }
 
 // Work units of the matrix-core passes (one workgroup).  The bins of the
