@@ -200,40 +200,43 @@ __device__ inline void item_row_tiles(const ItemBox& b, int ty, int nt, int& tx0
     tx1 = min(tx1, tx0 + nt - 1);
 }
 
-// Every (plane group, tile) bin of an item, spread over the 64 lanes of the
-// calling wavefront: f(g, ty, tx) is called once per bin (wrapped tile
-// indices).  Lane r first takes tile row ty0 + r and its tiles; a wave-wide
-// prefix sum of the per-row counts then deals the (row, tile, group) entries
-// round-robin over the lanes.  Items with more than 64 tile rows (long tracks
-// on large grids) take their rows in turn.  All lanes must call it.
-template <typename F>
+// Every (plane group, tile) bin of an item, spread over an aligned group of W
+// lanes of the calling wavefront (W = 64: the whole wavefront): f(g, ty, tx)
+// is called once per bin (wrapped tile indices).  Lane r of the group first
+// takes tile row ty0 + r and its tiles; a prefix sum of the per-row counts
+// over the group then deals the (row, tile, group) entries round-robin over
+// its lanes.  Items with more than W tile rows take their rows in turn.  All
+// lanes of the group must call it; other groups of the wavefront may serve
+// other items (the group's shuffles stay inside the group).
+template <int W = 64, typename F>
 __device__ inline void for_item_bins(const ItemBox& b, int NT, F f) {
-    const int lane = threadIdx.x & 63;
+    static_assert(W >= 2 && W <= 64 && (W & (W - 1)) == 0, "a power-of-two group of lanes");
+    const int lane = threadIdx.x & (W - 1);
     const int ny = b.ty1 - b.ty0 + 1, ng = b.g1 - b.g0 + 1;
     if (ny <= 0 || ng <= 0) return;
-    for (int r0 = 0; r0 < ny; r0 += 64) {
+    for (int r0 = 0; r0 < ny; r0 += W) {
         const int ty = b.ty0 + r0 + lane;
         int tx0 = 1, tx1 = 0;
         if (r0 + lane < ny) item_row_tiles(b, ty, NT, tx0, tx1);
         const int cnt = max(0, tx1 - tx0 + 1);
-        int incl = cnt;   // inclusive prefix sum over the lanes
+        int incl = cnt;   // inclusive prefix sum over the group's lanes
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int u = __shfl_up(incl, o, 64);
+        for (int o = 1; o < W; o <<= 1) {
+            const int u = __shfl_up(incl, o, W);
             if (lane >= o) incl += u;
         }
-        const int total = __shfl(incl, 63, 64);   // uniform: every lane runs every round
-        for (int e0 = 0; e0 < total * ng; e0 += 64) {
+        const int total = __shfl(incl, W - 1, W);   // uniform over the group: every lane runs every round
+        for (int e0 = 0; e0 < total * ng; e0 += W) {
             const int e = min(e0 + lane, total * ng - 1);
             const int ti = e % total, g = b.g0 + e / total;
             // the lane whose row holds tile entry ti: the first with incl > ti
             int lo = 0;
 #pragma unroll
-            for (int step = 32; step > 0; step >>= 1) {
-                const int probe = __shfl(incl, lo + step - 1, 64);
+            for (int step = W / 2; step > 0; step >>= 1) {
+                const int probe = __shfl(incl, lo + step - 1, W);
                 if (probe <= ti) lo += step;
             }
-            const int start = __shfl(incl - cnt, lo, 64), rtx0 = __shfl(tx0, lo, 64);
+            const int start = __shfl(incl - cnt, lo, W), rtx0 = __shfl(tx0, lo, W);
             if (e0 + lane < total * ng) f(g, (b.ty0 + r0 + lo) & (NT - 1), (rtx0 + ti - start) & (NT - 1));
         }
     }

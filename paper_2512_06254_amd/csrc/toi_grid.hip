@@ -216,8 +216,8 @@ __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__
     }
     __syncthreads();
     if (threadIdx.x < 32) {
-        if (hist[threadIdx.x]) atomicAdd(&aux[kAuxBuckets + threadIdx.x], hist[threadIdx.x]);
-        if (hunits[threadIdx.x]) atomicAdd(&aux[kAuxUnits + threadIdx.x], hunits[threadIdx.x]);
+        if (hist[threadIdx.x]) atomicAdd(&aux[kAuxBuckets + kAuxStride * threadIdx.x], hist[threadIdx.x]);
+        if (hunits[threadIdx.x]) atomicAdd(&aux[kAuxUnits + kAuxStride * threadIdx.x], hunits[threadIdx.x]);
     }
     if (threadIdx.x == 0) aux[kAuxTotals + blockIdx.x] = total;
 }
@@ -244,8 +244,8 @@ __global__ __launch_bounds__(1024) void k_scan_top(int n_blocks, int n_bins, int
         if (carry > bin_cap) atomicOr(&P->status, (uint32_t)TOI_STATUS_OVERFLOW);
         int acc = 0;
         for (int k = 31; k >= 0; --k) {
-            aux[kAuxCursors + k] = acc;
-            acc += aux[kAuxBuckets + k];
+            aux[kAuxCursors + kAuxStride * k] = acc;
+            acc += aux[kAuxBuckets + kAuxStride * k];
         }
         *n_active = acc;
     }
@@ -257,11 +257,26 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
                                                      uint32_t* __restrict__ tile_bits,
                                                      uint32_t* __restrict__ row_bits,
                                                      const DevPlan* __restrict__ P) {
+    // The workgroup's bins are whole tile rows (NT and kScanBlock are powers
+    // of two, NT <= kScanBlock): their occupancy words, at most 512 (one per
+    // row when NT < 32), are gathered in LDS from the counts already loaded,
+    // and so are the rows' row_bits words, at most 64 (one per plane group
+    // when NT < 32, at most 4096 / 8 / 8 groups), added with one global atomic
+    // per word (an atomic per non-empty tile word on a handful of shared words
+    // serialised the workgroups: 33 us per snapshot).
+    constexpr int kMaxWords = kScanBlock / 8, kMaxRowWords = kScanBlock / 64;
     __shared__ int32_t hist[32], start[32];
-    __shared__ uint32_t rbs[64];   // this workgroup's tile-row words of row_bits
-    if (blockIdx.x * kScanBlock >= P->ng * NT * NT) return;   // unused plane groups: never read
+    __shared__ uint32_t tbs[kMaxWords], rbs[kMaxRowWords];
+    const int tiles = NT * NT;
+    if (blockIdx.x * kScanBlock >= P->ng * tiles) return;   // unused plane groups: never read
+    const int words = (NT + 31) / 32;
+    const int row0 = blockIdx.x * (kScanBlock / NT);        // the workgroup's rows [row0, row0 + nrows)
+    const int nrows = min(kScanBlock / NT, n_bins / NT - row0);
+    const int nwords = nrows * words;                       // tile_bits words of those rows (contiguous)
+    const int wbase = (row0 / NT) * words + ((row0 % NT) >> 5);   // first row_bits word
     if (threadIdx.x < 32) hist[threadIdx.x] = 0;
-    if (threadIdx.x < 64) rbs[threadIdx.x] = 0;
+    if (threadIdx.x < kMaxRowWords) rbs[threadIdx.x] = 0;
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) tbs[w] = 0;
     __syncthreads();
     const int add = aux[kAuxTotals + blockIdx.x];
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
@@ -274,15 +289,23 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
             const int o = off[base + j] + add;
             off[base + j] = o;
             cursor[base + j] = o;
-            if (c[j] > 0) atomicAdd(&hist[31 - __clz(c[j])], 1);
+            if (c[j] > 0) {
+                atomicAdd(&hist[31 - __clz(c[j])], 1);
+                const int r = (base + j) / NT, tx = (base + j) % NT;   // global tile row, column
+                atomicOr(&tbs[(r - row0) * words + (tx >> 5)], 1u << (tx & 31));
+                const int g = r / NT, ty = r % NT;
+                atomicOr(&rbs[g * words + (ty >> 5) - wbase], 1u << (ty & 31));
+            }
         }
     }
     __syncthreads();
     if (threadIdx.x < 32) {
         const int h = hist[threadIdx.x];
-        start[threadIdx.x] = h ? atomicAdd(&aux[kAuxCursors + threadIdx.x], h) : 0;
+        start[threadIdx.x] = h ? atomicAdd(&aux[kAuxCursors + kAuxStride * threadIdx.x], h) : 0;
         hist[threadIdx.x] = 0;
     }
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) tile_bits[(size_t)row0 * words + w] = tbs[w];
+    if (threadIdx.x < kMaxRowWords && rbs[threadIdx.x]) atomicOr(&row_bits[wbase + threadIdx.x], rbs[threadIdx.x]);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j)
@@ -290,35 +313,6 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
             const int k = 31 - __clz(c[j]);
             order[start[k] + atomicAdd(&hist[k], 1)] = base + j;
         }
-    // occupancy words of the tile rows that start in this workgroup's range
-    const int words = (NT + 31) / 32;
-    const int row0 = (blockIdx.x * kScanBlock + NT - 1) / NT;
-    const int row1 = min(n_bins, (blockIdx.x + 1) * kScanBlock + NT - 1) / NT;   // rows [row0, row1)
-    // The rows' row_bits words are gathered in LDS first and added with one
-    // global atomic per word: an atomic per non-empty tile word on a handful
-    // of shared words serialised the workgroups (33 us per snapshot).  The
-    // range spans at most 64 words: kScanBlock / NT <= 512 rows, 32 rows per
-    // word, or one word per plane group when NT < 32 (at most 64 groups).
-    static_assert(kScanBlock / 8 / 8 <= 64, "row words of one scan workgroup fit in rbs");
-    const int wbase = (row0 / NT) * words + ((row0 % NT) >> 5);
-    // one word per half-wavefront: each lane tests one tile, a ballot packs them
-    const int hw = (int)(threadIdx.x >> 5), hl = (int)(threadIdx.x & 31);
-    for (int w = row0 * words + hw; w < row1 * words; w += blockDim.x >> 5) {
-        const int row = w / words, wd = w % words;
-        const int i = wd * 32 + hl;
-        const bool nz = i < NT && count[(size_t)row * NT + i] > 0;
-        const uint64_t m = __ballot(nz);
-        const uint32_t bits = (threadIdx.x & 32) ? (uint32_t)(m >> 32) : (uint32_t)m;
-        if (hl == 0) {
-            tile_bits[w] = bits;
-            if (bits) {
-                const int g = row / NT, ty = row % NT;
-                atomicOr(&rbs[g * words + (ty >> 5) - wbase], 1u << (ty & 31));
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 64 && rbs[threadIdx.x]) atomicOr(&row_bits[wbase + threadIdx.x], rbs[threadIdx.x]);
 }
 
 // Work units of the matrix-core passes (one workgroup).  The bins of the
@@ -337,10 +331,10 @@ __global__ __launch_bounds__(1024) void k_units(const DevPlan* __restrict__ P, c
     const int ushift = P->unit_shift, U = 1 << ushift;
     int n_big = 0, n_units = 0;
     for (int k = 31; k >= ushift; --k) {       // uniform over the workgroup
-        const int u = aux[kAuxUnits + k];
+        const int u = aux[kAuxUnits + kAuxStride * k];
         if (n_units + u > kSplitSlots) break;
         n_units += u;
-        n_big += aux[kAuxBuckets + k];
+        n_big += aux[kAuxBuckets + kAuxStride * k];
     }
     int carry = 0;
     for (int i0 = 0; i0 < n_big; i0 += 1024) {
@@ -362,14 +356,18 @@ __global__ __launch_bounds__(1024) void k_units(const DevPlan* __restrict__ P, c
 }
 
 // ---------------------------------------------------------------- 2b. fill
+// kFillLanes lanes per item: an item has about five bins, and the fill is
+// bound by the latency of its returned atomics, so a wavefront serves four
+// items at once (one item per wavefront: 43 us per MeerKAT-shaped snapshot).
+constexpr int kFillLanes = 16;
 __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ items, int n_items, int NT,
                                                   int bin_cap, int32_t* __restrict__ cursor,
                                                   int32_t* __restrict__ list) {
-    const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int item = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kFillLanes);
     if (item >= n_items) return;
     const ItemBox box = items[item];
     const int tiles = NT * NT;
-    for_item_bins(box, NT, [&](int g, int ty, int tx) {   // the same bins as the count in k_items
+    for_item_bins<kFillLanes>(box, NT, [&](int g, int ty, int tx) {   // the same bins as the count in k_items
         const int pos = atomicAdd(&cursor[(size_t)g * tiles + ty * NT + tx], 1);
         if (pos < bin_cap) list[pos] = item;
     });
@@ -390,7 +388,7 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
 // over the list, the workgroup's barrier between passes).
 __device__ inline int heavy_bins(const int32_t* __restrict__ aux) {
     int n = 0;
-    for (int k = kSortShift; k < 32; ++k) n += aux[kAuxBuckets + k];
+    for (int k = kSortShift; k < 32; ++k) n += aux[kAuxBuckets + kAuxStride * k];
     return n;
 }
 
@@ -801,7 +799,8 @@ hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
         hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->plan, c->bin_count, c->bin_order,
                            c->bin_aux, c->units, c->scratch_i);
         if (n_items > 0) {
-            hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, c->items, n_items, NT,
+            hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 256 / kFillLanes - 1) / (256 / kFillLanes)), dim3(256), 0,
+                               c->stream, c->items, n_items, NT,
                                c->bin_cap, c->bin_cursor, c->bin_list);
             hipLaunchKernelGGL(k_bin_sort_block, dim3(kBinSortBlocks), dim3(1024), 0, c->stream, c->plan,
                                c->bin_order, c->bin_aux, c->bin_off, c->bin_list);

@@ -61,7 +61,11 @@ constexpr int kSplitSlots = 16384;
 // number of non-empty bins, the launch-order cursor and the work units of its
 // bins (ceil(count / 2^unit_shift) each), then one total per scan workgroup,
 // then one partial max(|Re|, |Im|) of g x per scan workgroup (float bits).
-constexpr int kAuxBuckets = 0, kAuxCursors = 32, kAuxUnits = 64, kAuxTotals = 96;
+// Each bucket's three words sit in a 128-byte line of their own (word
+// kAux* + kAuxStride k): every scan workgroup adds to them with device-wide
+// atomics, which are applied one at a time per line.
+constexpr int kAuxStride = 32;
+constexpr int kAuxBuckets = 0, kAuxCursors = 1, kAuxUnits = 2, kAuxTotals = 32 * kAuxStride;
 // After the list fill, every bin's items are put in increasing item order:
 // bins of fewer than 2^kSortShift items by one wavefront, larger ones by a
 // workgroup in LDS up to kSortLds items, beyond that in place in HBM.
