@@ -377,8 +377,9 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
 // The fill leaves each bin's items in the order of the atomic cursor; these
 // kernels sort every bin's list into increasing item order (the items of a
 // bin are distinct).  Bins of buckets below kSortShift (fewer than 64 items;
-// the launch order's entries from the heavy buckets' total on) are
-// sorted by one wavefront each, by a bitonic network across the lanes.  The
+// the launch order's entries from the heavy buckets' total on) are sorted by
+// a bitonic network across the lanes: one wavefront per bin of 16 or more
+// items, 16 lanes per bin below that.  The
 // others (the first entries of the launch order) by one workgroup each: a
 // bitonic network whose every comparison puts the smaller value at the lower
 // index (the first substage of each merge compares mirrored positions), so a
@@ -392,6 +393,26 @@ __device__ inline int heavy_bins(const int32_t* __restrict__ aux) {
     return n;
 }
 
+// Bitonic network over aligned groups of W lanes, ascending; every lane of
+// the wavefront runs it (each group sorts its own values).
+template <int W>
+__device__ inline int sort_lanes(int v) {
+    const int l = threadIdx.x & (W - 1);
+#pragma unroll
+    for (int k = 2; k <= W; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int o = __shfl_xor(v, j, W);
+            const bool keep_min = ((l & j) == 0) == ((l & k) == 0);
+            v = keep_min ? min(v, o) : max(v, o);
+        }
+    }
+    return v;
+}
+
+// Bins of 16 to 63 items one per wavefront, bins of fewer than 16 items four
+// per wavefront (16 lanes each): the pass is bound by the latency of its
+// loads, and most bins hold a few items.
 __global__ __launch_bounds__(256) void k_bin_sort_wave(const DevPlan* __restrict__ P, const int32_t* __restrict__ order,
                                                        const int32_t* __restrict__ n_active,
                                                        const int32_t* __restrict__ aux,
@@ -399,21 +420,23 @@ __global__ __launch_bounds__(256) void k_bin_sort_wave(const DevPlan* __restrict
     if (P->status & kStatusFatal) return;
     const int lane = threadIdx.x & 63;
     const int waves = gridDim.x * (blockDim.x >> 6);
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int n_act = *n_active;
-    for (int ob = heavy_bins(aux) + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ob < n_act; ob += waves) {
+    const int first = heavy_bins(aux);
+    const int mid_end = first + aux[kAuxBuckets + kAuxStride * 4] + aux[kAuxBuckets + kAuxStride * 5];
+    for (int ob = first + wave; ob < mid_end; ob += waves) {   // 16 .. 63 items
         const int bin = order[ob];
-        const int b0 = off[bin], n = off[bin + 1] - b0;   // n < 2^kSortShift = 64
-        int v = lane < n ? list[b0 + lane] : INT_MAX;
-#pragma unroll
-        for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                const int o = __shfl_xor(v, j, 64);
-                const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
-                v = keep_min ? min(v, o) : max(v, o);
-            }
-        }
+        const int b0 = off[bin], n = off[bin + 1] - b0;
+        const int v = sort_lanes<64>(lane < n ? list[b0 + lane] : INT_MAX);
         if (lane < n) list[b0 + lane] = v;
+    }
+    const int l16 = lane & 15;
+    for (int ob = mid_end + 4 * wave + (lane >> 4); ob - (lane >> 4) < n_act; ob += 4 * waves) {   // below 16
+        const bool have = ob < n_act;
+        const int bin = have ? order[ob] : 0;
+        const int b0 = have ? off[bin] : 0, n = have ? off[bin + 1] - b0 : 0;
+        const int v = sort_lanes<16>(l16 < n ? list[b0 + l16] : INT_MAX);
+        if (l16 < n) list[b0 + l16] = v;
     }
 }
 

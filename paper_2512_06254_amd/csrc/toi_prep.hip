@@ -16,25 +16,38 @@ __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ wei
     const int r = blockIdx.x;
     double cnt = 0, s1 = 0, s2 = 0, ws = 0;
     double mn = 1e300, mx = -1e300;
-    for (int c = threadIdx.x; c < n_chan; c += blockDim.x) {
-        const size_t base = ((size_t)r * n_chan + c) * n_corr;
-        double w = 0.0;
-        for (int k = 0; k < n_corr; ++k) {
-            if (!((mask >> k) & 1u)) continue;
-            double wk = weight ? (double)weight[base + k] : 1.0;
-            if (flag && flag[base + k]) wk = 0.0;
-            w += wk;
+    // kB channels per thread per round: their loads are issued before any of
+    // them is used (one channel at a time left the row latency-bound)
+    constexpr int kB = 4;
+    for (int c0 = threadIdx.x; c0 < n_chan; c0 += kB * blockDim.x) {
+        double w[kB], nu[kB];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+            const int c = c0 + i * blockDim.x;
+            w[i] = 0.0;
+            nu[i] = 0.0;
+            if (c < n_chan) {
+                const size_t base = ((size_t)r * n_chan + c) * n_corr;
+                nu[i] = freq[c];
+                for (int k = 0; k < n_corr; ++k) {
+                    if (!((mask >> k) & 1u)) continue;
+                    double wk = weight ? (double)weight[base + k] : 1.0;
+                    if (flag && flag[base + k]) wk = 0.0;
+                    w[i] += wk;
+                }
+            }
         }
-        if (w > 0.0) {
-            const double nu = freq[c];
-            const double kk = div_by(nu, kCLight, kInvCLight);
-            cnt += 1.0;
-            s1 += kk;
-            s2 += kk * kk;
-            ws += w;
-            mn = fmin(mn, nu);
-            mx = fmax(mx, nu);
-        }
+#pragma unroll
+        for (int i = 0; i < kB; ++i)
+            if (w[i] > 0.0) {
+                const double kk = div_by(nu[i], kCLight, kInvCLight);
+                cnt += 1.0;
+                s1 += kk;
+                s2 += kk * kk;
+                ws += w[i];
+                mn = fmin(mn, nu[i]);
+                mx = fmax(mx, nu[i]);
+            }
     }
     __shared__ double red[4][16], redm[2][16];
     double sums[4] = {cnt, s1, s2, ws};
