@@ -26,13 +26,30 @@ __global__ __launch_bounds__(256) void k_tlisi_tiles(const float* __restrict__ a
     const int ty = blockIdx.x / T, tx = blockIdx.x % T;
     double sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0, mn = 1e300, mx = -1e300;
     const int n = tile * tile;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const size_t o = (size_t)(ty * tile + i / tile) * N + tx * tile + i % tile;
-        const double va = a[o], vb = b[o], vc = c[o];
-        const double X = vb - va, Y = vc - vb;
-        sx += X; sy += Y; sxx += X * X; syy += Y * Y; sxy += X * Y;
-        mn = fmin(mn, fmin(X, Y));
-        mx = fmax(mx, fmax(X, Y));
+    // kB pixels per thread per round, loaded before any is used (one at a
+    // time left the pass latency-bound); the sums keep the pixel order
+    constexpr int kB = 4;
+    for (int i0 = threadIdx.x; i0 < n; i0 += kB * blockDim.x) {
+        float va[kB], vb[kB], vc[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const int i = i0 + q * blockDim.x;
+            va[q] = vb[q] = vc[q] = 0.f;
+            if (i < n) {
+                const size_t o = (size_t)(ty * tile + i / tile) * N + tx * tile + i % tile;
+                va[q] = a[o];
+                vb[q] = b[o];
+                vc[q] = c[o];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
+            if (i0 + q * (int)blockDim.x < n) {
+                const double X = (double)vb[q] - (double)va[q], Y = (double)vc[q] - (double)vb[q];
+                sx += X; sy += Y; sxx += X * X; syy += Y * Y; sxy += X * Y;
+                mn = fmin(mn, fmin(X, Y));
+                mx = fmax(mx, fmax(X, Y));
+            }
     }
     double sums[5] = {sx, sy, sxx, syy, sxy};
     block_sum_n(sums, red);

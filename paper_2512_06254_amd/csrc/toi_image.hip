@@ -239,20 +239,28 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
 // Re-projection (Section 3.3): output pixel -> reduced SIN map to the tilted
 // plane (x' = x + r0 z xi, y' = y + r0 z eta, z = 1 - n) -> in-plane 2x2 block
 // of V -> transformed-plane coordinates -> bilinear gather.  FP64 coordinates.
+// kReprojRows output rows per thread: the coordinate chain of a pixel (an
+// FP64 square root and three divisions) is long, and independent pixels in
+// one thread let it overlap (one pixel per thread left the pass latency-bound).
+constexpr int kReprojRows = 4;
 __global__ __launch_bounds__(256) void k_reproject(const float* __restrict__ tplane_t, float* __restrict__ img,
                                                    const DevPlan* __restrict__ plan, int N, double cell_rad) {
     const int j1 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j2 = blockIdx.y;
     if (j1 >= N) return;
-    float val = 0.f;
-    int i1, i2;
-    float f1, f2;
-    if (!(plan->status & kStatusFatal) && reproject_source(plan, N, cell_rad, j1, j2, i1, i2, f1, f2)) {
-        const float* c0 = tplane_t + (size_t)i1 * N + i2;      // j1-major t-plane
-        const float* c1 = c0 + N;
-        val = (1.f - f1) * (1.f - f2) * c0[0] + f1 * (1.f - f2) * c1[0] + (1.f - f1) * f2 * c0[1] + f1 * f2 * c1[1];
+    const bool fatal = plan->status & kStatusFatal;
+#pragma unroll
+    for (int q = 0; q < kReprojRows; ++q) {
+        const int j2 = blockIdx.y * kReprojRows + q;
+        float val = 0.f;
+        int i1, i2;
+        float f1, f2;
+        if (j2 < N && !fatal && reproject_source(plan, N, cell_rad, j1, j2, i1, i2, f1, f2)) {
+            const float* c0 = tplane_t + (size_t)i1 * N + i2;      // j1-major t-plane
+            const float* c1 = c0 + N;
+            val = (1.f - f1) * (1.f - f2) * c0[0] + f1 * (1.f - f2) * c1[0] + (1.f - f1) * f2 * c0[1] + f1 * f2 * c1[1];
+        }
+        if (j2 < N) img[(size_t)j2 * N + j1] = val;
     }
-    img[(size_t)j2 * N + j1] = val;
 }
 
 __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src, float* __restrict__ dst, int N) {
@@ -300,7 +308,8 @@ hipError_t launch_image(toi_ctx* c, float* image_out, float* tplane_out) {
     const int N = c->N;
     const double cell = c->p.cell_deg * kPi / 180.0;
     StageTimer timer(c, TOI_STAGE_REPROJECT);
-    hipLaunchKernelGGL(k_reproject, dim3((N + 255) / 256, N), dim3(256), 0, c->stream, c->tplane_t, image_out,
+    hipLaunchKernelGGL(k_reproject, dim3((N + 255) / 256, (N + kReprojRows - 1) / kReprojRows), dim3(256), 0,
+                       c->stream, c->tplane_t, image_out,
                        c->plan, N, cell);
     if (tplane_out)
         hipLaunchKernelGGL(k_transpose, dim3(N / 32, N / 32), dim3(256), 0, c->stream, c->tplane_t, tplane_out, N);
