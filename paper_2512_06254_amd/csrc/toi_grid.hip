@@ -4,9 +4,10 @@
 // Tile-owner design, no float atomics on the grid:
 //  1. Work items are runs of kItemChans channels of one row.  A row's samples
 //     lie on a radial track (b = uvw nu / c), so an item's 8 x 8 footprints
-//     cover a small box; k_items computes the box and the slabs it touches,
-//     counts the item into every (plane group, 8 x 8 tile) bin it overlaps and
-//     writes each sample's gridding record (cell, offsets, slab, value).
+//     cover a small box.  k_items writes each sample's gridding record (cell,
+//     offsets, slab, value); k_item_bins computes the box and the slabs it
+//     touches and counts the item into every (plane group, 8 x 8 tile) bin it
+//     overlaps.
 //  2. k_scan_local / k_scan_top / k_scan_apply turn the counts into list
 //     offsets, a heaviest-first launch order and occupancy bit masks; k_units
 //     splits the heaviest bins into work units of at most 2^unit_shift items;
@@ -31,30 +32,29 @@
 namespace toi {
 
 // ---------------------------------------------------------------- 1. items
-// One wavefront per item; lane l also writes the gridding record of channel
-// c0 + l (FP64 coordinates split into a cell and FP32 offsets once per sample).
+// One wavefront per item; lane l writes the gridding record of channel c0 + l
+// (FP64 coordinates split into a cell and FP32 offsets once per sample), and
+// the item's largest value and extreme kept frequencies go to its ItemBox
+// (k_item_bins derives the box and counts the bins from them).
 __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, const float2* __restrict__ vis,
                                                const float* __restrict__ weight, const uint8_t* __restrict__ flag,
                                                const double* __restrict__ freq, const int32_t* __restrict__ ant1,
                                                const int32_t* __restrict__ ant2, const float2* __restrict__ gains,
                                                int n_ant, int n_chan, int n_corr, uint32_t mask, int vec4,
-                                               int mode, DevPlan* __restrict__ P, int M, int NT, double cell_rad,
-                                               int n_items, ItemBox* __restrict__ items, SampleRec* __restrict__ recs,
-                                               int32_t* __restrict__ bin_count) {
+                                               int mode, const DevPlan* __restrict__ P, int M, double cell_rad,
+                                               int n_items, ItemBox* __restrict__ items, SampleRec* __restrict__ recs) {
     const int lane = threadIdx.x & 63;
     const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (item >= n_items) return;
     const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
     const int r = item / n_chunks;
     const int c = (item % n_chunks) * kItemChans + lane;
-    ItemBox box;
-    box.x0 = box.y0 = box.x1 = box.y1 = 0.0;
-    box.ty0 = 1; box.ty1 = 0; box.g0 = 1; box.g1 = 0;
-    box.vmax = 0.f;
-    box.pad_ = 0;
-    box.inv_dy = 0.0;
     if (P->status) {
-        if (lane == 0) items[item] = box;
+        if (lane == 0) {
+            items[item].vmax = 0.f;
+            items[item].nlo = 1e300;
+            items[item].nhi = -1e300;
+        }
         return;
     }
     const Track tr = row_track(uvw, r, P, M, cell_rad);
@@ -94,36 +94,68 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     }
     // the item's largest value (reduced over all items by the bin scan: no
     // atomic on one address per item)
-    box.vmax = wave_max(vabs);
+    const float vmax = wave_max(vabs);
     // X, Y and r3 are linear in nu along the row: their extremes over the kept
     // channels sit at the extreme kept frequencies
     double nlo = 1e300, nhi = -1e300;
     if (kept) nlo = nhi = freq[c];
     nlo = wave_min(nlo);
     nhi = wave_max(nhi);
-    if (nlo > nhi) {   // no kept sample
-        if (lane == 0) items[item] = box;
-        return;
+    if (lane == 0) {
+        items[item].vmax = vmax;
+        items[item].nlo = nlo;
+        items[item].nhi = nhi;
     }
-    box.x0 = 0.5 * M + tr.ax * nlo;
-    box.x1 = 0.5 * M + tr.ax * nhi;
-    box.y0 = 0.5 * M + tr.ay * nlo;
-    box.y1 = 0.5 * M + tr.ay * nhi;
-    // (an extent below 1e-9 cells counts as none: every row then takes the whole X range)
-    box.inv_dy = fabs(box.y1 - box.y0) > 1e-9 ? 1.0 / (box.y1 - box.y0) : 0.0;
-    const double ra = tr.a3 * nlo, rb = tr.a3 * nhi;
-    const double ylo = fmin(box.y0, box.y1), yhi = fmax(box.y0, box.y1);
-    // footprint rows [ceil(Y - 4), ceil(Y - 4) + 7] -> tile rows (floor division)
-    box.ty0 = ((int)ceil(ylo - 1e-6 - 4.0)) >> kTileShift;
-    box.ty1 = ((int)ceil(yhi + 1e-6 - 4.0) + 7) >> kTileShift;
-    box.ty1 = min(box.ty1, box.ty0 + NT - 1);
-    const int p0 = mode == 3 ? slab_index(fmin(ra, rb), P) : 0, p1 = mode == 3 ? slab_index(fmax(ra, rb), P) : 0;
-    box.g0 = group_of_slab(p0, P);
-    box.g1 = group_of_slab(p1, P) + (P->K > P->gp ? P->parts - 1 : 0);
-    if (lane == 0) items[item] = box;
+}
+
+// Per item, kItemLanes lanes (four items per wavefront): the track box of the
+// kept samples from the extreme kept frequencies, and the item counted into
+// every (plane group, tile) bin its footprints can touch.  The per-item work
+// is the same for every lane of a group, so it was most of the record pass's
+// instructions while that pass gave it a whole wavefront per item.
+constexpr int kItemLanes = 16;
+__global__ __launch_bounds__(256) void k_item_bins(const double* __restrict__ uvw, int n_chan, int mode,
+                                                   const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
+                                                   int n_items, ItemBox* __restrict__ items,
+                                                   int32_t* __restrict__ bin_count) {
+    const int item = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kItemLanes);
+    if (item >= n_items) return;
+    const bool writer = (threadIdx.x & (kItemLanes - 1)) == 0;
+    const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
+    const double nlo = items[item].nlo, nhi = items[item].nhi;
+    ItemBox box;
+    box.x0 = box.y0 = box.x1 = box.y1 = 0.0;
+    box.ty0 = 1; box.ty1 = 0; box.g0 = 1; box.g1 = 0;
+    box.inv_dy = 0.0;
+    if (!P->status && nlo <= nhi) {
+        const Track tr = row_track(uvw, item / n_chunks, P, M, cell_rad);
+        box.x0 = 0.5 * M + tr.ax * nlo;
+        box.x1 = 0.5 * M + tr.ax * nhi;
+        box.y0 = 0.5 * M + tr.ay * nlo;
+        box.y1 = 0.5 * M + tr.ay * nhi;
+        // (an extent below 1e-9 cells counts as none: every row then takes the whole X range)
+        box.inv_dy = fabs(box.y1 - box.y0) > 1e-9 ? 1.0 / (box.y1 - box.y0) : 0.0;
+        const double ra = tr.a3 * nlo, rb = tr.a3 * nhi;
+        const double ylo = fmin(box.y0, box.y1), yhi = fmax(box.y0, box.y1);
+        // footprint rows [ceil(Y - 4), ceil(Y - 4) + 7] -> tile rows (floor division)
+        box.ty0 = ((int)ceil(ylo - 1e-6 - 4.0)) >> kTileShift;
+        box.ty1 = ((int)ceil(yhi + 1e-6 - 4.0) + 7) >> kTileShift;
+        box.ty1 = min(box.ty1, box.ty0 + NT - 1);
+        const int p0 = mode == 3 ? slab_index(fmin(ra, rb), P) : 0, p1 = mode == 3 ? slab_index(fmax(ra, rb), P) : 0;
+        box.g0 = group_of_slab(p0, P);
+        box.g1 = group_of_slab(p1, P) + (P->K > P->gp ? P->parts - 1 : 0);
+    }
+    if (writer) {   // the box fields (vmax, nlo, nhi stay as the record pass wrote them)
+        ItemBox& o = items[item];
+        o.x0 = box.x0; o.y0 = box.y0; o.x1 = box.x1; o.y1 = box.y1;
+        o.ty0 = box.ty0; o.ty1 = box.ty1; o.g0 = box.g0; o.g1 = box.g1;
+        o.inv_dy = box.inv_dy;
+    }
     // count into bins (each row's tiles from the track)
     const int tiles = NT * NT;
-    for_item_bins(box, NT, [&](int g, int ty, int tx) { atomicAdd(&bin_count[(size_t)g * tiles + ty * NT + tx], 1); });
+    for_item_bins<kItemLanes>(box, NT, [&](int g, int ty, int tx) {
+        atomicAdd(&bin_count[(size_t)g * tiles + ty * NT + tx], 1);
+    });
 }
 
 // ---------------------------------------------------------------- 2. scan
@@ -367,7 +399,7 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
     if (item >= n_items) return;
     const ItemBox box = items[item];
     const int tiles = NT * NT;
-    for_item_bins<kFillLanes>(box, NT, [&](int g, int ty, int tx) {   // the same bins as the count in k_items
+    for_item_bins<kFillLanes>(box, NT, [&](int g, int ty, int tx) {   // the same bins as the count in k_item_bins
         const int pos = atomicAdd(&cursor[(size_t)g * tiles + ty * NT + tx], 1);
         if (pos < bin_cap) list[pos] = item;
     });
@@ -811,7 +843,11 @@ hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
                                (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2,
                                (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask,
                                (int)vec4_ok(s.vis, s.flag, s.weight, p.n_corr), p.mode, c->plan, M,
-                               NT, cell, n_items, c->items, c->recs, c->bin_count);
+                               cell, n_items, c->items, c->recs);
+        if (n_items > 0)
+            hipLaunchKernelGGL(k_item_bins, dim3((n_items + 256 / kItemLanes - 1) / (256 / kItemLanes)), dim3(256), 0,
+                               c->stream, s.uvw, p.n_chan, p.mode, c->plan, M, NT, cell, n_items, c->items,
+                               c->bin_count);
         hipLaunchKernelGGL(k_scan_local, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, c->plan,
                            NT * NT, c->items, n_items, c->bin_off, c->bin_aux);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, n_scan, n_bins, c->bin_cap, c->plan,

@@ -114,6 +114,7 @@ struct ItemBox {
     float vmax;
     int32_t pad_;
     double inv_dy;   // 1 / (y1 - y0), 0 when |y1 - y0| <= 1e-9
+    double nlo, nhi; // extreme kept frequencies (nlo > nhi: none kept), from the record pass
 };
 
 // One sample prepared for gridding (written by k_items, read by the
