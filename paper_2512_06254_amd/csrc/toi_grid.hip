@@ -108,12 +108,12 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
     }
 }
 
-// Per item, kItemLanes lanes (four items per wavefront): the track box of the
+// Per item, kItemLanes lanes (eight items per wavefront): the track box of the
 // kept samples from the extreme kept frequencies, and the item counted into
 // every (plane group, tile) bin its footprints can touch.  The per-item work
 // is the same for every lane of a group, so it was most of the record pass's
 // instructions while that pass gave it a whole wavefront per item.
-constexpr int kItemLanes = 16;
+constexpr int kItemLanes = 8;
 __global__ __launch_bounds__(256) void k_item_bins(const double* __restrict__ uvw, int n_chan, int mode,
                                                    const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
                                                    int n_items, ItemBox* __restrict__ items,
@@ -389,9 +389,10 @@ __global__ __launch_bounds__(1024) void k_units(const DevPlan* __restrict__ P, c
 
 // ---------------------------------------------------------------- 2b. fill
 // kFillLanes lanes per item: an item has about five bins, and the fill is
-// bound by the latency of its returned atomics, so a wavefront serves four
-// items at once (one item per wavefront: 43 us per MeerKAT-shaped snapshot).
-constexpr int kFillLanes = 16;
+// bound by the latency of its returned atomics, so a wavefront serves eight
+// items at once (one item per wavefront: 43 us per MeerKAT-shaped snapshot,
+// four: 22 us, eight: 20.5 us).
+constexpr int kFillLanes = 8;
 __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ items, int n_items, int NT,
                                                   int bin_cap, int32_t* __restrict__ cursor,
                                                   int32_t* __restrict__ list) {
