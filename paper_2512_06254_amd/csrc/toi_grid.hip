@@ -173,14 +173,18 @@ __global__ __launch_bounds__(256) void k_item_bins(const double* __restrict__ uv
 // aux: layout kAux* (toi_internal.h).
 constexpr int kScanPer = kScanBlock / 1024;
 
-__global__ __launch_bounds__(256) void k_scan_clear(int32_t* __restrict__ count, int n_bins,
-                                                    int32_t* __restrict__ aux, uint32_t* __restrict__ row_bits,
-                                                    int n_row_words) {
+// Only the bins and row words of the plan's plane groups are cleared (the
+// scan treats the bins of the other groups as empty, whatever they hold).
+__global__ __launch_bounds__(256) void k_scan_clear(const DevPlan* __restrict__ P, int32_t* __restrict__ count,
+                                                    int n_bins, int tiles, int32_t* __restrict__ aux,
+                                                    uint32_t* __restrict__ row_bits, int n_row_words, int words) {
     const int stride = gridDim.x * blockDim.x;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int i = t; i < n_bins; i += stride) count[i] = 0;
+    const int ng = P->ng;
+    const int nb = min(n_bins, ng * tiles), nw = min(n_row_words, ng * words);
+    for (int i = t; i < nb; i += stride) count[i] = 0;
     if (t < kAuxTotals) aux[t] = 0;
-    for (int i = t; i < n_row_words; i += stride) row_bits[i] = 0;
+    for (int i = t; i < nw; i += stride) row_bits[i] = 0;
 }
 
 __device__ inline int block_exclusive_scan(int v, int& total) {
@@ -227,11 +231,12 @@ __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__
         hunits[threadIdx.x] = 0;
     }
     const int ushift = P->unit_shift;
+    const int n_live = min(n_bins, P->ng * tiles);   // bins of the plan's plane groups
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
     int c[kScanPer], sum = 0;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-        c[j] = base + j < n_bins ? count[base + j] : 0;
+        c[j] = base + j < n_live ? count[base + j] : 0;
         sum += c[j];
     }
     int total;
@@ -311,13 +316,14 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
     for (int w = threadIdx.x; w < nwords; w += blockDim.x) tbs[w] = 0;
     __syncthreads();
     const int add = aux[kAuxTotals + blockIdx.x];
+    const int n_live = min(n_bins, P->ng * tiles);   // bins of the plan's plane groups
     const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
     int c[kScanPer];
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
         c[j] = 0;
         if (base + j < n_bins) {
-            c[j] = count[base + j];
+            c[j] = base + j < n_live ? count[base + j] : 0;
             const int o = off[base + j] + add;
             off[base + j] = o;
             cursor[base + j] = o;
@@ -409,20 +415,21 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
 // ---------------------------------------------------------------- 2c. order
 // The fill leaves each bin's items in the order of the atomic cursor; these
 // kernels sort every bin's list into increasing item order (the items of a
-// bin are distinct).  Bins of buckets below kSortShift (fewer than 64 items;
-// the launch order's entries from the heavy buckets' total on) are sorted by
-// a bitonic network across the lanes: one wavefront per bin of 16 or more
-// items, 16 lanes per bin below that.  The
-// others (the first entries of the launch order) by one workgroup each: a
+// bin are distinct).  Bins of buckets below kBlockSortShift (fewer than 256
+// items; the launch order's entries from the heaviest buckets' total on) are
+// sorted by a bitonic network across the lanes: one wavefront per bin of 16 or
+// more items (four values per lane from 64 items), 16 lanes per bin below
+// that.  The others (the first entries of the launch order) by one workgroup each: a
 // bitonic network whose every comparison puts the smaller value at the lower
 // index (the first substage of each merge compares mirrored positions), so a
 // list of any length sorts as if padded to a power of two with values larger
 // than every item, and the padding is never stored.  Up to kSortLds items the
 // list is sorted in LDS; longer lists in place in HBM (each substage a pass
 // over the list, the workgroup's barrier between passes).
-__device__ inline int heavy_bins(const int32_t* __restrict__ aux) {
+// Non-empty bins of the buckets lo .. hi - 1 (floor(log2(count))).
+__device__ inline int bucket_bins(const int32_t* __restrict__ aux, int lo, int hi) {
     int n = 0;
-    for (int k = kSortShift; k < 32; ++k) n += aux[kAuxBuckets + kAuxStride * k];
+    for (int k = lo; k < hi; ++k) n += aux[kAuxBuckets + kAuxStride * k];
     return n;
 }
 
@@ -443,9 +450,33 @@ __device__ inline int sort_lanes(int v) {
     return v;
 }
 
-// Bins of 16 to 63 items one per wavefront, bins of fewer than 16 items four
-// per wavefront (16 lanes each): the pass is bound by the latency of its
-// loads, and most bins hold a few items.
+// Bitonic network over 64 S values held S per lane (value s 64 + lane in
+// v[s]), ascending: partners within a slot by lane shuffles, partners 64 or
+// more apart by register exchange.
+template <int S>
+__device__ inline void sort_wave_slots(int (&v)[S]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64 * S; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            int o[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) o[s] = j >= 64 ? v[s ^ (j >> 6)] : __shfl_xor(v[s], j, 64);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int e = s * 64 + lane;
+                const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+                v[s] = keep_min ? min(v[s], o[s]) : max(v[s], o[s]);
+            }
+        }
+    }
+}
+
+// Bins of 64 to 255 items one per wavefront, four values per lane; bins of
+// 16 to 63 items one per wavefront; bins of fewer than 16 items four per
+// wavefront (16 lanes each): the pass is bound by the latency of its loads,
+// and most bins hold a few items.
 __global__ __launch_bounds__(256) void k_bin_sort_wave(const DevPlan* __restrict__ P, const int32_t* __restrict__ order,
                                                        const int32_t* __restrict__ n_active,
                                                        const int32_t* __restrict__ aux,
@@ -455,9 +486,21 @@ __global__ __launch_bounds__(256) void k_bin_sort_wave(const DevPlan* __restrict
     const int waves = gridDim.x * (blockDim.x >> 6);
     const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int n_act = *n_active;
-    const int first = heavy_bins(aux);
-    const int mid_end = first + aux[kAuxBuckets + kAuxStride * 4] + aux[kAuxBuckets + kAuxStride * 5];
-    for (int ob = first + wave; ob < mid_end; ob += waves) {   // 16 .. 63 items
+    const int first = bucket_bins(aux, kBlockSortShift, 32);
+    const int big_end = first + bucket_bins(aux, kSortShift, kBlockSortShift);
+    const int mid_end = big_end + bucket_bins(aux, 4, kSortShift);
+    for (int ob = first + wave; ob < big_end; ob += waves) {   // 64 .. 255 items
+        const int bin = order[ob];
+        const int b0 = off[bin], n = off[bin + 1] - b0;
+        int v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = q * 64 + lane < n ? list[b0 + q * 64 + lane] : INT_MAX;
+        sort_wave_slots<4>(v);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q * 64 + lane < n) list[b0 + q * 64 + lane] = v[q];
+    }
+    for (int ob = big_end + wave; ob < mid_end; ob += waves) {   // 16 .. 63 items
         const int bin = order[ob];
         const int b0 = off[bin], n = off[bin + 1] - b0;
         const int v = sort_lanes<64>(lane < n ? list[b0 + lane] : INT_MAX);
@@ -509,7 +552,7 @@ __global__ __launch_bounds__(1024) void k_bin_sort_block(const DevPlan* __restri
                                                          const int32_t* __restrict__ off, int32_t* __restrict__ list) {
     __shared__ int32_t s[kSortLds];
     if (P->status & kStatusFatal) return;
-    const int n_heavy = heavy_bins(aux);
+    const int n_heavy = bucket_bins(aux, kBlockSortShift, 32);   // 256 items and more
     for (int ob = blockIdx.x; ob < n_heavy; ob += gridDim.x) {
         const int bin = order[ob];
         const int b0 = off[bin], n = off[bin + 1] - b0;
@@ -837,8 +880,8 @@ hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
         StageTimer timer(c, TOI_STAGE_BIN);
         const int words = (NT + 31) / 32;
         const int n_scan = (n_bins + kScanBlock - 1) / kScanBlock;
-        hipLaunchKernelGGL(k_scan_clear, dim3(256), dim3(256), 0, c->stream, c->bin_count, n_bins, c->bin_aux,
-                           c->row_bits, c->NG_max * words);
+        hipLaunchKernelGGL(k_scan_clear, dim3(256), dim3(256), 0, c->stream, c->plan, c->bin_count, n_bins, NT * NT,
+                           c->bin_aux, c->row_bits, c->NG_max * words, words);
         if (n_items > 0)
             hipLaunchKernelGGL(k_items, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw,
                                (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2,

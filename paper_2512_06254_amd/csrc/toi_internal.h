@@ -67,9 +67,10 @@ constexpr int kSplitSlots = 16384;
 constexpr int kAuxStride = 32;
 constexpr int kAuxBuckets = 0, kAuxCursors = 1, kAuxUnits = 2, kAuxTotals = 32 * kAuxStride;
 // After the list fill, every bin's items are put in increasing item order:
-// bins of fewer than 2^kSortShift items by one wavefront, larger ones by a
-// workgroup in LDS up to kSortLds items, beyond that in place in HBM.
-constexpr int kSortShift = 6, kSortLds = 16384;
+// bins of fewer than 2^kBlockSortShift items by one wavefront (four values per
+// lane from 2^kSortShift items, 16 lanes per bin below 16 items), larger ones
+// by a workgroup in LDS up to kSortLds items, beyond that in place in HBM.
+constexpr int kSortShift = 6, kBlockSortShift = 8, kSortLds = 16384;
 constexpr int kPartFloats = 64 * 32;   // one partial tile: 64 cells x up to 16 complex planes
 constexpr int kAdjAbsmaxParts = 1024;  // workgroups of the adjoint's image-gradient maximum
 
