@@ -94,19 +94,17 @@ template <int M, int E>
 __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(const float2* __restrict__ hbuf, float* __restrict__ tplane_t,
                                                     const float2* __restrict__ tw, const float* __restrict__ corr,
                                                     const DevPlan* __restrict__ plan, float cell_rad, int mode,
-                                                    const uint32_t* __restrict__ row_bits, int ng_cap) {
+                                                    const uint32_t* __restrict__ row_bits) {
     constexpr int N = M / 2;
     constexpr int KEEP = E / 2;
     constexpr int NT = M / kTile, WORDS = (NT + 31) / 32;
     __shared__ float2 lds[fft_lds_size<M, E>()];
     __shared__ float2 tw_s[FftTw<M, E>::size()];
-    extern __shared__ uint32_t rb_s[];                 // [ng][WORDS] nonempty tile rows per group
     const int j1 = xcd_block_id(blockIdx.x, gridDim.x);
     int j2[KEEP];
 #pragma unroll
     for (int q = 0; q < KEEP; ++q) j2[q] = fft_kept_index<M, E>(q);
     float* out = tplane_t + (size_t)j1 * N;
-    for (int i = threadIdx.x; i < ng_cap * WORDS; i += blockDim.x) rb_s[i] = row_bits[i];
     load_twiddles<M, E>(tw_s, tw);
     if (plan->status & kStatusFatal) {
 #pragma unroll
@@ -121,7 +119,7 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
 
     if (mode == 2) {
         float2 v[E];
-        fft_load_masked<M, E, kHbufGroup>(v, hbuf + hbuf_index<M>(0, j1, 0), [&](int y) { return (rb_s[y >> (kTileShift + 5)] >> ((y >> kTileShift) & 31)) & 1u; });
+        fft_load_masked<M, E, kHbufGroup>(v, hbuf + hbuf_index<M>(0, j1, 0), [&](int y) { return (row_bits[y >> (kTileShift + 5)] >> ((y >> kTileShift) & 31)) & 1u; });
         fft_stages<M, E, 1>(v, lds, tw_s);
 #pragma unroll
         for (int q = 0; q < KEEP; ++q) tr[q] = v[fft_kept_slot<E>(q)].x;
@@ -176,7 +174,10 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
                 float2 v[E];
                 const int gk = group_of_plane(p * K + k, plan);
                 if (gk != occ_g) {   // planes of one group share the occupancy of their tile rows
-                    const uint32_t* rbg = rb_s + gk * WORDS;
+                    // the group's words come from L1/L2: a copy of every group's
+                    // words in LDS took 17 KB at 272 planes and left one
+                    // workgroup per CU instead of two
+                    const uint32_t* rbg = row_bits + gk * WORDS;
                     occ = fft_element_bits<M, E>(
                         [&](int y) { return (rbg[y >> (kTileShift + 5)] >> ((y >> kTileShift) & 31)) & 1u; });
                     occ_g = gk;
@@ -284,10 +285,8 @@ static hipError_t launch_fft_passes(toi_ctx* c) {
     }
     const float cell = (float)(c->p.cell_deg * kPi / 180.0);
     StageTimer timer(c, TOI_STAGE_FFT_COLS);
-    const int words = (c->NT + 31) / 32;
-    hipLaunchKernelGGL((k_fft_cols<M, EC>), dim3(M / 2), dim3(M / EC), c->NG_max * words * sizeof(uint32_t),
-                       c->stream, c->hbuf, c->tplane_t, c->twiddle, c->corr, c->plan, cell, c->p.mode, c->row_bits,
-                       c->NG_max);
+    hipLaunchKernelGGL((k_fft_cols<M, EC>), dim3(M / 2), dim3(M / EC), 0, c->stream, c->hbuf, c->tplane_t,
+                       c->twiddle, c->corr, c->plan, cell, c->p.mode, c->row_bits);
     return hipGetLastError();
 }
 
