@@ -66,6 +66,9 @@ __global__ __launch_bounds__(256) void k_tlisi_tiles(const float* __restrict__ a
     }
 }
 
+// Every workgroup takes the extremes over all tiles (exact, so the same in
+// each) and then the map values of its share of the tiles.
+constexpr int kTlisiFinalGroups = 16;
 __global__ __launch_bounds__(1024) void k_tlisi_final(const TileStat* __restrict__ st, int n_tiles, int tile,
                                                       float* __restrict__ out) {
     __shared__ double red[2][16];
@@ -79,7 +82,7 @@ __global__ __launch_bounds__(1024) void k_tlisi_final(const TileStat* __restrict
     const double L = mx - mn;
     const double C1 = (0.01 * L) * (0.01 * L), C2 = (0.03 * L) * (0.03 * L);
     const double inv_n = 1.0 / ((double)tile * tile);
-    for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tiles; i += gridDim.x * blockDim.x) {
         if (!(L > 0.0)) {
             out[i] = 1.f;
             continue;
@@ -97,7 +100,8 @@ static void tlisi_kernels(hipStream_t stream, const float* a, const float* b, co
                           TileStat* stats, float* out) {
     const int T = N / tile;
     hipLaunchKernelGGL(k_tlisi_tiles, dim3((T * T + 3) / 4), dim3(256), 0, stream, a, b, d, N, tile, stats);
-    hipLaunchKernelGGL(k_tlisi_final, dim3(1), dim3(1024), 0, stream, stats, T * T, tile, out);
+    hipLaunchKernelGGL(k_tlisi_final, dim3(std::min(kTlisiFinalGroups, (T * T + 1023) / 1024)), dim3(1024), 0, stream,
+                       stats, T * T, tile, out);
 }
 
 hipError_t launch_tlisi(toi_ctx* c, const float* a, const float* b, const float* d, float* out) {

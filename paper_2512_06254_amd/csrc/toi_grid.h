@@ -274,7 +274,8 @@ __device__ inline bool reproject_source(const DevPlan* __restrict__ P, int N, do
     const double a = l + P->xi * z, b = m + P->eta * z;
     const double t1 = P->V[0] * a + P->V[1] * b;
     const double t2 = P->V[3] * a + P->V[4] * b;
-    const double u1 = 0.5 * N - t1 / cell_rad, u2 = 0.5 * N + t2 / cell_rad;
+    const double icr = 1.0 / cell_rad;                            // uniform: one division per thread
+    const double u1 = 0.5 * N - div_by(t1, cell_rad, icr), u2 = 0.5 * N + div_by(t2, cell_rad, icr);
     const double f1d = floor(u1), f2d = floor(u2);
     if (!(f1d >= 0.0 && f1d <= N - 2 && f2d >= 0.0 && f2d <= N - 2)) return false;
     i1 = (int)f1d;
