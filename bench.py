@@ -519,6 +519,8 @@ def main():
     ap.add_argument("--workload", default="meerkat")
     ap.add_argument("--pool", type=int, default=4, help="distinct resident snapshots cycled through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", type=int, default=None,
+                    help="gridder variant of the plain leg instead of the autotuner's choice (the tuner still runs)")
     ap.add_argument("--batch", type=int, default=32, help="snapshots per batched graph launch (0 = skip)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--ingest", type=int, default=8, help="host-resident snapshots per toi_ingest call (0 = skip)")
@@ -560,6 +562,10 @@ def main():
                   n_ant=wl.n_ant, tile=32)
     variant, tune_ms = im.tune(pool[0])
     log(f"[bench] autotuned gridder variant {variant}: " + ", ".join(f"{m:.2f}" for m in tune_ms) + " ms")
+    if args.tuning is not None:   # a fixed variant (profiling runs: the same kernels whatever the timing)
+        variant = args.tuning
+        im.set_tuning(variant)
+        log(f"[bench] gridder variant {variant} (--tuning)")
     N = wl.n_pix
     ring = [torch.zeros((N, N), dtype=torch.float32, device=device) for _ in range(3)]
     tl = torch.zeros((N // 32, N // 32), dtype=torch.float32, device=device)
@@ -627,7 +633,7 @@ def main():
         # "alu" against the FP32 vector peak.  8 planes per pass: FP32 matrix
         # instructions, which share the vector ALU on gfx950.
         ach = grid_flops(wl, P) / (dom_ms * 1e-3) / 1e12
-        kname = "k_grid_tiles_mfma"
+        kname = "k_grid_bins16" if variant & 8 else "k_grid_tiles_mfma"
         bound = "alu" if split16 else "mfma"
         peak = FP32_VECTOR_PEAK_TFLOPS if split16 else FP32_MFMA_PEAK_TFLOPS
         roofline = {"bound": bound, "achieved": round(ach, 2), "peak": peak,
@@ -656,6 +662,8 @@ def main():
                              "of one step, null when any kernel source changed since they were taken"}
     fp32 = [tune_ms[v] for v in range(len(tune_ms)) if v & 4]
     b16 = [tune_ms[v] for v in range(len(tune_ms)) if not v & 4]
+    bins8 = [tune_ms[v] for v in range(len(tune_ms)) if not v & 12]
+    bins16 = [tune_ms[v] for v in range(len(tune_ms)) if v & 8]
     out = {
         "metric": METRIC, "value": round(ms, 4), "unit": "ms/snapshot", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": False, "scaling": "weak",
@@ -677,8 +685,11 @@ def main():
                         f"FETCH_SIZE + WRITE_SIZE (profiles/), null when stale"),
         "tuning": {"variant": variant, "grid_plus_image_ms_per_variant": [round(m, 3) for m in tune_ms],
                    "variants": "bits 0-1 work-unit size 32 << bits items; bit 2 8 planes per pass on the FP32 "
-                               "matrix cores instead of 16 on the fp16 matrix cores (split operands)",
+                               "matrix cores instead of 16 on the fp16 matrix cores (split operands); bit 3 "
+                               "bins of 16 x 16 cells instead of 8 x 8 (16 planes per pass)",
                    "best_ms_f16x3_16_planes": round(min(b16), 3),
+                   "best_ms_f16x3_8x8_bins": round(min(bins8), 3),
+                   "best_ms_f16x3_16x16_bins": round(min(bins16), 3) if bins16 else None,
                    "best_ms_fp32_8_planes": round(min(fp32), 3)},
     }
     im.close()

@@ -278,12 +278,15 @@ toi_status toi_ingest(toi_ctx* ctx, const toi_snapshot* host_snaps, int32_t n,
                       float* images_out, float* tlisi_out);
 
 /* Autotuning of the gridder (batched use).  The gridder accumulates each
- * 8 x 8 grid tile of a plane group in one wavefront's matrix-core
- * accumulators, over a work unit of the tile's item list; the variants differ
+ * bin (grid tile) of a plane group in one wavefront's matrix-core
+ * accumulators, over a work unit of the bin's item list; the variants differ
  * in the work-unit size (bits 0-1: bins are split into units of at most
- * 32 << bits items -- the subgrid work granularity) and the plane schedule
+ * 32 << bits items -- the subgrid work granularity), the plane schedule
  * (bit 2: 8 planes per pass over a tile on the FP32 matrix cores, else 16
- * planes per pass on the bf16 matrix cores with operands split as hi + lo).
+ * planes per pass on the fp16 matrix cores with operands split as hi + lo)
+ * and the bin size (bit 3, variants 8 .. 11, 16 planes per pass: bins of
+ * 16 x 16 cells instead of 8 x 8 where the grid side is at least 256; the
+ * adjoint then bins the snapshot again at 8 x 8 before its gather).
  * Every variant computes the same image up to FP32 rounding order, and each
  * variant's image is the same from run to run.  toi_tune synchronises, times
  * grid + image of `sample` with every variant (HIP events, after one
@@ -291,7 +294,7 @@ toi_status toi_ingest(toi_ctx* ctx, const toi_snapshot* host_snaps, int32_t n,
  * ms_out (host, TOI_TUNE_VARIANTS entries, nullable) receives each variant's
  * time.  It overwrites the context's workspaces.  toi_set_tuning selects a
  * variant directly (default 1: 64-item units, 16 planes per pass). */
-#define TOI_TUNE_VARIANTS 8
+#define TOI_TUNE_VARIANTS 12
 toi_status toi_tune(toi_ctx* ctx, const toi_snapshot* sample, int32_t* variant_out, float* ms_out);
 toi_status toi_set_tuning(toi_ctx* ctx, int32_t variant);
 
@@ -303,9 +306,11 @@ toi_status toi_plan_info(toi_ctx* ctx, double V_out[9], double* omega, double* w
 
 /* Synchronise and report the gridding work of the last gridded snapshot (host
  * outputs, each nullable; diagnostics for measurement, never called by the
- * imaging loop): entries = (work item, 8 x 8 tile, plane group) entries of
- * the bin lists; tiles = (plane group, tile) pairs holding samples (the grid
- * tiles the gridder writes and the row pass reads, per plane of the group);
+ * imaging loop): entries = (work item, bin, plane group) entries of the bin
+ * lists (8 x 8 bins, or 16 x 16 for the variants with bit 3); tiles = (plane
+ * group, 8 x 8 tile) pairs the gridder writes and the row pass reads, per
+ * plane of the group (tiles holding samples, or part of a 16 x 16 bin that
+ * does);
  * tile_rows = (plane group, tile row) pairs holding samples (the row pass
  * writes 8 grid rows of N kept bins per plane of the group for each);
  * units = work units of split bins. */

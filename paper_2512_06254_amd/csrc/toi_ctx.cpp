@@ -217,6 +217,7 @@ toi_status toi_create(const toi_params* pin, void* hip_stream, toi_ctx** out) {
 
     const size_t N = c->N, M = c->M, P = c->P_cap, T = c->T;
     c->NT = c->M / kTile;
+    c->bins_shift = kTileShift;
     c->NG_max = std::max(1, c->P_cap);   // every group holds at least one plane
     c->n_items_max = std::max(1, p.n_row_max * ((p.n_chan + kItemChans - 1) / kItemChans));
     // default: 128 (tile, plane group) entries per work item on average; an
@@ -432,8 +433,8 @@ toi_status toi_plan_info(toi_ctx* c, double V_out[9], double* omega, double* wsu
 toi_status toi_bin_info(toi_ctx* c, int64_t* entries, int64_t* tiles, int64_t* tile_rows, int64_t* units) {
     if (!c) return fail(nullptr, TOI_EINVAL, "toi_bin_info: ctx is NULL");
     DevPlan h{};
-    const int NT = c->NT, words = (NT + 31) / 32;
-    const size_t n_bins = (size_t)c->NG_max * NT * NT;
+    const int NT = c->NT, words = (NT + 31) / 32, NB = c->M >> c->bins_shift;
+    const size_t n_bins = (size_t)c->NG_max * NB * NB;
     int32_t total = 0, cnt[4] = {0, 0, 0, 0};
     hipError_t e = hipMemcpyAsync(&h, c->plan, sizeof(h), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess)

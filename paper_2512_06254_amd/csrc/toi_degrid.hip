@@ -702,6 +702,12 @@ hipError_t launch_degrid(toi_ctx* c, const float* grad_image, const toi_snapshot
     const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;
     const int n_items = s.n_row * n_chunks;
     if (n_items > 0) {
+        // the gather walks bins of 8 x 8 cells: bins of the 16 x 16 variants
+        // are built again at that size from the same records
+        if (c->bins_shift != kTileShift) {
+            const hipError_t e = launch_rebin(c, s, kTileShift);
+            if (e != hipSuccess) return e;
+        }
         const int NT = c->NT;
         const size_t n_samp = (size_t)s.n_row * p.n_chan;
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, c->stream, reinterpret_cast<float*>(c->gx),

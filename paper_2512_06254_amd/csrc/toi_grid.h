@@ -171,21 +171,23 @@ __device__ inline void work_unit_items(const WorkUnit& u, const int32_t* __restr
     }
 }
 
-// Tiles of tile row ty that the footprints of an item's kept samples can
-// touch: [tx0, tx1] (unwrapped; empty when tx1 < tx0).  A footprint starting
-// at row ceil(Y - 4) overlaps the tile row's cells [8 ty, 8 ty + 7] exactly
-// when Y lies in (8 ty - 4, 8 ty + 11]; along the track that is an interval
+// Tiles (bins of S = 2^bsh cells per side) of tile row ty that the footprints
+// of an item's kept samples can touch: [tx0, tx1] (unwrapped; empty when
+// tx1 < tx0).  A footprint starting at row ceil(Y - 4) overlaps the tile
+// row's cells [S ty, S ty + S - 1] exactly when Y lies in
+// (S ty - 4, S ty + S + 3]; along the track that is an interval
 // of the parameter l in [0, 1] (X, Y = start + l (end - start)), over which
 // the footprint start columns ceil(X - 4) give the tiles.  Both windows are
 // widened by 1e-6 cells, so that a sample whose coordinates were rounded
 // differently (or the interval's ends by the reciprocal of the extent) is
 // never left out; a tile too many only costs a visit that finds no sample.  At most nt tiles (one full turn of the periodic grid).
-__device__ inline void item_row_tiles(const ItemBox& b, int ty, int nt, int& tx0, int& tx1) {
+__device__ inline void item_row_tiles(const ItemBox& b, int ty, int nt, int bsh, int& tx0, int& tx1) {
     constexpr double eps = 1e-6;
     const double dx = b.x1 - b.x0;
+    const double S = (double)(1 << bsh);
     double l0 = 0.0, l1 = 1.0;
     if (b.inv_dy != 0.0) {
-        const double la = (8.0 * ty - 4.0 - eps - b.y0) * b.inv_dy, lb = (8.0 * ty + 11.0 + eps - b.y0) * b.inv_dy;
+        const double la = (S * ty - 4.0 - eps - b.y0) * b.inv_dy, lb = (S * ty + S + 3.0 + eps - b.y0) * b.inv_dy;
         l0 = fmax(0.0, fmin(la, lb));
         l1 = fmin(1.0, fmax(la, lb));
     }
@@ -195,8 +197,8 @@ __device__ inline void item_row_tiles(const ItemBox& b, int ty, int nt, int& tx0
         return;
     }
     const double xa = b.x0 + l0 * dx, xb = b.x0 + l1 * dx;
-    tx0 = ((int)ceil(fmin(xa, xb) - eps - 4.0)) >> kTileShift;
-    tx1 = ((int)ceil(fmax(xa, xb) + eps - 4.0) + 7) >> kTileShift;
+    tx0 = ((int)ceil(fmin(xa, xb) - eps - 4.0)) >> bsh;
+    tx1 = ((int)ceil(fmax(xa, xb) + eps - 4.0) + 7) >> bsh;
     tx1 = min(tx1, tx0 + nt - 1);
 }
 
@@ -209,7 +211,7 @@ __device__ inline void item_row_tiles(const ItemBox& b, int ty, int nt, int& tx0
 // lanes of the group must call it; other groups of the wavefront may serve
 // other items (the group's shuffles stay inside the group).
 template <int W = 64, typename F>
-__device__ inline void for_item_bins(const ItemBox& b, int NT, F f) {
+__device__ inline void for_item_bins(const ItemBox& b, int NT, int bsh, F f) {
     static_assert(W >= 2 && W <= 64 && (W & (W - 1)) == 0, "a power-of-two group of lanes");
     const int lane = threadIdx.x & (W - 1);
     const int ny = b.ty1 - b.ty0 + 1, ng = b.g1 - b.g0 + 1;
@@ -217,7 +219,7 @@ __device__ inline void for_item_bins(const ItemBox& b, int NT, F f) {
     for (int r0 = 0; r0 < ny; r0 += W) {
         const int ty = b.ty0 + r0 + lane;
         int tx0 = 1, tx1 = 0;
-        if (r0 + lane < ny) item_row_tiles(b, ty, NT, tx0, tx1);
+        if (r0 + lane < ny) item_row_tiles(b, ty, NT, bsh, tx0, tx1);
         const int cnt = max(0, tx1 - tx0 + 1);
         int incl = cnt;   // inclusive prefix sum over the group's lanes
 #pragma unroll

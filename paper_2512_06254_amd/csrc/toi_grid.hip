@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, c
 // instructions while that pass gave it a whole wavefront per item.
 constexpr int kItemLanes = 8;
 __global__ __launch_bounds__(256) void k_item_bins(const double* __restrict__ uvw, int n_chan, int mode,
-                                                   const DevPlan* __restrict__ P, int M, int NT, double cell_rad,
+                                                   const DevPlan* __restrict__ P, int M, int NT, int bsh, double cell_rad,
                                                    int n_items, ItemBox* __restrict__ items,
                                                    int32_t* __restrict__ bin_count) {
     const int item = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kItemLanes);
@@ -137,9 +137,9 @@ __global__ __launch_bounds__(256) void k_item_bins(const double* __restrict__ uv
         box.inv_dy = fabs(box.y1 - box.y0) > 1e-9 ? 1.0 / (box.y1 - box.y0) : 0.0;
         const double ra = tr.a3 * nlo, rb = tr.a3 * nhi;
         const double ylo = fmin(box.y0, box.y1), yhi = fmax(box.y0, box.y1);
-        // footprint rows [ceil(Y - 4), ceil(Y - 4) + 7] -> tile rows (floor division)
-        box.ty0 = ((int)ceil(ylo - 1e-6 - 4.0)) >> kTileShift;
-        box.ty1 = ((int)ceil(yhi + 1e-6 - 4.0) + 7) >> kTileShift;
+        // footprint rows [ceil(Y - 4), ceil(Y - 4) + 7] -> bin rows (floor division)
+        box.ty0 = ((int)ceil(ylo - 1e-6 - 4.0)) >> bsh;
+        box.ty1 = ((int)ceil(yhi + 1e-6 - 4.0) + 7) >> bsh;
         box.ty1 = min(box.ty1, box.ty0 + NT - 1);
         const int p0 = mode == 3 ? slab_index(fmin(ra, rb), P) : 0, p1 = mode == 3 ? slab_index(fmax(ra, rb), P) : 0;
         box.g0 = group_of_slab(p0, P);
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_item_bins(const double* __restrict__ uv
     }
     // count into bins (each row's tiles from the track)
     const int tiles = NT * NT;
-    for_item_bins<kItemLanes>(box, NT, [&](int g, int ty, int tx) {
+    for_item_bins<kItemLanes>(box, NT, bsh, [&](int g, int ty, int tx) {
         atomicAdd(&bin_count[(size_t)g * tiles + ty * NT + tx], 1);
     });
 }
@@ -288,29 +288,35 @@ __global__ __launch_bounds__(1024) void k_scan_top(int n_blocks, int n_bins, int
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__ count, int n_bins, int NT,
+__global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__ count, int n_bins, int NT, int bsh,
                                                      int32_t* __restrict__ off, int32_t* __restrict__ cursor,
                                                      int32_t* __restrict__ order, int32_t* __restrict__ aux,
                                                      uint32_t* __restrict__ tile_bits,
                                                      uint32_t* __restrict__ row_bits,
                                                      const DevPlan* __restrict__ P) {
-    // The workgroup's bins are whole tile rows (NT and kScanBlock are powers
-    // of two, NT <= kScanBlock): their occupancy words, at most 512 (one per
-    // row when NT < 32), are gathered in LDS from the counts already loaded,
+    // NT bins of 2^bsh cells per axis; the masks are per kTile x kTile tile,
+    // sub x sub mask tiles per bin (sub = 1 or 2; with sub = 2 at least 16
+    // bins per axis).  The workgroup's bins are whole bin rows (NT and
+    // kScanBlock are powers of two, NT <= kScanBlock): the occupancy words of
+    // their mask rows, at most 512 (one per row when there are fewer than 32
+    // mask tiles per row), are gathered in LDS from the counts already loaded,
     // and so are the rows' row_bits words, at most 64 (one per plane group
-    // when NT < 32, at most 4096 / 8 / 8 groups), added with one global atomic
-    // per word (an atomic per non-empty tile word on a handful of shared words
-    // serialised the workgroups: 33 us per snapshot).
+    // when there are fewer than 32 mask tiles per row, at most 4096 / 8 / 8
+    // groups), added with one global atomic per word (an atomic per non-empty
+    // tile word on a handful of shared words serialised the workgroups: 33 us
+    // per snapshot).
     constexpr int kMaxWords = kScanBlock / 8, kMaxRowWords = kScanBlock / 64;
     __shared__ int32_t hist[32], start[32];
     __shared__ uint32_t tbs[kMaxWords], rbs[kMaxRowWords];
     const int tiles = NT * NT;
     if (blockIdx.x * kScanBlock >= P->ng * tiles) return;   // unused plane groups: never read
-    const int words = (NT + 31) / 32;
-    const int row0 = blockIdx.x * (kScanBlock / NT);        // the workgroup's rows [row0, row0 + nrows)
+    const int sub = 1 << (bsh - kTileShift), NTm = NT * sub;  // mask tiles per bin side, per axis
+    const int words = (NTm + 31) / 32;
+    const int row0 = blockIdx.x * (kScanBlock / NT);        // the workgroup's bin rows [row0, row0 + nrows)
     const int nrows = min(kScanBlock / NT, n_bins / NT - row0);
-    const int nwords = nrows * words;                       // tile_bits words of those rows (contiguous)
-    const int wbase = (row0 / NT) * words + ((row0 % NT) >> 5);   // first row_bits word
+    const int mrow0 = row0 * sub;                           // and mask rows [mrow0, mrow0 + nrows sub)
+    const int nwords = nrows * sub * words;                 // tile_bits words of those rows (contiguous)
+    const int wbase = (mrow0 / NTm) * words + ((mrow0 % NTm) >> 5);   // first row_bits word
     if (threadIdx.x < 32) hist[threadIdx.x] = 0;
     if (threadIdx.x < kMaxRowWords) rbs[threadIdx.x] = 0;
     for (int w = threadIdx.x; w < nwords; w += blockDim.x) tbs[w] = 0;
@@ -329,10 +335,14 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
             cursor[base + j] = o;
             if (c[j] > 0) {
                 atomicAdd(&hist[31 - __clz(c[j])], 1);
-                const int r = (base + j) / NT, tx = (base + j) % NT;   // global tile row, column
-                atomicOr(&tbs[(r - row0) * words + (tx >> 5)], 1u << (tx & 31));
+                const int r = (base + j) / NT, tx = (base + j) % NT;   // global bin row, column
                 const int g = r / NT, ty = r % NT;
-                atomicOr(&rbs[g * words + (ty >> 5) - wbase], 1u << (ty & 31));
+                const uint32_t cols = ((1u << sub) - 1u) << ((tx * sub) & 31);   // one word (sub <= 2)
+                for (int a = 0; a < sub; ++a) {                        // mask rows r sub + a = g NTm + ty sub + a
+                    atomicOr(&tbs[(r * sub + a - mrow0) * words + ((tx * sub) >> 5)], cols);
+                    const int mty = ty * sub + a;
+                    atomicOr(&rbs[g * words + (mty >> 5) - wbase], 1u << (mty & 31));
+                }
             }
         }
     }
@@ -342,7 +352,7 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
         start[threadIdx.x] = h ? atomicAdd(&aux[kAuxCursors + kAuxStride * threadIdx.x], h) : 0;
         hist[threadIdx.x] = 0;
     }
-    for (int w = threadIdx.x; w < nwords; w += blockDim.x) tile_bits[(size_t)row0 * words + w] = tbs[w];
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) tile_bits[(size_t)mrow0 * words + w] = tbs[w];
     if (threadIdx.x < kMaxRowWords && rbs[threadIdx.x]) atomicOr(&row_bits[wbase + threadIdx.x], rbs[threadIdx.x]);
     __syncthreads();
 #pragma unroll
@@ -357,7 +367,8 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
 // heaviest buckets are listed unit by unit, ceil(count / U) units each
 // (U = 2^unit_shift items, from the tuning): every bucket from the top down to
 // unit_shift (at least U items per bin) while the units of the buckets taken
-// fit in kSplitSlots.
+// fit in max_units (kSplitSlots partial tiles of 8 x 8 cells: a quarter as
+// many units of 16 x 16 bins).
 // The cut falls between whole buckets, so which bins are split depends only on
 // the bin counts, not on the order of the bins inside a bucket; the bins of
 // the buckets below the cut run whole.  The split bins are the first entries
@@ -365,12 +376,12 @@ __global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__
 // cnt[2] = bins they cover.
 __global__ __launch_bounds__(1024) void k_units(const DevPlan* __restrict__ P, const int32_t* __restrict__ count,
                                                 const int32_t* __restrict__ order, const int32_t* __restrict__ aux,
-                                                int4* __restrict__ units, int32_t* __restrict__ cnt) {
+                                                int max_units, int4* __restrict__ units, int32_t* __restrict__ cnt) {
     const int ushift = P->unit_shift, U = 1 << ushift;
     int n_big = 0, n_units = 0;
     for (int k = 31; k >= ushift; --k) {       // uniform over the workgroup
         const int u = aux[kAuxUnits + kAuxStride * k];
-        if (n_units + u > kSplitSlots) break;
+        if (n_units + u > max_units) break;
         n_units += u;
         n_big += aux[kAuxBuckets + kAuxStride * k];
     }
@@ -399,14 +410,14 @@ __global__ __launch_bounds__(1024) void k_units(const DevPlan* __restrict__ P, c
 // items at once (one item per wavefront: 43 us per MeerKAT-shaped snapshot,
 // four: 22 us, eight: 20.5 us).
 constexpr int kFillLanes = 8;
-__global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ items, int n_items, int NT,
+__global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ items, int n_items, int NT, int bsh,
                                                   int bin_cap, int32_t* __restrict__ cursor,
                                                   int32_t* __restrict__ list) {
     const int item = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kFillLanes);
     if (item >= n_items) return;
     const ItemBox box = items[item];
     const int tiles = NT * NT;
-    for_item_bins<kFillLanes>(box, NT, [&](int g, int ty, int tx) {   // the same bins as the count in k_item_bins
+    for_item_bins<kFillLanes>(box, NT, bsh, [&](int g, int ty, int tx) {   // the same bins as the count in k_item_bins
         const int pos = atomicAdd(&cursor[(size_t)g * tiles + ty * NT + tx], 1);
         if (pos < bin_cap) list[pos] = item;
     });
@@ -831,15 +842,242 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
     }
 }
 
+// Matrix-core gridder over bins of 16 x 16 cells (the tuning's 16 x 16 bin
+// variants; 16 planes per pass, operands split as hi + lo in fp16 and
+// accumulated in FP32 exactly as in k_grid_tiles_mfma<32>).  One wavefront per
+// bin holds 256 cells x 32 columns in eight 32 x 32 accumulator blocks:
+// block (bx, by) covers the cells x in [8 bx, 8 bx + 8), y in [4 by, 4 by + 4),
+// its A row i is cell (8 bx + i mod 8, 4 by + i / 8), and its register r of
+// lane l holds cell (8 bx + 4 (l / 32) + r mod 4, 4 by + r / 4), column l mod
+// 32.  A sample meets about 2.1 bins instead of 3.5 tiles of 8 x 8 cells, so
+// its kernel weights and Chebyshev values are staged, and the steps of the
+// walk formed, less often; the blocks that none of a step's 16 samples
+// touches are skipped (a uniform branch per block).  (Two wavefronts per bin,
+// each with half the accumulators and half the staging, allow three
+// wavefronts per SIMD instead of two, but the barriers of the shared staging
+// made the pass slower: 0.78 against 0.67 ms.)
+// Staging in LDS, rows of 68 floats, one column per sample slot: T rows
+// 0..15, x rows (bin columns 0..15) at rows 16..31, 7 spare rows, y rows (bin
+// rows 0..15) at rows 39..54, Re and Im of g x at rows 55 and 56, 5 spare
+// rows, the slots' block masks (bytes) in row 62.  A sample's kernel weights
+// are evaluated at its 8 footprint cells only: the footprint start d relative
+// to the bin lies in [-7, 15], and the weights are stored at x (y) rows
+// d .. d + 7 after rows 0..15 of the slot were set to zero.  Rows below 0 or
+// above 15 fall on T rows 9..15 and the spare rows (x), or on the spare rows,
+// the g x rows and the spare rows after them (y), all of which the lane
+// writes afterwards or nobody reads, and only in its own slot's column.
+__global__ __launch_bounds__(64, 2) void k_grid_bins16(
+    const SampleRec* __restrict__ recs, int n_chan, const DevPlan* __restrict__ P, int M, int NT,
+    const int32_t* __restrict__ bin_off, const int32_t* __restrict__ list, int bin_cap,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ cnt, const int4* __restrict__ units,
+    float* __restrict__ split_part, float2* __restrict__ grid) {
+    constexpr int S = 16, R = kBin16Stride;      // bin side, LDS row stride (floats)
+    constexpr int rT = 0, rX = 16, rY = 39, rV = 55, rM = 62;
+    static_assert(rM < kBin16Rows, "staging rows");
+    typedef float f32x16 __attribute__((ext_vector_type(16)));
+    auto ld8 = [](const float* p, float* o) __attribute__((always_inline)) {
+        const float4 u = reinterpret_cast<const float4*>(p)[0], w = reinterpret_cast<const float4*>(p)[1];
+        o[0] = u.x; o[1] = u.y; o[2] = u.z; o[3] = u.w; o[4] = w.x; o[5] = w.y; o[6] = w.z; o[7] = w.w;
+    };
+    extern __shared__ float lds[];
+    const int tiles = NT * NT;
+    if (P->status & kStatusFatal) return;
+    const int lane = threadIdx.x;
+    const int n_chunks = (n_chan + kItemChans - 1) / kItemChans;
+    float vs = 1.f, ivs = 1.f;   // fp16 scale of the values, as in k_grid_tiles_mfma<32>
+    {
+        const float vmax = __uint_as_float(P->vmax_bits);
+        if (vmax > 0.f) {
+            int ex;
+            (void)frexpf(vmax, &ex);
+            ex = min(max(ex, -100), 127);
+            vs = ldexpf(1.f, 14 - ex);
+            ivs = ldexpf(1.f, ex - 14);
+        }
+    }
+    // walk operands of this lane: A row i = lane mod 32, samples 8 h .. 8 h + 7
+    // of a step; B column i: order i mod 16, Re (i < 16) or Im
+    const int h = lane >> 5, i = lane & 31;
+    const float* pT = lds + (rT + (i & 15)) * R + 8 * h;
+    const float* pV = lds + (rV + (i >> 4)) * R + 8 * h;
+    const float* pX = lds + (rX + (i & 7)) * R + 8 * h;    // + 8 R for bx = 1
+    const float* pY = lds + (rY + (i >> 3)) * R + 8 * h;   // + 4 by R
+    const uint8_t* pM = reinterpret_cast<const uint8_t*>(lds + rM * R);
+    const int n_units = work_unit_count(cnt);
+    for (int ob = blockIdx.x; ob < n_units; ob += gridDim.x) {
+    const WorkUnit un = work_unit(ob, units, order, cnt);
+    const int bid = un.bin;
+    const int g = bid / tiles, tile = bid % tiles;
+    if (g >= P->ng) continue;
+    int b0, b1;
+    work_unit_items(un, bin_off, bin_cap, P->unit_shift, b0, b1);
+    if (b1 <= b0 && un.parts == 1) continue;   // every unit of a split bin reports in
+    int s0, s1, k0, k1;
+    group_range(g, P, s0, s1, k0, k1);         // one slab per group (max_sg = 1)
+    const int nk = k1 - k0;                    // <= 16 planes
+    const int tx = tile % NT, ty = tile / NT;
+    f32x16 acc[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[b] = f32x16{};
+    auto load_rec = [&](int item_, float4& ra, float4& rb) __attribute__((always_inline)) {
+        const int c = (item_ % n_chunks) * kItemChans + lane;
+        if (c < n_chan) {
+            const float4* src = reinterpret_cast<const float4*>(recs + (size_t)(item_ / n_chunks) * n_chan + c);
+            ra = src[0];
+            rb = src[1];
+        } else {
+            ra = make_float4(__int_as_float(-1), 0.f, 4.f, 4.f);
+            rb = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    float4 ra, rb, ra2, rb2;
+    if (b0 < b1) load_rec(list[b0], ra, rb);
+    if (b0 + 1 < b1) load_rec(list[b0 + 1], ra2, rb2);
+    for (int it = b0; it < b1; ++it) {
+        const int pk = __float_as_int(ra.x), sp = __float_as_int(ra.y);
+        const int ix = pk & 8191, iy = (pk >> 13) & 8191;
+        const float ox = ra.z, oy = ra.w, ss = rb.x, vr = rb.y, vi = rb.z;
+        const int ddx = (ix - tx * S) & (M - 1), ddy = (iy - ty * S) & (M - 1);
+        const bool act = pk >= 0 && (sp >= s0 && sp < s1) && (ddx < S || ddx >= M - 7) && (ddy < S || ddy >= M - 7);
+        ra = ra2;
+        rb = rb2;
+        if (it + 2 < b1) load_rec(list[it + 2], ra2, rb2);   // the records two items ahead
+        const uint64_t amask = __ballot(act);
+        if (amask == 0) continue;
+        const int n_act = __popcll(amask), n4 = (n_act + 15) & ~15;
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(amask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)amask, 0));
+        const int q = act ? below : n_act + (lane - below);
+        if (q < n4) {
+            // footprint starts relative to the bin, in [-7, 15] (padding slots:
+            // 0, with finite weights and g x = 0)
+            const int dx = act ? (ddx < S ? ddx : ddx - M) : 0, dy = act ? (ddy < S ? ddy : ddy - M) : 0;
+            const float oxa = act ? ox : 0.f, oya = act ? oy : 0.f, ssa = act ? ss : 0.f;
+            float* col = lds + q;
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                col[(rX + r) * R] = 0.f;
+                col[(rY + r) * R] = 0.f;
+            }
+            float* cx = col + (rX + dx) * R;
+            float* cy = col + (rY + dy) * R;
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {   // footprint position p: z = (p - o) / 4 in [-1, 1)
+                cx[p * R] = es_kernel(((float)p - oxa) * 0.25f);
+                cy[p * R] = es_kernel(((float)p - oya) * 0.25f);
+            }
+            float t, tm1;
+            cheb_start(ssa, k0, t, tm1);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                col[(rT + k) * R] = t;
+                const float tn = 2.f * ssa * t - tm1;
+                tm1 = t;
+                t = tn;
+            }
+            col[rV * R] = act ? vr * vs : 0.f;
+            col[(rV + 1) * R] = act ? vi * vs : 0.f;
+            // blocks touched: x half bx where [dx, dx + 8) meets [8 bx, 8 bx + 8),
+            // y quarter by where [dy, dy + 8) meets [4 by, 4 by + 4); bit 4 bx + by
+            uint32_t m = 0;
+            if (act) {
+                uint32_t my = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) my |= (dy <= 4 * b + 3 && dy >= 4 * b - 7) ? (1u << b) : 0u;
+                m = (dx < 8 ? my : 0u) | (dx >= 1 ? my << 4 : 0u);
+            }
+            reinterpret_cast<uint8_t*>(lds + rM * R)[q] = (uint8_t)m;
+        }
+        lds_order();                                        // staging writes precede the walk's reads
+        // the block masks of the item's steps (at most four), uniform; slots
+        // past n4 hold older masks and belong to no step
+        uint32_t sm[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const uint4 mw = reinterpret_cast<const uint4*>(pM)[s4];
+            uint32_t m = mw.x | mw.y | mw.z | mw.w;
+            m |= m >> 16;
+            m |= m >> 8;
+            sm[s4] = __builtin_amdgcn_readfirstlane(m & 0xffu);
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int q0 = 16 * s4;
+            if (q0 >= n4) break;
+            const uint32_t m = sm[s4];
+            // every operand of the step is read up front (one wait for all of
+            // them; the blocks below only form products)
+            float t[8], v[8], x[2][8], y[4][8];
+            ld8(pT + q0, t);
+            ld8(pV + q0, v);
+#pragma unroll
+            for (int bx = 0; bx < 2; ++bx) ld8(pX + bx * 8 * R + q0, x[bx]);
+#pragma unroll
+            for (int by = 0; by < 4; ++by) ld8(pY + by * 4 * R + q0, y[by]);
+            f16x8_t bh, bl;
+            split_prod_f16x8(t, v, bh, bl);
+#pragma unroll
+            for (int bx = 0; bx < 2; ++bx)
+#pragma unroll
+                for (int by = 0; by < 4; ++by) {
+                    if (!(m & (1u << (4 * bx + by)))) continue;
+                    f16x8_t ah, al;
+                    split_prod_f16x8(x[bx], y[by], ah, al);
+                    f32x16& a = acc[4 * bx + by];
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, a, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, a, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, a, 0, 0, 0);
+                }
+        }
+        lds_order();                                        // the walk's reads precede the next staging writes
+    }
+    // write-out, half a bin (rows 8 hb .. 8 hb + 7) at a time: accumulators ->
+    // LDS [cell][33] -> planes of the group in HBM (or the partial tile)
+    float* wo = lds;
+    const int col = lane & 31;
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+#pragma unroll
+        for (int bx = 0; bx < 2; ++bx)
+#pragma unroll
+            for (int byl = 0; byl < 2; ++byl)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int cx = 8 * bx + 4 * (lane >> 5) + (r & 3), cyl = 4 * byl + (r >> 2);
+                    wo[(cyl * S + cx) * 33 + col] = acc[4 * bx + 2 * hb + byl][r] * ivs;
+                }
+        lds_order();
+        if (un.parts > 1) {   // partial tile [plane][cell], cell = y 16 + x, added up by k_split_sum
+            float2* part = reinterpret_cast<float2*>(split_part + (size_t)ob * (4 * kPartFloats));
+            for (int e = threadIdx.x; e < nk * 128; e += blockDim.x) {
+                const int pl = e / 128, cell = e % 128;
+                const float* w = wo + cell * 33;
+                part[pl * 256 + hb * 128 + cell] = make_float2(w[pl], w[16 + pl]);
+            }
+        } else {
+            for (int e = threadIdx.x; e < nk * 128; e += blockDim.x) {
+                const int pl = e / 128, cell = e % 128;
+                const int ly = cell / S, lx = cell % S;
+                const int pg = s0 * P->K + k0 + pl;    // global plane index
+                const float* w = wo + cell * 33;
+                grid[((size_t)pg * M + ty * S + 8 * hb + ly) * M + tx * S + lx] = make_float2(w[pl], w[16 + pl]);
+            }
+        }
+        lds_order();                               // the write-out reads precede the next writes to LDS
+    }
+    }
+}
+
 // Tiles of split bins: the partial tiles of a bin's units (consecutive unit
 // slots from part 0) added in part order, written to the grid.  One workgroup
 // per split bin at a time.
 constexpr int kSplitSumWorkgroups = 1024;
-__global__ __launch_bounds__(256) void k_split_sum(const DevPlan* __restrict__ P, int M, int NT,
+__global__ __launch_bounds__(256) void k_split_sum(const DevPlan* __restrict__ P, int M, int NT, int bsh,
                                                    const int4* __restrict__ units, const int32_t* __restrict__ cnt,
                                                    const float* __restrict__ split_part, float2* __restrict__ grid) {
     if (P->status & kStatusFatal) return;
     const int n_split = cnt[1], tiles = NT * NT;
+    const int S = 1 << bsh, cells = S * S;                                  // a bin of S x S cells
+    const size_t part_floats = (size_t)kPartFloats << (2 * (bsh - kTileShift));
     for (int ob = blockIdx.x; ob < n_split; ob += gridDim.x) {
         const int4 u = units[ob];
         if (u.z <= 1 || u.y != 0) continue;   // whole bins and parts after the first
@@ -848,16 +1086,16 @@ __global__ __launch_bounds__(256) void k_split_sum(const DevPlan* __restrict__ P
         int s0, s1, k0, k1;
         group_range(g, P, s0, s1, k0, k1);
         const int nk = k1 - k0, tx = tile % NT, ty = tile / NT;
-        for (int i = threadIdx.x; i < nk * 64; i += blockDim.x) {
+        for (int i = threadIdx.x; i < nk * cells; i += blockDim.x) {
             float2 v = make_float2(0.f, 0.f);
             for (int p = 0; p < u.z; ++p) {
-                const float2 a = reinterpret_cast<const float2*>(split_part + (size_t)(ob + p) * kPartFloats)[i];
+                const float2 a = reinterpret_cast<const float2*>(split_part + (size_t)(ob + p) * part_floats)[i];
                 v.x += a.x;
                 v.y += a.y;
             }
-            const int pl = i / 64, cell = i % 64;
+            const int pl = i / cells, cell = i % cells;
             const int pg = s0 * P->K + k0 + pl;
-            grid[((size_t)pg * M + ty * kTile + cell / kTile) * M + tx * kTile + cell % kTile] = v;
+            grid[((size_t)pg * M + ty * S + cell / S) * M + tx * S + cell % S] = v;
         }
     }
 }
@@ -869,72 +1107,87 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
 
 constexpr int kBinSortBlocks = 512, kBinSortWaveGroups = 2048;
 
-hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
+// The bin pipeline with bins of 2^bsh cells per side; the record pass too when
+// records is set (otherwise the records and items of the last launch_bin of
+// this snapshot are reused).
+static hipError_t bin_pipeline(toi_ctx* c, const toi_snapshot& s, int bsh, bool records) {
     const toi_params& p = c->p;
-    const int M = c->M, NT = c->NT;
+    const int M = c->M, NB = M >> bsh;
     const double cell = p.cell_deg * kPi / 180.0;
     const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;
     const int n_items = s.n_row * n_chunks;
-    const int n_bins = c->NG_max * NT * NT;
-    {
-        StageTimer timer(c, TOI_STAGE_BIN);
-        const int words = (NT + 31) / 32;
-        const int n_scan = (n_bins + kScanBlock - 1) / kScanBlock;
-        hipLaunchKernelGGL(k_scan_clear, dim3(256), dim3(256), 0, c->stream, c->plan, c->bin_count, n_bins, NT * NT,
-                           c->bin_aux, c->row_bits, c->NG_max * words, words);
-        if (n_items > 0)
-            hipLaunchKernelGGL(k_items, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw,
-                               (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2,
-                               (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask,
-                               (int)vec4_ok(s.vis, s.flag, s.weight, p.n_corr), p.mode, c->plan, M,
-                               cell, n_items, c->items, c->recs);
-        if (n_items > 0)
-            hipLaunchKernelGGL(k_item_bins, dim3((n_items + 256 / kItemLanes - 1) / (256 / kItemLanes)), dim3(256), 0,
-                               c->stream, s.uvw, p.n_chan, p.mode, c->plan, M, NT, cell, n_items, c->items,
-                               c->bin_count);
-        hipLaunchKernelGGL(k_scan_local, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, c->plan,
-                           NT * NT, c->items, n_items, c->bin_off, c->bin_aux);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, n_scan, n_bins, c->bin_cap, c->plan,
-                           c->bin_aux, c->bin_off, c->scratch_i);
-        hipLaunchKernelGGL(k_scan_apply, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, NT,
-                           c->bin_off, c->bin_cursor, c->bin_order, c->bin_aux, c->tile_bits, c->row_bits,
-                           c->plan);
-        hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->plan, c->bin_count, c->bin_order,
-                           c->bin_aux, c->units, c->scratch_i);
-        if (n_items > 0) {
-            hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 256 / kFillLanes - 1) / (256 / kFillLanes)), dim3(256), 0,
-                               c->stream, c->items, n_items, NT,
-                               c->bin_cap, c->bin_cursor, c->bin_list);
-            hipLaunchKernelGGL(k_bin_sort_block, dim3(kBinSortBlocks), dim3(1024), 0, c->stream, c->plan,
-                               c->bin_order, c->bin_aux, c->bin_off, c->bin_list);
-            hipLaunchKernelGGL(k_bin_sort_wave, dim3(kBinSortWaveGroups), dim3(256), 0, c->stream, c->plan,
-                               c->bin_order, c->scratch_i, c->bin_aux, c->bin_off, c->bin_list);
-        }
+    const int n_bins = c->NG_max * NB * NB;
+    const int words = (c->NT + 31) / 32;   // row_bits words per plane group (mask tiles)
+    const int n_scan = (n_bins + kScanBlock - 1) / kScanBlock;
+    const int max_units = kSplitSlots >> (2 * (bsh - kTileShift));
+    c->bins_shift = bsh;
+    hipLaunchKernelGGL(k_scan_clear, dim3(256), dim3(256), 0, c->stream, c->plan, c->bin_count, n_bins, NB * NB,
+                       c->bin_aux, c->row_bits, c->NG_max * words, words);
+    if (n_items > 0 && records)
+        hipLaunchKernelGGL(k_items, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw,
+                           (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2,
+                           (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask,
+                           (int)vec4_ok(s.vis, s.flag, s.weight, p.n_corr), p.mode, c->plan, M,
+                           cell, n_items, c->items, c->recs);
+    if (n_items > 0)
+        hipLaunchKernelGGL(k_item_bins, dim3((n_items + 256 / kItemLanes - 1) / (256 / kItemLanes)), dim3(256), 0,
+                           c->stream, s.uvw, p.n_chan, p.mode, c->plan, M, NB, bsh, cell, n_items, c->items,
+                           c->bin_count);
+    hipLaunchKernelGGL(k_scan_local, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, c->plan,
+                       NB * NB, c->items, n_items, c->bin_off, c->bin_aux);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, c->stream, n_scan, n_bins, c->bin_cap, c->plan,
+                       c->bin_aux, c->bin_off, c->scratch_i);
+    hipLaunchKernelGGL(k_scan_apply, dim3(n_scan), dim3(1024), 0, c->stream, c->bin_count, n_bins, NB, bsh,
+                       c->bin_off, c->bin_cursor, c->bin_order, c->bin_aux, c->tile_bits, c->row_bits,
+                       c->plan);
+    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->plan, c->bin_count, c->bin_order,
+                       c->bin_aux, max_units, c->units, c->scratch_i);
+    if (n_items > 0) {
+        hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 256 / kFillLanes - 1) / (256 / kFillLanes)), dim3(256), 0,
+                           c->stream, c->items, n_items, NB, bsh,
+                           c->bin_cap, c->bin_cursor, c->bin_list);
+        hipLaunchKernelGGL(k_bin_sort_block, dim3(kBinSortBlocks), dim3(1024), 0, c->stream, c->plan,
+                           c->bin_order, c->bin_aux, c->bin_off, c->bin_list);
+        hipLaunchKernelGGL(k_bin_sort_wave, dim3(kBinSortWaveGroups), dim3(256), 0, c->stream, c->plan,
+                           c->bin_order, c->scratch_i, c->bin_aux, c->bin_off, c->bin_list);
     }
     return hipGetLastError();
 }
 
+hipError_t launch_bin(toi_ctx* c, const toi_snapshot& s) {
+    StageTimer timer(c, TOI_STAGE_BIN);
+    return bin_pipeline(c, s, bin_shift_of(c->tuning, c->M), true);
+}
+
+hipError_t launch_rebin(toi_ctx* c, const toi_snapshot& s, int bin_shift) {
+    StageTimer timer(c, TOI_STAGE_BIN);
+    return bin_pipeline(c, s, bin_shift, false);
+}
+
 hipError_t launch_gridder(toi_ctx* c, const toi_snapshot& s) {
     const toi_params& p = c->p;
-    const int M = c->M, NT = c->NT;
+    const int M = c->M, bsh = c->bins_shift, NB = M >> bsh;
     const int n_chunks = (p.n_chan + kItemChans - 1) / kItemChans;
     const int n_items = s.n_row * n_chunks;
-    const int n_bins = c->NG_max * NT * NT;
+    const int n_bins = c->NG_max * NB * NB;
     if (n_items == 0) return hipGetLastError();
     StageTimer timer(c, TOI_STAGE_GRID);
-    const GridShape gs = grid_shape(c->tuning);
+    const GridShape gs = grid_shape(c->tuning, bsh);
     // a fixed grid of single-wave workgroups takes the work units in turn
-    const int mblocks = unit_workgroups(n_items, n_bins);
+    // (a 16 x 16 bin holds about as many items as four 8 x 8 tiles)
+    const int mblocks = unit_workgroups(n_items >> (2 * (bsh - kTileShift)), n_bins);
 #define TOI_MFMA_ARGS                                                                                      \
-    dim3(mblocks), dim3(64), gs.lds_bytes, c->stream, c->recs, p.n_chan, c->plan, M, NT, c->bin_off, c->bin_list, \
+    dim3(mblocks), dim3(64), gs.lds_bytes, c->stream, c->recs, p.n_chan, c->plan, M, NB, c->bin_off, c->bin_list, \
         c->bin_cap, c->bin_order, c->scratch_i, c->units, c->split_part, c->grid
-    if (gs.gp > 8)
+    if (bsh > kTileShift)
+        hipLaunchKernelGGL(k_grid_bins16, TOI_MFMA_ARGS);
+    else if (gs.gp > 8)
         hipLaunchKernelGGL((k_grid_tiles_mfma<32>), TOI_MFMA_ARGS);
     else
         hipLaunchKernelGGL((k_grid_tiles_mfma<16>), TOI_MFMA_ARGS);
 #undef TOI_MFMA_ARGS
-    hipLaunchKernelGGL(k_split_sum, dim3(kSplitSumWorkgroups), dim3(256), 0, c->stream, c->plan, M, NT, c->units,
-                       c->scratch_i, c->split_part, c->grid);
+    hipLaunchKernelGGL(k_split_sum, dim3(kSplitSumWorkgroups), dim3(256), 0, c->stream, c->plan, M, NB, bsh,
+                       c->units, c->scratch_i, c->split_part, c->grid);
     return hipGetLastError();
 }
 

@@ -47,6 +47,10 @@ struct DevPlan {
 
 // Binned gridding: grid tiles of kTile x kTile cells, work items of kItemChans
 // channels of one row, up to kGroupPlanes planes accumulated per tile pass.
+// The occupancy masks of the FFT passes are always kept per kTile x kTile
+// tile; the bins of the gridder are tiles of 2^bin_shift cells per side,
+// bin_shift = kTileShift or kTileShift + 1 (the tuning's 16 x 16 bins, each
+// four mask tiles).
 constexpr int kTile = 8, kTileShift = 3;
 constexpr int kItemChans = 64;
 constexpr int kGroupPlanes = 16;   // largest plane group held in LDS
@@ -72,6 +76,8 @@ constexpr int kAuxBuckets = 0, kAuxCursors = 1, kAuxUnits = 2, kAuxTotals = 32 *
 // by a workgroup in LDS up to kSortLds items, beyond that in place in HBM.
 constexpr int kSortShift = 6, kBlockSortShift = 8, kSortLds = 16384;
 constexpr int kPartFloats = 64 * 32;   // one partial tile: 64 cells x up to 16 complex planes
+// (a 16 x 16 bin's partial tile takes four such slots, so at most
+// kSplitSlots / 4 of its units are listed)
 constexpr int kAdjAbsmaxParts = 1024;  // workgroups of the adjoint's image-gradient maximum
 
 // Gridder variant chosen by the autotuner (toi_tune / toi_set_tuning):
@@ -80,24 +86,38 @@ constexpr int kAdjAbsmaxParts = 1024;  // workgroups of the adjoint's image-grad
 // shorter ones balance the heaviest tiles across more wavefronts);
 // bit 2: the plane schedule, 8 planes per pass over a tile on the FP32 matrix
 // cores (v_mfma_f32_16x16x1f32, one instruction per sample) instead of 16
-// planes per pass on the bf16 matrix cores with split operands.
-constexpr int kTuneUnitMask = 3, kTuneEightPlanes = 4;
-constexpr int kTuneDefault = 1;   // 64-item units, 16 planes per pass
+// planes per pass on the fp16 matrix cores with split operands;
+// bit 3 (with bit 2 clear; variants 8 .. 11): bins of 16 x 16 cells, one
+// wavefront per bin (each sample visits about 2.1 bins instead of 3.5 tiles
+// of 8 x 8; used where the grid has at least 256 cells per side).
+constexpr int kTuneUnitMask = 3, kTuneEightPlanes = 4, kTuneBin16 = 8;
+constexpr int kTuneDefault = 1;   // 64-item units, 16 planes per pass, 8 x 8 bins
 constexpr size_t kLdsBytes = 160 * 1024;   // per workgroup on gfx950
 
-// Launch shape of the tile gridder for a variant: one wavefront per work unit,
-// LDS for staging (rows 8 x 68, 8 x 64, 2 x 64, gp x 68) and then the
-// write-out buffer [64][2 gp + 1].
+// Bin side of a variant on a grid of side M: 2^bin_shift cells.
+inline int bin_shift_of(int tuning, int M) {
+    return ((tuning & kTuneBin16) && !(tuning & kTuneEightPlanes) && M >= 256) ? kTileShift + 1 : kTileShift;
+}
+
+// Launch shape of the tile gridder for a variant: one wavefront per work unit.
+// 8 x 8 bins: LDS for staging (rows 8 x 68, 8 x 64, 2 x 64, gp x 68) and then
+// the write-out buffer [64][2 gp + 1]; 16 x 16 bins: 63 staging rows of 68
+// floats, then the write-out buffer of half a bin [128][33].
 struct GridShape {
     int gp, max_sg, unit_shift;
     size_t lds_bytes;
 };
-inline GridShape grid_shape(int tuning) {
+constexpr int kBin16Rows = 63, kBin16Stride = 68;
+inline GridShape grid_shape(int tuning, int bin_shift = kTileShift) {
     GridShape g;
     g.gp = (tuning & kTuneEightPlanes) ? 8 : kGroupPlanes;
     g.max_sg = 1;   // one slab per plane group (the gridder and the adjoint gather rely on it)
     g.unit_shift = 5 + (tuning & kTuneUnitMask);
-    const size_t stage = (size_t)8 * 68 + 8 * 64 + 2 * 64 + (size_t)g.gp * 68, wout = (size_t)64 * (2 * g.gp + 1);
+    size_t stage = (size_t)8 * 68 + 8 * 64 + 2 * 64 + (size_t)g.gp * 68, wout = (size_t)64 * (2 * g.gp + 1);
+    if (bin_shift > kTileShift) {
+        stage = (size_t)kBin16Rows * kBin16Stride;
+        wout = (size_t)128 * 33;
+    }
     g.lds_bytes = (stage > wout ? stage : wout) * sizeof(float);
     return g;
 }
@@ -177,6 +197,7 @@ struct toi_ctx {
     // workspace (device)
     float2* grid;         // [P_cap][M][M]   only tiles with samples are written
     int NT;               // grid tiles per axis (M / kTile)
+    int bins_shift;       // bin side 2^bins_shift of the bins last built (launch_bin)
     int NG_max;           // plane-group capacity
     int n_items_max;      // work items capacity (n_row_max * chunks)
     toi::ItemBox* items;  // [n_items_max]
@@ -245,6 +266,8 @@ toi_status hip_check(toi_ctx* ctx, hipError_t e, const char* what);
 hipError_t launch_prep(toi_ctx* ctx, const toi_snapshot& s);
 hipError_t launch_grid(toi_ctx* ctx, const toi_snapshot& s);      // launch_bin + launch_gridder
 hipError_t launch_bin(toi_ctx* ctx, const toi_snapshot& s);       // records, bins, work units
+// bins (not the records) again, with bins of 2^bin_shift cells per side
+hipError_t launch_rebin(toi_ctx* ctx, const toi_snapshot& s, int bin_shift);
 hipError_t launch_gridder(toi_ctx* ctx, const toi_snapshot& s);   // the tile gridder (+ split sums)
 hipError_t launch_image(toi_ctx* ctx, float* image_out, float* tplane_out);
 hipError_t launch_degrid(toi_ctx* ctx, const float* grad_image, const toi_snapshot& s,

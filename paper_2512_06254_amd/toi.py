@@ -93,7 +93,7 @@ _SIGS = {
     "toi_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
 
-TUNE_VARIANTS = 8
+TUNE_VARIANTS = 12
 
 STAGES = ("prep", "bin", "grid", "fft_rows", "fft_cols", "reproject", "tlisi", "degrid", "batch", "detect")
 

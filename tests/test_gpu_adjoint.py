@@ -54,6 +54,33 @@ def test_adjoint_matches_oracle(n_slab, K, dense):
     im.close()
 
 
+def test_adjoint_after_a_16x16_bin_forward():
+    # forward gridded with 16 x 16 bins (variant 9, 256-cell grid); the gather
+    # walks 8 x 8 bins, which toi_degrid builds again from the forward's records
+    import torch
+    from paper_2512_06254_amd import toi as T
+    wl, snap = _setup(K=16, n_pix=128)
+    op = A.SnapshotOperator(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=16)
+    rng = np.random.default_rng(5)
+    y = rng.normal(size=(wl.n_pix, wl.n_pix))
+    gx = op.adjoint(y)
+    gv_ref, gg_ref = A.vis_gradients(snap, op.res.samples, gx)
+    im = _imager(wl, snap, 1, 16)
+    im.set_tuning(9)
+    d = T.to_device(snap)
+    im.grid(d)
+    img, tp = im.image(tplane=True)
+    ref = O.image_snapshot(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=16)
+    e_f = np.abs(tp.cpu().numpy() - ref.tplane).max() / np.abs(ref.tplane).max()
+    gv, gg = im.degrid(torch.from_numpy(y.astype(np.float32)).cuda(), d, want_vis=True, want_gains=True)
+    e_v = np.abs(gv.cpu().numpy() - gv_ref).max() / np.abs(gv_ref).max()
+    e_g = np.abs(gg.cpu().numpy() - gg_ref).max() / np.abs(gg_ref).max()
+    print(f"[adjoint after 16 x 16 bins] forward err {e_f:.3e}  grad_vis err {e_v:.3e}  grad_gains err {e_g:.3e}",
+          flush=True)
+    assert e_f < 1e-4 and e_v < 1e-4 and e_g < 1e-4
+    im.close()
+
+
 def test_dot_product_identity_through_the_abi():
     import torch
     from paper_2512_06254_amd import toi as T

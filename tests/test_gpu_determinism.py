@@ -14,11 +14,12 @@ from gpu_helpers import DENSE, IMAGE_TOL, items_per_bin, max_rel_err
 pytestmark = pytest.mark.gpu
 
 
-def _run(wl, snaps, n_slab, K, tile=16):
+def _run(wl, snaps, n_slab, K, tile=16, tuning=1):
     import torch
     from paper_2512_06254_amd import toi as T
     im = T.Imager(wl.n_pix, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K, tile=tile,
                   max_planes=32)
+    im.set_tuning(tuning)
     imgs, tps = [], []
     for s in snaps:
         im.grid(T.to_device(s))
@@ -36,19 +37,23 @@ def _run(wl, snaps, n_slab, K, tile=16):
     return ([i.cpu().numpy() for i in imgs], tps, tl, boxes.cpu().numpy()[:int(n.item())], batch)
 
 
-@pytest.mark.parametrize("case", ["dense_split_bins", "three_slabs"])
+@pytest.mark.parametrize("case", ["dense_split_bins", "dense_16x16_bins", "three_slabs"])
 def test_repeat_runs_are_bitwise_identical(case):
+    tuning = 1
     if case == "dense_split_bins":
         wl = S.scaled(S.WORKLOADS["tiny"], n_steady=4, n_snap=4, **DENSE)
         n_slab, K = 1, 16
         assert items_per_bin(wl).max() > 2 * 64          # bins sorted by a workgroup, split into units
+    elif case == "dense_16x16_bins":                     # 16 x 16 bins (256-cell grid), split into units
+        wl = S.scaled(S.WORKLOADS["tiny"], n_steady=4, n_snap=4, **{**DENSE, "n_pix": 128, "cell_arcsec": 30.0})
+        n_slab, K, tuning = 1, 16, 9
     else:
         wl = S.scaled(S.WORKLOADS["tiny"], n_ant=12, n_chan=96, n_pix=64, cell_arcsec=60.0, sigma_h_m=60.0,
                       n_steady=4, n_snap=4)
         n_slab, K = 3, 8
     snaps = [S.make_snapshot(wl, t) for t in range(4)]
-    a = _run(wl, snaps, n_slab, K)
-    b = _run(wl, snaps, n_slab, K)
+    a = _run(wl, snaps, n_slab, K, tuning=tuning)
+    b = _run(wl, snaps, n_slab, K, tuning=tuning)
     for x, y in zip(a[0] + a[1] + a[2], b[0] + b[1] + b[2]):
         assert np.array_equal(x, y)
     assert np.array_equal(a[3], b[3])

@@ -40,10 +40,16 @@ def _snapshot_on_device(wl, snap_index):
     return host, T.to_device(host), [(l[i], m[i]) for i in order[:2]]
 
 
-def _gpu_image(wl, dev, n_slab, K):
+# gridder variants checked at the real shapes: 8 x 8 bins (the default) and
+# 16 x 16 bins, both with 64-item work units and 16 planes per pass
+VARIANTS = (1, 9)
+
+
+def _gpu_image(wl, dev, n_slab, K, tuning=1):
     from paper_2512_06254_amd import toi as T
     im = T.Imager(wl.n_pix, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K,
                   max_planes=n_slab * K)
+    im.set_tuning(tuning)
     im.grid(dev)
     img, tp = im.image(tplane=True)
     info = im.plan_info()
@@ -62,14 +68,15 @@ def _tplane_pixel(V, l, m, N, cell_deg):
 def _sampled_parity(wl, n_slab, K, label, n_grid=32, n_blocks=4):
     host, dev, bright = _snapshot_on_device(wl, 0)
     N = wl.n_pix
-    img, tp, info = _gpu_image(wl, dev, n_slab, K)
+    runs = {v: _gpu_image(wl, dev, n_slab, K, v) for v in VARIANTS}
     smp = O.select_samples(host)
     bas = O.snapshot_basis(smp.b)
     r = O.rotate(bas.V, smp.b)
     plan = O.make_plan(r[:, 2], bas.V, N, wl.cell_deg, n_slab=n_slab, K=K)
-    np.testing.assert_allclose(info["V"], bas.V, atol=1e-10)
-    assert abs(info["wsum"] - smp.W) <= 1e-12 * smp.W and info["status"] == 0
-    assert (info["n_slab"], info["K"]) == (plan.n_slab, plan.K)
+    for _, _, info in runs.values():
+        np.testing.assert_allclose(info["V"], bas.V, atol=1e-10)
+        assert abs(info["wsum"] - smp.W) <= 1e-12 * smp.W and info["status"] == 0
+        assert (info["n_slab"], info["K"]) == (plan.n_slab, plan.K)
     rng = np.random.default_rng(1)
     # transformed plane: a sub-grid through the brightest source
     jb1, jb2 = _tplane_pixel(bas.V, *bright[0], N, wl.cell_deg)
@@ -81,12 +88,12 @@ def _sampled_parity(wl, n_slab, K, label, n_grid=32, n_blocks=4):
     j2 = np.unique(np.concatenate([fixed2, j2]))
     ref = O.image_3d_cheb(r, smp.x, smp.W, bas.omega, bas.V, plan, N, wl.cell_deg, j1=j1, j2=j2)
     scale = np.abs(ref).max()
-    e_tp = np.abs(tp[np.ix_(j2, j1)] - ref).max() / scale
+    e_tp = {v: np.abs(tp[np.ix_(j2, j1)] - ref).max() / scale for v, (_, tp, _) in runs.items()}
     # re-projected pixels: 8 x 8 output blocks at the two brightest sources and two random places
     d = math.radians(wl.cell_deg)
     centres = [(int(round(N / 2 - l / d)), int(round(N / 2 + m / d))) for l, m in bright]
     centres += [tuple(rng.integers(N // 8, 7 * N // 8, 2)) for _ in range(n_blocks - len(centres))]
-    e_im, n_px, n_valid, mismatch = 0.0, 0, 0, 0
+    e_im, n_px, n_valid, mismatch = dict.fromkeys(runs, 0.0), 0, dict.fromkeys(runs, 0), dict.fromkeys(runs, 0)
     for c1, c2 in centres:
         o1 = np.arange(c1 - 4, c1 + 4)
         o2 = np.arange(c2 - 4, c2 + 4)
@@ -98,19 +105,23 @@ def _sampled_parity(wl, n_slab, K, label, n_grid=32, n_blocks=4):
         tp_part = np.zeros((N, N))
         tp_part[np.ix_(q2, q1)] = vals
         want, valid = O.bilinear(tp_part, u1, u2, ok)
-        got = img[O2, O1]
-        both = valid & (got != 0)
-        if both.any():
-            e_im = max(e_im, np.abs(got[both] - want[both]).max() / scale)
         n_px += O1.size
-        n_valid += int(both.sum())
-        mismatch += int(np.sum(valid != (got != 0)))
-    print(f"[{label}] plan ({info['n_slab']},{info['K']}) {j1.size}x{j2.size} t-plane pixels err {e_tp:.3e}; "
-          f"{n_px} re-projected pixels ({n_valid} valid) err {e_im:.3e}, validity mismatches {mismatch} "
-          f"(scale {scale:.4f} at the brightest source)", flush=True)
-    assert j1.size * j2.size >= 1024 and n_px >= 256 and n_valid >= 200
-    assert e_tp <= IMAGE_TOL and e_im <= IMAGE_TOL
-    assert mismatch == 0
+        for v, (img, _, _) in runs.items():
+            got = img[O2, O1]
+            both = valid & (got != 0)
+            if both.any():
+                e_im[v] = max(e_im[v], np.abs(got[both] - want[both]).max() / scale)
+            n_valid[v] += int(both.sum())
+            mismatch[v] += int(np.sum(valid != (got != 0)))
+    for v, (_, _, info) in runs.items():
+        print(f"[{label}, variant {v}] plan ({info['n_slab']},{info['K']}) {j1.size}x{j2.size} t-plane pixels "
+              f"err {e_tp[v]:.3e}; {n_px} re-projected pixels ({n_valid[v]} valid) err {e_im[v]:.3e}, validity "
+              f"mismatches {mismatch[v]} (scale {scale:.4f} at the brightest source)", flush=True)
+    assert j1.size * j2.size >= 1024 and n_px >= 256
+    for v in runs:
+        assert n_valid[v] >= 200
+        assert e_tp[v] <= IMAGE_TOL and e_im[v] <= IMAGE_TOL
+        assert mismatch[v] == 0
 
 
 @pytest.mark.parametrize("name", ["meerkat", "full"])

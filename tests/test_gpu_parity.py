@@ -135,6 +135,31 @@ def test_every_gridder_variant_matches_oracle(ns, k):
     im.close()
 
 
+def test_dense_16x16_bins_split_into_work_units():
+    # the dense snapshot on a 256-cell grid: the 16 x 16 bin variants (8 .. 11)
+    # hold the items of four 8 x 8 tiles of up to ~185 items, so the units of
+    # 32, 64 and 128 items split them, and their 256-cell partial tiles are
+    # added in a fixed order; the 8 x 8 default after them
+    from paper_2512_06254_amd import toi as T
+    wl = S.scaled(S.WORKLOADS["tiny"], **{**DENSE, "n_pix": 128, "cell_arcsec": 30.0})
+    assert items_per_bin(wl).max() > 2 * 64
+    snap = S.make_snapshot(wl, 0)
+    ref = O.image_snapshot(snap, wl.n_pix, wl.cell_deg, mode=3, n_slab=1, K=16)
+    im = T.Imager(wl.n_pix, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=1, cheb_k=16)
+    d = T.to_device(snap)
+    for v in (8, 9, 10, 11, 1):
+        im.set_tuning(v)
+        im.grid(d)
+        img, tp = im.image(tplane=True)
+        e = max_rel_err(tp.cpu().numpy(), ref.tplane)
+        units = im.bin_info()["units"]
+        print(f"[dense 16 x 16 bins, variant {v}] t-plane err {e:.3e}, {units} work units", flush=True)
+        assert e <= IMAGE_TOL
+        if v != 11:
+            assert units > 0
+    im.close()
+
+
 def test_dense_bins_split_into_work_units():
     # bins of up to ~190 items: the gridder splits them into units of 32, 64,
     # 128 (or 256: whole) items, per tuning, whose partial tiles are added in
@@ -154,7 +179,10 @@ def test_dense_bins_split_into_work_units():
         units = im.bin_info()["units"]
         print(f"[dense bins, variant {v}] t-plane err {e:.3e}, {units} work units", flush=True)
         assert e <= IMAGE_TOL
-        assert (units > 0) == ((32 << (v & 3)) <= 185)
+        if v & 8:   # 16 x 16 bins: each holds the items of its four 8 x 8 tiles, so it splits at least as often
+            assert units > 0 or (32 << (v & 3)) > 185
+        else:
+            assert (units > 0) == ((32 << (v & 3)) <= 185)
     im.close()
 
 
