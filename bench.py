@@ -363,6 +363,7 @@ def many_slab_leg(n_snap, reps, device):
     N, TT = wl.n_pix, wl.n_pix // 32
     im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K, tile=32,
                   max_planes=n_slab * K)
+    variant, _ = im.tune(pool[0])
     imgs = torch.zeros((n_snap, N, N), dtype=torch.float32, device=device)
 
     def run():
@@ -382,7 +383,8 @@ def many_slab_leg(n_snap, reps, device):
     im.close()
     alg = method_bytes(wl, n_slab * K, False)
     return {"workload": "aa2", "baselines": wl.n_row, "channels": wl.n_chan, "correlations": wl.n_corr,
-            "image": f"{N}x{N}", "planes": f"{info['n_slab']} slabs x K={info['K']}", "ms_per_snapshot": round(ms, 4),
+            "image": f"{N}x{N}", "planes": f"{info['n_slab']} slabs x K={info['K']}", "tuned_variant": variant,
+            "ms_per_snapshot": round(ms, 4),
             "hbm_roofline_frac": hbm_frac(alg, ms), "algorithmic_bytes": alg,
             "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]}}
 
@@ -400,6 +402,7 @@ def full_leg(n_snap, reps, device):
     pool = make_pool(wl, 2, device)
     N = wl.n_pix
     im = T.Imager(N, wl.cell_deg, wl.n_row, wl.n_chan, wl.n_corr, n_slab=n_slab, cheb_k=K, tile=32)
+    variant, _ = im.tune(pool[0])
     ring = [torch.zeros((N, N), dtype=torch.float32, device=device) for _ in range(3)]
     tl = torch.zeros((N // 32, N // 32), dtype=torch.float32, device=device)
     state = {"i": 0}
@@ -424,6 +427,7 @@ def full_leg(n_snap, reps, device):
     alg = method_bytes(wl, n_slab * K, False)
     return {"workload": wl.name, "baselines": wl.n_row, "channels": wl.n_chan, "correlations": wl.n_corr,
             "image": f"{N}x{N}", "grid": f"{2 * N}x{2 * N}", "planes": f"{info['n_slab']} slab x K={info['K']}",
+            "tuned_variant": variant,
             "status": info["status"], "ms_per_snapshot": round(ms, 4), "hbm_roofline_frac": hbm_frac(alg, ms),
             "algorithmic_bytes": alg, "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]}}
 
