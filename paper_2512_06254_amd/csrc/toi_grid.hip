@@ -527,21 +527,34 @@ __global__ __launch_bounds__(256) void k_bin_sort_wave(const DevPlan* __restrict
     }
 }
 
-template <typename Buf>
+// The bitonic network of k_bin_sort_block over a[0 .. n): substage (k, j) =
+// (2^lk, 2^lj) compares the pair (i, l) of every t < P2 / 2 (shifts and
+// masks: all sizes are powers of two).  In LDS (kWaveLocal), a substage whose
+// pairs stay inside aligned blocks of 128 elements (j <= 64, or the mirrored
+// first substage of k <= 128) touches only the elements of its wavefront's
+// own pairs (thread t of wavefront w: elements 128 w + 2048 r + 0..127), so
+// between two such substages the wavefront orders its own LDS accesses
+// instead of waiting for the workgroup.
+template <bool kWaveLocal, typename Buf>
 __device__ inline void sort_network(Buf a, int n) {
-    int P2 = 1;
-    while (P2 < n) P2 <<= 1;
+    int P2 = 1, lp = 0;
+    while (P2 < n) {
+        P2 <<= 1;
+        ++lp;
+    }
     const int nt = blockDim.x;
-    for (int k = 2; k <= P2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
+    auto local = [](int lk, int lj) { return lj == lk - 1 ? lk <= 7 : lj <= 6; };
+    for (int lk = 1; lk <= lp; ++lk) {
+        for (int lj = lk - 1; lj >= 0; --lj) {
+            const int j = 1 << lj;
             for (int t = threadIdx.x; t < P2 / 2; t += nt) {
-                const int blk = t / j, o = t % j;
+                const int blk = t >> lj, o = t & (j - 1);
                 int i, l;
-                if (j == (k >> 1)) {   // mirrored pair of the k-block
-                    i = (t / (k >> 1)) * k + t % (k >> 1);
-                    l = (t / (k >> 1)) * k + k - 1 - t % (k >> 1);
+                if (lj == lk - 1) {   // mirrored pair of the k-block
+                    i = (blk << lk) + o;
+                    l = (blk << lk) + (1 << lk) - 1 - o;
                 } else {
-                    i = blk * 2 * j + o;
+                    i = (blk << (lj + 1)) + o;
                     l = i + j;
                 }
                 if (l < n) {
@@ -552,7 +565,11 @@ __device__ inline void sort_network(Buf a, int n) {
                     }
                 }
             }
-            __syncthreads();
+            const int nk = lj > 0 ? lk : lk + 1, nj = lj > 0 ? lj - 1 : lk;   // the next substage
+            if (kWaveLocal && nk <= lp && local(lk, lj) && local(nk, nj))
+                lds_order();
+            else
+                __syncthreads();
         }
     }
 }
@@ -570,10 +587,10 @@ __global__ __launch_bounds__(1024) void k_bin_sort_block(const DevPlan* __restri
         if (n <= kSortLds) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = list[b0 + i];
             __syncthreads();
-            sort_network(s, n);
+            sort_network<true>(s, n);
             for (int i = threadIdx.x; i < n; i += blockDim.x) list[b0 + i] = s[i];
         } else {
-            sort_network(list + b0, n);
+            sort_network<false>(list + b0, n);
         }
         __syncthreads();   // the write-back precedes the next bin's loads into LDS
     }
