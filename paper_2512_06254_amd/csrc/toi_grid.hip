@@ -36,13 +36,37 @@ namespace toi {
 // (FP64 coordinates split into a cell and FP32 offsets once per sample), and
 // the item's largest value and extreme kept frequencies go to its ItemBox
 // (k_item_bins derives the box and counts the bins from them).
+// The counters the bin pass adds to: the bin counts and row words of the
+// plan's plane groups (the scan treats the bins of the other groups as empty,
+// whatever they hold) and the scan's bucket words.  Done by the record pass's
+// threads (its grid covers them many times over), or by k_scan_clear when the
+// bins are built again from existing records.
+struct BinClear {
+    int32_t* count;
+    int n_bins, tiles;
+    int32_t* aux;
+    uint32_t* row_bits;
+    int n_row_words, words;
+};
+__device__ inline void clear_bins(const DevPlan* __restrict__ P, const BinClear& bc) {
+    const int stride = gridDim.x * blockDim.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ng = P->ng;
+    const int nb = min(bc.n_bins, ng * bc.tiles), nw = min(bc.n_row_words, ng * bc.words);
+    for (int i = t; i < nb; i += stride) bc.count[i] = 0;
+    if (t < kAuxTotals) bc.aux[t] = 0;
+    for (int i = t; i < nw; i += stride) bc.row_bits[i] = 0;
+}
+
 __global__ __launch_bounds__(256) void k_items(const double* __restrict__ uvw, const float2* __restrict__ vis,
                                                const float* __restrict__ weight, const uint8_t* __restrict__ flag,
                                                const double* __restrict__ freq, const int32_t* __restrict__ ant1,
                                                const int32_t* __restrict__ ant2, const float2* __restrict__ gains,
                                                int n_ant, int n_chan, int n_corr, uint32_t mask, int vec4,
                                                int mode, const DevPlan* __restrict__ P, int M, double cell_rad,
-                                               int n_items, ItemBox* __restrict__ items, SampleRec* __restrict__ recs) {
+                                               int n_items, ItemBox* __restrict__ items, SampleRec* __restrict__ recs,
+                                               BinClear bc) {
+    clear_bins(P, bc);   // (a launch of its own cost 4 us)
     const int lane = threadIdx.x & 63;
     const int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (item >= n_items) return;
@@ -173,18 +197,8 @@ __global__ __launch_bounds__(256) void k_item_bins(const double* __restrict__ uv
 // aux: layout kAux* (toi_internal.h).
 constexpr int kScanPer = kScanBlock / 1024;
 
-// Only the bins and row words of the plan's plane groups are cleared (the
-// scan treats the bins of the other groups as empty, whatever they hold).
-__global__ __launch_bounds__(256) void k_scan_clear(const DevPlan* __restrict__ P, int32_t* __restrict__ count,
-                                                    int n_bins, int tiles, int32_t* __restrict__ aux,
-                                                    uint32_t* __restrict__ row_bits, int n_row_words, int words) {
-    const int stride = gridDim.x * blockDim.x;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ng = P->ng;
-    const int nb = min(n_bins, ng * tiles), nw = min(n_row_words, ng * words);
-    for (int i = t; i < nb; i += stride) count[i] = 0;
-    if (t < kAuxTotals) aux[t] = 0;
-    for (int i = t; i < nw; i += stride) row_bits[i] = 0;
+__global__ __launch_bounds__(256) void k_scan_clear(const DevPlan* __restrict__ P, BinClear bc) {
+    clear_bins(P, bc);
 }
 
 __device__ inline int block_exclusive_scan(int v, int& total) {
@@ -424,8 +438,8 @@ __global__ __launch_bounds__(256) void k_bin_fill(const ItemBox* __restrict__ it
 }
 
 // ---------------------------------------------------------------- 2c. order
-// The fill leaves each bin's items in the order of the atomic cursor; these
-// kernels sort every bin's list into increasing item order (the items of a
+// The fill leaves each bin's items in the order of the atomic cursor; k_bin_sort
+// sorts every bin's list into increasing item order (the items of a
 // bin are distinct).  Bins of buckets below kBlockSortShift (fewer than 256
 // items; the launch order's entries from the heaviest buckets' total on) are
 // sorted by a bitonic network across the lanes: one wavefront per bin of 16 or
@@ -488,11 +502,9 @@ __device__ inline void sort_wave_slots(int (&v)[S]) {
 // 16 to 63 items one per wavefront; bins of fewer than 16 items four per
 // wavefront (16 lanes each): the pass is bound by the latency of its loads,
 // and most bins hold a few items.
-__global__ __launch_bounds__(256) void k_bin_sort_wave(const DevPlan* __restrict__ P, const int32_t* __restrict__ order,
-                                                       const int32_t* __restrict__ n_active,
-                                                       const int32_t* __restrict__ aux,
-                                                       const int32_t* __restrict__ off, int32_t* __restrict__ list) {
-    if (P->status & kStatusFatal) return;
+__device__ inline void sort_small_bins(const int32_t* __restrict__ order, const int32_t* __restrict__ n_active,
+                                       const int32_t* __restrict__ aux, const int32_t* __restrict__ off,
+                                       int32_t* __restrict__ list) {
     const int lane = threadIdx.x & 63;
     const int waves = gridDim.x * (blockDim.x >> 6);
     const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -527,7 +539,7 @@ __global__ __launch_bounds__(256) void k_bin_sort_wave(const DevPlan* __restrict
     }
 }
 
-// The bitonic network of k_bin_sort_block over a[0 .. n): substage (k, j) =
+// The bitonic network of sort_heavy_bins over a[0 .. n): substage (k, j) =
 // (2^lk, 2^lj) compares the pair (i, l) of every t < P2 / 2 (shifts and
 // masks: all sizes are powers of two).  In LDS (kWaveLocal), a substage whose
 // pairs stay inside aligned blocks of 128 elements (j <= 64, or the mirrored
@@ -574,12 +586,8 @@ __device__ inline void sort_network(Buf a, int n) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_bin_sort_block(const DevPlan* __restrict__ P,
-                                                         const int32_t* __restrict__ order,
-                                                         const int32_t* __restrict__ aux,
-                                                         const int32_t* __restrict__ off, int32_t* __restrict__ list) {
-    __shared__ int32_t s[kSortLds];
-    if (P->status & kStatusFatal) return;
+__device__ inline void sort_heavy_bins(const int32_t* __restrict__ order, const int32_t* __restrict__ aux,
+                                       const int32_t* __restrict__ off, int32_t* __restrict__ list, int32_t* s) {
     const int n_heavy = bucket_bins(aux, kBlockSortShift, 32);   // 256 items and more
     for (int ob = blockIdx.x; ob < n_heavy; ob += gridDim.x) {
         const int bin = order[ob];
@@ -594,6 +602,19 @@ __global__ __launch_bounds__(1024) void k_bin_sort_block(const DevPlan* __restri
         }
         __syncthreads();   // the write-back precedes the next bin's loads into LDS
     }
+}
+
+// Both sorts in one launch (one launch each cost about 4 us more): every
+// workgroup first takes its share of the heavy bins, then each of its
+// wavefronts its share of the others.
+__global__ __launch_bounds__(1024) void k_bin_sort(const DevPlan* __restrict__ P, const int32_t* __restrict__ order,
+                                                   const int32_t* __restrict__ n_active,
+                                                   const int32_t* __restrict__ aux,
+                                                   const int32_t* __restrict__ off, int32_t* __restrict__ list) {
+    __shared__ int32_t s[kSortLds];
+    if (P->status & kStatusFatal) return;
+    sort_heavy_bins(order, aux, off, list, s);
+    sort_small_bins(order, n_active, aux, off, list);
 }
 
 // ---------------------------------------------------------------- 3. tiles, matrix cores
@@ -1139,7 +1160,7 @@ hipError_t launch_grid(toi_ctx* c, const toi_snapshot& s) {
     return e != hipSuccess ? e : launch_gridder(c, s);
 }
 
-constexpr int kBinSortBlocks = 512, kBinSortWaveGroups = 2048;
+constexpr int kBinSortBlocks = 512;   // 8192 wavefronts
 
 // The bin pipeline with bins of 2^bsh cells per side; the record pass too when
 // records is set (otherwise the records and items of the last launch_bin of
@@ -1155,14 +1176,15 @@ static hipError_t bin_pipeline(toi_ctx* c, const toi_snapshot& s, int bsh, bool 
     const int n_scan = (n_bins + kScanBlock - 1) / kScanBlock;
     const int max_units = kSplitSlots >> (2 * (bsh - kTileShift));
     c->bins_shift = bsh;
-    hipLaunchKernelGGL(k_scan_clear, dim3(256), dim3(256), 0, c->stream, c->plan, c->bin_count, n_bins, NB * NB,
-                       c->bin_aux, c->row_bits, c->NG_max * words, words);
+    const BinClear bc{c->bin_count, n_bins, NB * NB, c->bin_aux, c->row_bits, c->NG_max * words, words};
     if (n_items > 0 && records)
         hipLaunchKernelGGL(k_items, dim3((n_items + 3) / 4), dim3(256), 0, c->stream, s.uvw,
                            (const float2*)s.vis, s.weight, s.flag, s.freq, s.ant1, s.ant2,
                            (const float2*)s.gains, p.n_ant, p.n_chan, p.n_corr, p.corr_mask,
                            (int)vec4_ok(s.vis, s.flag, s.weight, p.n_corr), p.mode, c->plan, M,
-                           cell, n_items, c->items, c->recs);
+                           cell, n_items, c->items, c->recs, bc);
+    else
+        hipLaunchKernelGGL(k_scan_clear, dim3(256), dim3(256), 0, c->stream, c->plan, bc);
     if (n_items > 0)
         hipLaunchKernelGGL(k_item_bins, dim3((n_items + 256 / kItemLanes - 1) / (256 / kItemLanes)), dim3(256), 0,
                            c->stream, s.uvw, p.n_chan, p.mode, c->plan, M, NB, bsh, cell, n_items, c->items,
@@ -1180,9 +1202,7 @@ static hipError_t bin_pipeline(toi_ctx* c, const toi_snapshot& s, int bsh, bool 
         hipLaunchKernelGGL(k_bin_fill, dim3((n_items + 256 / kFillLanes - 1) / (256 / kFillLanes)), dim3(256), 0,
                            c->stream, c->items, n_items, NB, bsh,
                            c->bin_cap, c->bin_cursor, c->bin_list);
-        hipLaunchKernelGGL(k_bin_sort_block, dim3(kBinSortBlocks), dim3(1024), 0, c->stream, c->plan,
-                           c->bin_order, c->bin_aux, c->bin_off, c->bin_list);
-        hipLaunchKernelGGL(k_bin_sort_wave, dim3(kBinSortWaveGroups), dim3(256), 0, c->stream, c->plan,
+        hipLaunchKernelGGL(k_bin_sort, dim3(kBinSortBlocks), dim3(1024), 0, c->stream, c->plan,
                            c->bin_order, c->scratch_i, c->bin_aux, c->bin_off, c->bin_list);
     }
     return hipGetLastError();
