@@ -646,8 +646,9 @@ def main():
                     "kernel": kname, "algorithmic_flops": grid_flops(wl, P),
                     "avg_launch_ms": round(dom_ms, 4), "launches_timed": n,
                     "frac_of_f16_matrix_peak": round(ach / F16_MFMA_PEAK_TFLOPS, 4) if split16 else None,
-                    "note": ("products on the fp16 matrix cores (operands split as hi + lo in fp16, 3 terms, "
-                             "FP32 accumulation) beside the vector ALU; bound by vector-ALU issue"
+                    "note": (("products on the fp16 matrix cores (operands split as hi + lo in fp16, 3 terms, "
+                              "FP32 accumulation) beside the vector ALU; bound by vector-ALU issue"
+                              + (" and latency (16 x 16 bins: 2 waves per SIMD)" if variant & 8 else ""))
                              if split16 else None)}
     else:
         ach = sb[dom] / (dom_ms * 1e-3) / 1e9
