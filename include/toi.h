@@ -65,8 +65,9 @@ typedef struct {
     int32_t  n_chan;
     int32_t  n_corr;       /* 1, 2 or 4                                                      */
     int32_t  n_ant;        /* antennas (gains length), may be 0 when no gains are used       */
-    int32_t  bin_cap;      /* capacity of the gridding bin lists in (work item, 8 x 8 tile)  */
-                           /* entries; 0 = 128 per work item (a work item is 64 channels of*/
+    int32_t  bin_cap;      /* capacity of the gridding bin lists in (work item, bin) entries */
+                           /* (bins of 8 x 8 or 16 x 16 cells, by the gridder variant);     */
+                           /* 0 = 128 per work item (a work item is 64 channels of         */
                            /* one row) + 65536.  A snapshot needing more sets               */
                            /* TOI_STATUS_OVERFLOW and images to zero.                        */
 } toi_params;
