@@ -891,7 +891,7 @@ __global__ __launch_bounds__(64, NCOL == 32 ? 3 : 5) void k_grid_tiles_mfma(
 // touches are skipped (a uniform branch per block).  (Two wavefronts per bin,
 // each with half the accumulators and half the staging, allow three
 // wavefronts per SIMD instead of two, but the barriers of the shared staging
-// made the pass slower: 0.78 against 0.67 ms.)
+// made the pass slower: 0.78 against 0.64 ms.)
 // Staging in LDS, rows of 68 floats, one column per sample slot: T rows
 // 0..15, x rows (bin columns 0..15) at rows 16..31, 7 spare rows, y rows (bin
 // rows 0..15) at rows 39..54, Re and Im of g x at rows 55 and 56, 5 spare
@@ -1105,10 +1105,10 @@ __global__ __launch_bounds__(64, 2) void k_grid_bins16(
 
 // Tiles of split bins: the partial tiles of a bin's units (consecutive unit
 // slots from part 0) added in part order, written to the grid.  One workgroup
-// per 256 elements (plane, cell) of a split bin at a time; each thread issues
-// the loads of eight parts before it adds them in order (with one load per
-// add, each add waited for its load: 25 us per MeerKAT-shaped snapshot with
-// 16 x 16 bins, whose heaviest bins have some 20 parts).
+// per 256 elements (plane, cell) of a split bin at a time, one element per
+// thread, whose loads of up to eight parts are issued before it adds them in
+// order.  (One workgroup per split bin, each thread adding 16 elements one
+// load at a time, took 25 us per MeerKAT-shaped snapshot with 16 x 16 bins.)
 constexpr int kSplitSumWorkgroups = 2048;
 __global__ __launch_bounds__(256) void k_split_sum(const DevPlan* __restrict__ P, int M, int NT, int bsh,
                                                    const int4* __restrict__ units, const int32_t* __restrict__ cnt,
