@@ -169,9 +169,12 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
                     }
                 }
             }
-            // orders K-1 .. 0 with their planes
-            for (int k = K - 1; k >= 0; --k) {
-                float2 v[E];
+            // orders K-1 .. 0 with their planes.  Each plane's column is loaded
+            // as soon as the previous plane's kept bins are out of its
+            // registers, so that the loads are in flight while that plane is
+            // folded into the combination (the same registers; 0.341 ->
+            // 0.325 ms against loading each column right before its transform)
+            auto plane_occ = [&](int k) {
                 const int gk = group_of_plane(p * K + k, plan);
                 if (gk != occ_g) {   // planes of one group share the occupancy of their tile rows
                     // the group's words come from L1/L2: a copy of every group's
@@ -182,8 +185,17 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
                         [&](int y) { return (rbg[y >> (kTileShift + 5)] >> ((y >> kTileShift) & 31)) & 1u; });
                     occ_g = gk;
                 }
-                fft_load_bits<M, E, kHbufGroup>(v, hbuf + hbuf_index<M>(p * K + k, j1, 0), occ);
+                return occ;
+            };
+            float2 v[E];
+            fft_load_bits<M, E, kHbufGroup>(v, hbuf + hbuf_index<M>(p * K + K - 1, j1, 0), plane_occ(K - 1));
+            for (int k = K - 1; k >= 0; --k) {
                 fft_stages<M, E, 1>(v, lds, tw_s);
+                float2 Fk[KEEP];
+#pragma unroll
+                for (int q = 0; q < KEEP; ++q) Fk[q] = v[fft_kept_slot<E>(q)];
+                if (k > 0)
+                    fft_load_bits<M, E, kHbufGroup>(v, hbuf + hbuf_index<M>(p * K + k - 1, j1, 0), plane_occ(k - 1));
 #pragma unroll
                 for (int q = 0; q < KEEP; ++q) {
                     float jk;
@@ -198,7 +210,7 @@ __global__ __launch_bounds__(M / E, (M / E) <= 512 ? 2 : 1) void k_fft_cols(cons
                         if ((k & 1) == 0) nrm[q] += (k == 0 ? 1.f : 2.f) * jk;
                     }
                     const float f = (k == 0 ? 1.f : 2.f) * jk;
-                    const float2 F = v[fft_kept_slot<E>(q)];
+                    const float2 F = Fk[q];
                     switch (k & 3) {   // c_k = 2 i^k J_k (c_0 = J_0)
                         case 0: ar[q] += f * F.x; ai[q] += f * F.y; break;
                         case 1: ar[q] -= f * F.y; ai[q] += f * F.x; break;
